@@ -1,0 +1,226 @@
+"""ctypes wrapper of the FP64 CPU oracle (liboracle.so).
+
+TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+benchmark's CPU-baseline leg.  The product path never imports this module.
+The wrapped C code follows the plain definitions of the paper's grid
+integrals (Eq. 1-5) and shares no code with the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+SRC = os.path.join(HERE, "gint_oracle.c")
+
+ORACLE_OK, ORACLE_EINVAL, ORACLE_EPATTERN, ORACLE_ENOMEM = 0, -1, -2, -3
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code):
+        super().__init__({-1: "EINVAL", -2: "EPATTERN", -3: "ENOMEM"}.get(code, str(code)))
+        self.code = code
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (plain -O3, OpenMP)."""
+    if force or not os.path.exists(LIB):
+        cmd = ["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-Wall",
+               "-o", LIB + ".tmp", SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+class _Sys(C.Structure):
+    _fields_ = [
+        ("natom", C.c_int), ("cell", C.c_void_p), ("pos", C.c_void_p), ("species", C.c_void_p),
+        ("nspecies", C.c_int), ("sp_rcut", C.c_void_p), ("sp_dr", C.c_void_p), ("sp_rs", C.c_void_p),
+        ("sp_nknots", C.c_void_p), ("sp_cutoff", C.c_void_p), ("sp_chan_off", C.c_void_p),
+        ("chan_l", C.c_void_p), ("chan_alpha", C.c_void_p), ("chan_tab_off", C.c_void_p),
+        ("tab_f", C.c_void_p), ("tab_fp", C.c_void_p), ("grid", C.c_void_p),
+        ("nblk", C.c_int), ("blk_i", C.c_void_p), ("blk_j", C.c_void_p), ("blk_r", C.c_void_p),
+        ("blk_off", C.c_void_p), ("radial_mode", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = C.CDLL(LIB)
+        P = C.c_void_p
+        lib.oracle_vlocal.argtypes = [P, P, P, C.c_long, C.c_long]
+        lib.oracle_rho.argtypes = [P, P, P, C.c_long, C.c_long]
+        lib.oracle_force_stress.argtypes = [P, P, P, P, P, P, C.c_long, C.c_long]
+        lib.oracle_rho_points.argtypes = [P, P, C.c_long, P, P]
+        lib.oracle_vlocal_blocks.argtypes = [P, P, C.c_int, P, P]
+        lib.oracle_force_atoms.argtypes = [P, P, P, C.c_int, P, P, P]
+        lib.oracle_orbitals.argtypes = [P, C.c_int, C.c_long, P, P, P]
+        lib.oracle_radial.argtypes = [P, C.c_int, C.c_int, C.c_long, P, P, P]
+        lib.oracle_neighbours.argtypes = [P, C.c_long, C.c_int, P, P, P]
+        lib.oracle_work.argtypes = [P, C.c_long, C.c_long, P]
+        _lib = lib
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+class Oracle:
+    """Oracle bound to one System (see paper_2409_09399_amd.inputs).
+
+    radial: "table" (cubic Hermite of the tabulated f, f') or "analytic"."""
+
+    def __init__(self, system, radial: str = "table"):
+        self.lib = _load()
+        s = system
+        self.system = s
+        keep = []
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(np.asarray(x), dtype=dt)
+            keep.append(a)
+            return a
+
+        sps = s.species_list
+        nch = [sp.nchan for sp in sps]
+        chan_off = np.concatenate([[0], np.cumsum(nch)]).astype(np.int32)
+        chan_l = np.concatenate([sp.ls for sp in sps]).astype(np.int32)
+        chan_alpha = np.concatenate([sp.alphas for sp in sps]).astype(np.float64)
+        tabs_f, tabs_fp, tab_off, o = [], [], [], 0
+        for sp in sps:
+            for c in range(sp.nchan):
+                tabs_f.append(sp.f[c]); tabs_fp.append(sp.fp[c]); tab_off.append(o)
+                o += sp.nknots
+        st = _Sys()
+        st.natom = s.natom
+        st.cell = _p(arr(s.cell, np.float64))
+        st.pos = _p(arr(s.pos, np.float64))
+        st.species = _p(arr(s.species, np.int32))
+        st.nspecies = len(sps)
+        st.sp_rcut = _p(arr([sp.rcut for sp in sps], np.float64))
+        st.sp_dr = _p(arr([sp.dr for sp in sps], np.float64))
+        st.sp_rs = _p(arr([sp.rs for sp in sps], np.float64))
+        st.sp_nknots = _p(arr([sp.nknots for sp in sps], np.int32))
+        st.sp_cutoff = _p(arr([1 if sp.cutoff else 0 for sp in sps], np.int32))
+        st.sp_chan_off = _p(arr(chan_off, np.int32))
+        st.chan_l = _p(arr(chan_l, np.int32))
+        st.chan_alpha = _p(arr(chan_alpha, np.float64))
+        st.chan_tab_off = _p(arr(tab_off, np.int64))
+        st.tab_f = _p(arr(np.concatenate(tabs_f), np.float64))
+        st.tab_fp = _p(arr(np.concatenate(tabs_fp), np.float64))
+        st.grid = _p(arr(s.grid, np.int32))
+        st.nblk = int(s.blk_i.shape[0])
+        st.blk_i = _p(arr(s.blk_i, np.int32))
+        st.blk_j = _p(arr(s.blk_j, np.int32))
+        st.blk_r = _p(arr(s.blk_r, np.int32))
+        st.blk_off = _p(arr(s.blk_off, np.int64))
+        st.radial_mode = {"table": 0, "analytic": 1}[radial]
+        self._keep = keep
+        self._st = st
+        self._ps = C.cast(C.pointer(st), C.c_void_p)
+
+    @staticmethod
+    def _check(rc):
+        if rc < 0:
+            raise OracleError(rc)
+        return rc
+
+    def vlocal(self, v=None, g_range=(0, -1)) -> np.ndarray:
+        s = self.system
+        v = np.ascontiguousarray(s.v if v is None else v, dtype=np.float64)
+        h = np.zeros(s.nnz)
+        self._check(self.lib.oracle_vlocal(self._ps, _p(v), _p(h), g_range[0], g_range[1]))
+        return h
+
+    def rho(self, d=None, g_range=(0, -1)) -> np.ndarray:
+        s = self.system
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        rho = np.zeros(s.ngrid)
+        self._check(self.lib.oracle_rho(self._ps, _p(d), _p(rho), g_range[0], g_range[1]))
+        return rho
+
+    def force_stress(self, v=None, d=None, g_range=(0, -1)):
+        """Returns (F [natom,3], Z [3,3] = dE/d(strain), E, sigma = -Z/Omega)."""
+        s = self.system
+        v = np.ascontiguousarray(s.v if v is None else v, dtype=np.float64)
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        F = np.zeros((s.natom, 3))
+        Z = np.zeros((3, 3))
+        E = np.zeros(1)
+        self._check(self.lib.oracle_force_stress(self._ps, _p(v), _p(d), _p(F), _p(Z), _p(E),
+                                                 g_range[0], g_range[1]))
+        return F, Z, float(E[0]), -Z / s.volume
+
+    def rho_points(self, gidx, d=None) -> np.ndarray:
+        s = self.system
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        g = np.ascontiguousarray(gidx, dtype=np.int64)
+        out = np.zeros(g.shape[0])
+        self._check(self.lib.oracle_rho_points(self._ps, _p(d), g.shape[0], _p(g), _p(out)))
+        return out
+
+    def vlocal_blocks(self, blks, v=None):
+        """List of H blocks (n_I x n_J arrays) for the given block indices."""
+        s = self.system
+        v = np.ascontiguousarray(s.v if v is None else v, dtype=np.float64)
+        b = np.ascontiguousarray(blks, dtype=np.int32)
+        norb = s.norb_atom()
+        sizes = norb[s.blk_i[b]] * norb[s.blk_j[b]]
+        out = np.zeros(int(sizes.sum()))
+        self._check(self.lib.oracle_vlocal_blocks(self._ps, _p(v), b.shape[0], _p(b), _p(out)))
+        res, o = [], 0
+        for k, bb in enumerate(b):
+            ni, nj = int(norb[s.blk_i[bb]]), int(norb[s.blk_j[bb]])
+            res.append(out[o:o + ni * nj].reshape(ni, nj))
+            o += ni * nj
+        return res
+
+    def force_atoms(self, atoms, v=None, d=None):
+        """Per-atom force and strain-derivative contributions (F [n,3], Z [n,3,3])."""
+        s = self.system
+        v = np.ascontiguousarray(s.v if v is None else v, dtype=np.float64)
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        a = np.ascontiguousarray(atoms, dtype=np.int32)
+        F = np.zeros((a.shape[0], 3))
+        Z = np.zeros((a.shape[0], 3, 3))
+        self._check(self.lib.oracle_force_atoms(self._ps, _p(v), _p(d), a.shape[0], _p(a), _p(F), _p(Z)))
+        return F, Z
+
+    def orbitals(self, species: int, x):
+        x = np.ascontiguousarray(np.atleast_2d(x), dtype=np.float64)
+        no = self.system.species_list[species].norb
+        phi = np.zeros((x.shape[0], no))
+        grad = np.zeros((x.shape[0], no, 3))
+        self._check(self.lib.oracle_orbitals(self._ps, species, x.shape[0], _p(x), _p(phi), _p(grad)))
+        return phi, grad
+
+    def radial(self, species: int, chan: int, r):
+        r = np.ascontiguousarray(np.atleast_1d(r), dtype=np.float64)
+        p = np.zeros_like(r)
+        dp = np.zeros_like(r)
+        self._check(self.lib.oracle_radial(self._ps, species, chan, r.shape[0], _p(r), _p(p), _p(dp)))
+        return p, dp
+
+    def neighbours(self, g: int, cap: int = 4096):
+        atom = np.zeros(cap, np.int32)
+        T = np.zeros((cap, 3), np.int32)
+        x = np.zeros((cap, 3))
+        n = self._check(self.lib.oracle_neighbours(self._ps, int(g), cap, _p(atom), _p(T), _p(x)))
+        n = min(n, cap)
+        return atom[:n], T[:n], x[:n]
+
+    def work(self, g_range=(0, -1)) -> float:
+        w = np.zeros(1)
+        self._check(self.lib.oracle_work(self._ps, g_range[0], g_range[1], _p(w)))
+        return float(w[0])
