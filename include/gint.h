@@ -1,0 +1,161 @@
+/* gint.h — C ABI of the MI355X grid-integration ("Gint") library.
+ *
+ * The library evaluates the three real-space grid integrals of LCAO density
+ * functional theory (paper: "Real-Space Grid Integrals", Eq. 1-5) on an AMD
+ * Instinct MI355X (gfx950):
+ *
+ *   H_IJR[mu,nu] = sum_g w V_g sum_{T} phi_Imu(r_g - tau_I - T.h) phi_Jnu(r_g - tau_J - (T+R).h)   (Eq. 2)
+ *   rho_g        = sum_{(I,T,mu),(J,T',nu)} D_(I,J,T'-T)[mu,nu] phi_Imu phi_Jnu                      (Eq. 3)
+ *   F_K = -dE/dtau_K and Z = dE/d(strain) of E = sum_g w V_g rho_g (Pulay terms, Eq. 4-5)
+ *
+ * where g runs over the uniform grid r_g = sum_i (n_i/N_i) a_i of the periodic
+ * cell, w = Omega/N_g is the volume per point (Eq. 2's dV), T runs over lattice
+ * translations, and the orbitals are numerical atomic orbitals
+ * phi_{c,m}(x) = p_c(|x|) S_{l_c m}(x) with p_c the cubic Hermite interpolant
+ * of the tabulated radial function f_c and S_lm = r^l Y_lm the real solid
+ * harmonics (orthonormal Y_lm, m = -l..l, sin-type for m < 0, l <= 2),
+ * strictly zero for |x| >= rcut (paper: "Numerical Atomic Orbitals").
+ *
+ * Conventions shared by every entry point
+ *  - Units: Bohr, Hartree.  All floating-point inputs and outputs are FP64.
+ *  - Orbitals of an atom are ordered by channel (in the order given), then
+ *    m = -l..l.  At most 16 orbitals per atom, l <= 2.
+ *  - Block (I, J, R) couples atom I in cell 0 with atom J in cell R
+ *    (R = T' - T, an integer triple); it is stored row-major n_I x n_J at
+ *    element offset blk_off.  The pattern must be transpose-closed:
+ *    (I,J,R) present <=> (J,I,-R) present.
+ *  - D must satisfy D_JI(-R) = D_IJR^T up to round-off; the kernels use the
+ *    symmetrised D_sym = (D_IJR + D_JI(-R)^T)/2 throughout.
+ *  - Grid arrays (v_loc, rho) are FP64 [N1][N2][N3] in C order,
+ *    g = (n1 N2 + n2) N3 + n3.
+ *  - Device arrays are allocated and owned by the caller (e.g. through
+ *    PyTorch) on the plan's device; the library only reads inputs and
+ *    overwrites outputs.  Inputs are never modified.
+ *  - Every call enqueues its work on `stream` (a hipStream_t, NULL = the
+ *    default stream) and returns without synchronising.  Scalar outputs are
+ *    device pointers so that no call forces a host round trip.
+ *  - A plan is not thread-safe; separate plans are independent.
+ *  - Errors: every function returns GINT_OK (0) or a negative code; on error
+ *    the outputs are left untouched and no work is enqueued.  No exception,
+ *    abort or exit crosses this interface.
+ */
+#ifndef GINT_H
+#define GINT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GINT_OK = 0,
+    GINT_EINVAL = -1,        /* bad shape, index, non-finite input, bad option */
+    GINT_EPATTERN = -2,      /* an overlapping (I,J,R) is missing, or the pattern is not transpose-closed */
+    GINT_ENOMEM = -3,        /* host or device allocation failed (or exceeded a workspace cap) */
+    GINT_EHIP = -4,          /* a HIP runtime call failed; see gint_last_hip_error() */
+    GINT_EUNSUPPORTED = -5   /* l > 2, more than 16 orbitals per atom, unavailable precision */
+};
+
+enum {
+    GINT_FP64 = 0            /* plain path: FP64 orbitals, FP64 MFMA contractions */
+};
+
+typedef struct gint_plan gint_plan;
+
+/* Radial basis of one species (host memory, read during gint_plan_create).
+ * Knots r_k = k dr, k = 0..nknots-1, with (nknots-1) dr >= rcut.  f[c][k]
+ * and fp[c][k] hold f_c(r_k) and f_c'(r_k) of channel c; the radial factor
+ * of the orbital is R_c(r) = r^l f_c(r), interpolated by the cubic Hermite
+ * polynomial on [r_k, r_k+1]; this is the reading of "tabulated cubic-spline
+ * radial functions" used throughout (the interpolant's own derivative is used
+ * for gradients, so forces are exact derivatives of the energy). */
+typedef struct {
+    double rcut;             /* strict cutoff: phi = 0 for r >= rcut */
+    double dr;               /* knot spacing (> 0) */
+    int nknots;              /* >= 2 */
+    int nchan;               /* >= 1 */
+    const int *chan_l;       /* [nchan], 0 <= l <= 2 */
+    const double *f;         /* [nchan][nknots] */
+    const double *fp;        /* [nchan][nknots] */
+} gint_species;
+
+/* One periodic system (host memory, read during gint_plan_create). */
+typedef struct {
+    double cell[9];          /* rows a1, a2, a3 (Bohr); Omega = |det| > 0 */
+    int natom;               /* >= 1 */
+    const double *pos;       /* [natom][3] Cartesian, used as given (never wrapped) */
+    const int *species;      /* [natom], indices into species_list */
+    int nspecies;
+    const gint_species *species_list;
+    int grid[3];             /* N1, N2, N3 >= 1 */
+    int nblk;                /* number of (I, J, R) blocks */
+    const int *blk_i;        /* [nblk] */
+    const int *blk_j;        /* [nblk] */
+    const int *blk_r;        /* [nblk][3] */
+    const int64_t *blk_off;  /* [nblk] element offset of each block */
+} gint_system;
+
+/* Plan options; pass NULL for defaults. */
+typedef struct {
+    int precision;           /* GINT_FP64 */
+    int cluster_atoms;       /* atoms per cluster tile, 1..4 (0 = default 4) */
+    int max_bigcells_per_item; /* work-item length cap (0 = default) */
+    int reserved[5];
+} gint_options;
+
+/* Sizes of a plan (host struct filled by gint_plan_query). */
+typedef struct {
+    int64_t ngrid;           /* N1 N2 N3 */
+    int64_t nnz;             /* length of h_vals / d_vals */
+    int natom;
+    int ncluster;
+    int64_t npairs;          /* canonical cluster pairs */
+    int64_t nitems;          /* work items of the canonical list */
+    int64_t nbigcells;       /* bigcell visits summed over canonical pairs */
+    double work_units;       /* W = sum_g n_orb(g)^2 (0 unless computed) */
+    double volume;           /* Omega */
+    int64_t device_bytes;    /* device memory held by the plan */
+    double build_seconds;    /* host time of gint_plan_create */
+} gint_sizes;
+
+/* Build a plan for n_sys systems (n_sys == 1 in this version): validates
+ * the inputs, groups atoms into clusters, enumerates cluster-image pairs and
+ * the bigcells (4x4x4 grid points) where their orbitals overlap, maps every
+ * overlapping atom pair to its pattern block (paper: sub-task division and
+ * sub-task descriptors, "Computational Collaboration Between Host and
+ * Device"), and uploads the descriptors to the current device.  Synchronous.
+ * On success *out owns device memory until gint_plan_destroy. */
+int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys,
+                     const gint_options *opt, void *stream);
+
+/* H_IJR (Eq. 2) for every block of the pattern.  v_loc: device f64[N_g].
+ * h_vals: device f64[nnz], overwritten (blocks with no overlap become 0). */
+int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream);
+
+/* rho_g (Eq. 3).  d_vals: device f64[nnz].  rho: device f64[N_g], overwritten.
+ * n_elec: device f64[1] receiving sum_g w rho_g, or NULL. */
+int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, void *stream);
+
+/* Grid Pulay force and stress (Eq. 4-5).  force: device f64[natom][3],
+ * F_K = -dE/dtau_K.  stress: device f64[3][3], sigma = -Z/Omega with
+ * Z_ab = dE/d(eps_ab) at fixed w (unsymmetrised).  energy: device f64[1]
+ * receiving E = sum_g w V_g rho_g, or NULL.  All outputs overwritten. */
+int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals,
+                      double *force, double *stress, double *energy, void *stream);
+
+/* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
+ * the unit of work of the throughput metric, counted exactly from the plan's
+ * neighbour lists.  w_out: device f64[1], overwritten. */
+int gint_work_units(gint_plan *p, double *w_out, void *stream);
+
+int gint_plan_query(const gint_plan *p, gint_sizes *out);
+void gint_plan_destroy(gint_plan *p);
+const char *gint_strerror(int code);
+/* Last HIP error code recorded by a failing call (0 if none). */
+int gint_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GINT_H */

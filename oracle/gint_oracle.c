@@ -129,13 +129,7 @@ static void orbitals_at(const oracle_system *s, int sp, const double x[3], doubl
 /* ------------------------------------------------------------------------ */
 /* Block lookup (I, J, R) -> block index: open addressing hash table.        */
 /* ------------------------------------------------------------------------ */
-typedef struct { long *keys; int *vals; long cap; } bhash;
-
-static long bkey(int i, int j, int r0, int r1, int r2)
-{
-    /* r components in [-512, 511], atoms < 2^20 */
-    return ((((long)i * (1L << 20) + j) * 1024 + (r0 + 512)) * 1024 + (r1 + 512)) * 1024 + (r2 + 512);
-}
+typedef struct { int *keys; int *vals; long cap; } bhash;   /* keys: 5 ints per slot, keys[5q] = -1 if empty */
 
 static uint64_t mix64(uint64_t z)
 {
@@ -145,23 +139,38 @@ static uint64_t mix64(uint64_t z)
     return z ^ (z >> 31);
 }
 
+static uint64_t bhash_of(int i, int j, const int r[3])
+{
+    uint64_t h = mix64((uint64_t)(uint32_t)i);
+    h = mix64(h ^ (uint64_t)(uint32_t)j);
+    h = mix64(h ^ (uint64_t)(uint32_t)r[0]);
+    h = mix64(h ^ (uint64_t)(uint32_t)r[1]);
+    return mix64(h ^ (uint64_t)(uint32_t)r[2]);
+}
+
+static int bkey_eq(const int *k, int i, int j, const int r[3])
+{
+    return k[0] == i && k[1] == j && k[2] == r[0] && k[3] == r[1] && k[4] == r[2];
+}
+
 static int bhash_build(bhash *hb, const oracle_system *s)
 {
     long cap = 16;
     while (cap < 2L * s->nblk + 16) cap <<= 1;
     hb->cap = cap;
-    hb->keys = (long *)malloc(sizeof(long) * cap);
+    hb->keys = (int *)malloc(sizeof(int) * 5 * cap);
     hb->vals = (int *)malloc(sizeof(int) * cap);
     if (!hb->keys || !hb->vals) return ORACLE_ENOMEM;
-    for (long q = 0; q < cap; ++q) hb->keys[q] = -1;
+    for (long q = 0; q < cap; ++q) hb->keys[5 * q] = -1;
     for (int b = 0; b < s->nblk; ++b) {
+        const int i = s->blk_i[b], j = s->blk_j[b];
         const int *r = s->blk_r + 3 * b;
-        if (abs(r[0]) > 511 || abs(r[1]) > 511 || abs(r[2]) > 511) return ORACLE_EINVAL;
-        long k = bkey(s->blk_i[b], s->blk_j[b], r[0], r[1], r[2]);
-        long q = (long)(mix64((uint64_t)k) & (uint64_t)(cap - 1));
-        while (hb->keys[q] != -1 && hb->keys[q] != k) q = (q + 1) & (cap - 1);
-        if (hb->keys[q] == k) return ORACLE_EINVAL;   /* duplicate block */
-        hb->keys[q] = k;
+        if (i < 0 || j < 0 || i >= s->natom || j >= s->natom) return ORACLE_EINVAL;
+        long q = (long)(bhash_of(i, j, r) & (uint64_t)(cap - 1));
+        while (hb->keys[5 * q] != -1 && !bkey_eq(hb->keys + 5 * q, i, j, r)) q = (q + 1) & (cap - 1);
+        if (hb->keys[5 * q] != -1) return ORACLE_EINVAL;   /* duplicate block */
+        int *k = hb->keys + 5 * q;
+        k[0] = i; k[1] = j; k[2] = r[0]; k[3] = r[1]; k[4] = r[2];
         hb->vals[q] = b;
     }
     return ORACLE_OK;
@@ -169,11 +178,9 @@ static int bhash_build(bhash *hb, const oracle_system *s)
 
 static int bhash_find(const bhash *hb, int i, int j, const int r[3])
 {
-    if (abs(r[0]) > 511 || abs(r[1]) > 511 || abs(r[2]) > 511) return -1;
-    long k = bkey(i, j, r[0], r[1], r[2]);
-    long q = (long)(mix64((uint64_t)k) & (uint64_t)(hb->cap - 1));
-    while (hb->keys[q] != -1) {
-        if (hb->keys[q] == k) return hb->vals[q];
+    long q = (long)(bhash_of(i, j, r) & (uint64_t)(hb->cap - 1));
+    while (hb->keys[5 * q] != -1) {
+        if (bkey_eq(hb->keys + 5 * q, i, j, r)) return hb->vals[q];
         q = (q + 1) & (hb->cap - 1);
     }
     return -1;
@@ -854,3 +861,5 @@ int oracle_work(const oracle_system *s, long g0, long g1, double *w_out)
     ctx_free(&c);
     return ORACLE_OK;
 }
+
+int oracle_num_threads(void) { return nthreads_max(); }

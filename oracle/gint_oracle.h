@@ -83,6 +83,8 @@ int oracle_radial(const oracle_system *s, int species, int chan, long n, const d
 int oracle_neighbours(const oracle_system *s, long g, int cap, int *atom, int *T, double *x);
 /* Sum over grid points of n_orb(g)^2 (the unit of work W) over a range. */
 int oracle_work(const oracle_system *s, long g_begin, long g_end, double *w_out);
+/* OpenMP threads the oracle uses. */
+int oracle_num_threads(void);
 
 #ifdef __cplusplus
 }

@@ -68,12 +68,18 @@ def _load():
         lib.oracle_radial.argtypes = [P, C.c_int, C.c_int, C.c_long, P, P, P]
         lib.oracle_neighbours.argtypes = [P, C.c_long, C.c_int, P, P, P]
         lib.oracle_work.argtypes = [P, C.c_long, C.c_long, P]
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = C.c_int
         _lib = lib
     return _lib
 
 
 def _p(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
 
 
 class Oracle:

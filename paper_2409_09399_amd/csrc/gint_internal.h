@@ -1,0 +1,78 @@
+// Internal layout shared by the plan builder (host C++) and the HIP kernels.
+//
+// Work decomposition.  Atoms are grouped into spatially compact clusters of
+// at most CL atoms.  A cluster pair (A at image TA, B at image TB) owns the
+// 16 x 16 orbital tiles of every atom pair (a in A, b in B); each atom takes
+// one 16-wide orbital slot (13 orbitals of 2s2p1d padded to 16).  The region
+// where the pair's orbitals overlap is covered by bigcells of 4x4x4 grid
+// points on the unwrapped (infinite) grid; V and rho are indexed modulo the
+// grid.  A work item is a run of bigcells of one pair and is processed by one
+// workgroup, which keeps the pair's output tiles in registers across the
+// whole run (output-stationary), so H needs one write per item instead of
+// one read-modify-write per bigcell.
+#pragma once
+#include <stdint.h>
+
+#define GINT_CL 4            // atoms per cluster (max)
+#define GINT_ORB 16          // orbital slots per atom
+#define GINT_MAXCHAN 8       // radial channels per species
+#define GINT_BC 4            // bigcell edge in grid points
+#define GINT_BCPTS 64        // points per bigcell
+#define GINT_MAXSPECIES 16
+
+struct GSpecies {
+    double rcut;
+    double rcut2;
+    double dr;
+    double inv_dr;
+    int nknots;
+    int nchan;
+    int norb;
+    int tab_off;                 // offset (doubles) of [knot][chan][f, f'] in the table array
+    int chan_l[GINT_MAXCHAN];
+};
+
+struct GAtom {
+    double x, y, z;
+    int species;
+    int norb;
+};
+
+// One cluster pair.  hoff[i*4+j] is the element offset of block
+// (a_i -> b_j, R = TB - TA) or -1; hoff_t[i*4+j] that of (b_j -> a_i, -R).
+struct GPair {
+    int a[GINT_CL];              // atom ids, -1 = empty slot
+    int b[GINT_CL];
+    double shiftA[3];            // TA.h added to A-atom positions
+    double shiftB[3];            // TB.h added to B-atom positions
+    int self;                    // 1: A == B with TA == TB (tiles cover both orders)
+    int pad;
+    long long hoff[GINT_CL * GINT_CL];
+    long long hoff_t[GINT_CL * GINT_CL];
+};
+
+struct GBig {
+    int x, y, z, w;              // origin point index of a bigcell (w unused)
+};
+
+struct GItem {
+    int pair;
+    int bc_begin;
+    int bc_count;
+    int pad;
+};
+
+// Everything a kernel needs, passed by value.
+struct GDev {
+    const GSpecies *species;
+    const GAtom *atoms;
+    const double *tab;           // interleaved radial tables
+    const GPair *pairs;
+    const GBig *bigcells;
+    const GItem *items;
+    int nitems;
+    int natom;
+    int N[3];
+    double e[3][3];              // grid step vectors e_i = a_i / N_i (rows)
+    double w;                    // volume per grid point
+};

@@ -1,0 +1,607 @@
+// HIP kernels for grid integration on CDNA4 (gfx950), FP64 path.
+//
+// Each workgroup (4 waves, 256 threads) takes one work item: a run of
+// bigcells (4x4x4 grid points) of one cluster pair (A, B), see
+// gint_internal.h.  Per bigcell:
+//   phase 1  every thread evaluates orbitals of one A atom and one B atom at
+//            one point into LDS tiles phi[point][atom slot][16 orbitals]
+//            (cubic Hermite radial table x real solid harmonic, l <= 2), and
+//            marks which atoms reach which points;
+//   phase 2  MFMA v_mfma_f64_16x16x4f64 contractions on the tiles;
+//   phase 3  (rho, force) per-point reductions of the MFMA output.
+// Vlocal keeps the 16 (a_i, b_j) output tiles of the pair in registers for
+// the whole item (wave i owns row atom a_i) and writes them once at the end.
+#include <hip/hip_runtime.h>
+
+#include "gint_internal.h"
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+#define PSTR 65     // LDS doubles per point row: 4 slots x 16 orbitals + 1 (bank spread)
+
+namespace {
+
+constexpr double kC0 = 0.28209479177387814;    // 1/(2 sqrt(pi))
+constexpr double kC1 = 0.48860251190291992;    // sqrt(3/(4 pi))
+constexpr double kC2a = 1.0925484305920792;    // sqrt(15/pi)/2
+constexpr double kC2b = 0.31539156525252005;   // sqrt(5/pi)/4
+constexpr double kC2c = 0.54627421529603959;   // sqrt(15/pi)/4
+
+__device__ inline int wrap(int n, int N) {
+    int m = n % N;
+    return m < 0 ? m + N : m;
+}
+
+struct Pt {
+    double x, y, z;
+    long long g;
+};
+
+// Point pt (0..63, i-major: i = pt>>4, j = (pt>>2)&3, k = pt&3) of the
+// bigcell with origin o.
+__device__ inline Pt bigcell_point(const GDev &P, const GBig &o, int pt) {
+    const int n0 = o.x + (pt >> 4), n1 = o.y + ((pt >> 2) & 3), n2 = o.z + (pt & 3);
+    Pt r;
+    r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
+    r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
+    r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
+    r.g = ((long long)wrap(n0, P.N[0]) * P.N[1] + wrap(n1, P.N[1])) * P.N[2] + wrap(n2, P.N[2]);
+    return r;
+}
+
+// Hermite basis on [r_k, r_k+1] of the species table; returns the knot row.
+struct Herm {
+    const double *row0, *row1;
+    double h00, h10, h01, h11;     // value weights (h10, h11 include dr)
+    double d00, d10, d01, d11;     // derivative weights (per unit r)
+};
+
+__device__ inline Herm hermite(const GSpecies &sp, const double *tab, double r) {
+    double t = r * sp.inv_dr;
+    int k = (int)t;
+    if (k > sp.nknots - 2) k = sp.nknots - 2;
+    t -= (double)k;
+    const double t2 = t * t, t3 = t2 * t;
+    Herm h;
+    h.row0 = tab + sp.tab_off + (size_t)k * sp.nchan * 2;
+    h.row1 = h.row0 + sp.nchan * 2;
+    h.h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+    h.h10 = (t3 - 2.0 * t2 + t) * sp.dr;
+    h.h01 = 3.0 * t2 - 2.0 * t3;
+    h.h11 = (t3 - t2) * sp.dr;
+    h.d00 = (6.0 * t2 - 6.0 * t) * sp.inv_dr;
+    h.d10 = 3.0 * t2 - 4.0 * t + 1.0;
+    h.d01 = -h.d00;
+    h.d11 = 3.0 * t2 - 2.0 * t;
+    return h;
+}
+
+__device__ inline void solid9(double x, double y, double z, double S[9]) {
+    S[0] = kC0;
+    S[1] = kC1 * y;
+    S[2] = kC1 * z;
+    S[3] = kC1 * x;
+    S[4] = kC2a * x * y;
+    S[5] = kC2a * y * z;
+    S[6] = kC2b * (2.0 * z * z - x * x - y * y);
+    S[7] = kC2a * x * z;
+    S[8] = kC2c * (x * x - y * y);
+}
+
+// phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
+// (LDS); slots past the atom's orbitals are zero.
+__device__ inline void eval_phi(const GSpecies &sp, const double *tab, double x, double y, double z, double r2,
+                                double scale, double *dst) {
+    const double r = sqrt(r2);
+    const Herm h = hermite(sp, tab, r);
+    double S[9];
+    solid9(x, y, z, S);
+    int slot = 0;
+    for (int c = 0; c < sp.nchan; ++c) {
+        const double p = (h.h00 * h.row0[2 * c] + h.h10 * h.row0[2 * c + 1] + h.h01 * h.row1[2 * c] +
+                          h.h11 * h.row1[2 * c + 1]) * scale;
+        const int l = sp.chan_l[c];
+        if (l == 0) {
+            dst[slot] = p * S[0];
+            slot += 1;
+        } else if (l == 1) {
+            dst[slot] = p * S[1];
+            dst[slot + 1] = p * S[2];
+            dst[slot + 2] = p * S[3];
+            slot += 3;
+        } else {
+            dst[slot] = p * S[4];
+            dst[slot + 1] = p * S[5];
+            dst[slot + 2] = p * S[6];
+            dst[slot + 3] = p * S[7];
+            dst[slot + 4] = p * S[8];
+            slot += 5;
+        }
+    }
+    for (; slot < GINT_ORB; ++slot) dst[slot] = 0.0;
+}
+
+__device__ inline void zero16(double *dst) {
+#pragma unroll
+    for (int k = 0; k < GINT_ORB; ++k) dst[k] = 0.0;
+}
+
+// sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu for one atom at x
+// (grad phi = (p'/r) x S + p grad S; the first term is 0 at r = 0).
+__device__ inline void dot_phi_grad(const GSpecies &sp, const double *tab, double x, double y, double z, double r2,
+                                    const double *psi, double &e, double G[3]) {
+    const double r = sqrt(r2);
+    const Herm h = hermite(sp, tab, r);
+    const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
+    e = 0.0;
+    G[0] = G[1] = G[2] = 0.0;
+    int slot = 0;
+    for (int c = 0; c < sp.nchan; ++c) {
+        const double f0 = h.row0[2 * c], fp0 = h.row0[2 * c + 1], f1 = h.row1[2 * c], fp1 = h.row1[2 * c + 1];
+        const double p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
+        const double q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
+        const int l = sp.chan_l[c];
+        double A, Bx, By, Bz;   // A = sum_m psi_m S_m, B = sum_m psi_m grad S_m
+        if (l == 0) {
+            A = psi[slot] * kC0;
+            Bx = By = Bz = 0.0;
+            slot += 1;
+        } else if (l == 1) {
+            const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2];   // (y, z, x)
+            A = kC1 * (p0 * y + p1 * z + p2 * x);
+            Bx = kC1 * p2;
+            By = kC1 * p0;
+            Bz = kC1 * p1;
+            slot += 3;
+        } else {
+            const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2], p3 = psi[slot + 3],
+                         p4 = psi[slot + 4];
+            A = kC2a * (p0 * x * y + p1 * y * z + p3 * x * z) + kC2b * p2 * (2.0 * z * z - x * x - y * y) +
+                kC2c * p4 * (x * x - y * y);
+            Bx = kC2a * (p0 * y + p3 * z) - 2.0 * kC2b * p2 * x + 2.0 * kC2c * p4 * x;
+            By = kC2a * (p0 * x + p1 * z) - 2.0 * kC2b * p2 * y - 2.0 * kC2c * p4 * y;
+            Bz = kC2a * (p1 * y + p3 * x) + 4.0 * kC2b * p2 * z;
+            slot += 5;
+        }
+        e += p * A;
+        G[0] += q * A * x + p * Bx;
+        G[1] += q * A * y + p * By;
+        G[2] += q * A * z + p * Bz;
+    }
+}
+
+__device__ inline d4 mfma64(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ inline unsigned or16(unsigned m) {
+    m |= __shfl_xor(m, 1);
+    m |= __shfl_xor(m, 2);
+    m |= __shfl_xor(m, 4);
+    m |= __shfl_xor(m, 8);
+    return m;
+}
+
+// Phase 1: orbitals of the A atom (slot t>>6) and B atom at point t&63.
+// mode 0: A and B unscaled; mode 1: B scaled by w V_g; mode 2: B only, A
+// gets the activity bit only.
+template <int MODE>
+__device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, const double *__restrict__ V,
+                             double *phiA, double *phiB, unsigned *maskpt) {
+    const int t = threadIdx.x;
+    const int pt = t & 63, slot = t >> 6;
+    const Pt r = bigcell_point(P, o, pt);
+    unsigned bits = 0;
+    {
+        const int a = pr.a[slot];
+        double *dst = phiA + pt * PSTR + slot * GINT_ORB;
+        bool in = false;
+        double x = 0, y = 0, z = 0, r2 = 0;
+        if (a >= 0) {
+            const GAtom at = P.atoms[a];
+            x = r.x - at.x - pr.shiftA[0];
+            y = r.y - at.y - pr.shiftA[1];
+            z = r.z - at.z - pr.shiftA[2];
+            r2 = x * x + y * y + z * z;
+            const GSpecies &sp = P.species[at.species];
+            in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+            if (MODE != 2) {
+                if (in) eval_phi(sp, P.tab, x, y, z, r2, 1.0, dst);
+                else zero16(dst);
+            }
+        } else if (MODE != 2) {
+            zero16(dst);
+        }
+        if (in) bits |= 1u << slot;
+    }
+    {
+        const int b = pr.b[slot];
+        double *dst = phiB + pt * PSTR + slot * GINT_ORB;
+        bool in = false;
+        if (b >= 0) {
+            const GAtom at = P.atoms[b];
+            const double x = r.x - at.x - pr.shiftB[0];
+            const double y = r.y - at.y - pr.shiftB[1];
+            const double z = r.z - at.z - pr.shiftB[2];
+            const double r2 = x * x + y * y + z * z;
+            const GSpecies &sp = P.species[at.species];
+            in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+            if (in) {
+                const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
+                eval_phi(sp, P.tab, x, y, z, r2, scale, dst);
+            } else {
+                zero16(dst);
+            }
+        } else {
+            zero16(dst);
+        }
+        if (in) bits |= 1u << (4 + slot);
+    }
+    if (bits) atomicOr(&maskpt[pt], bits);
+}
+
+// D_sym[a_i mu][b_j nu] as the MFMA B operand of k-step s: lane holds
+// (mu = lane & 15, nu = 4 s + (lane >> 4)).
+__device__ inline void load_dsym(const GDev &P, const GPair &pr, const double *__restrict__ D, double dreg[4][4][4]) {
+    const int lane = threadIdx.x & 63;
+    const int mu = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
+            const int na = pr.a[i] >= 0 ? P.atoms[pr.a[i]].norb : 0;
+            const int nb = pr.b[j] >= 0 ? P.atoms[pr.b[j]].norb : 0;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int nu = 4 * s + (lane >> 4);
+                double v = 0.0;
+                if (o >= 0 && ot >= 0 && mu < na && nu < nb)
+                    v = 0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]);
+                dreg[i][j][s] = v;
+            }
+        }
+}
+
+// Phase 2 of rho/force: wave w computes psi[pt][a_i][mu] = sum_{b_j, nu}
+// phi_B[pt][b_j][nu] D_sym[a_i mu][b_j nu] for its 16 points and writes it
+// over its own rows of phiB (no other wave reads those rows).
+__device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const unsigned *maskpt) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    unsigned gm = or16(maskpt[16 * w + (lane & 15)]);
+    gm = __builtin_amdgcn_readfirstlane(gm);
+    d4 acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        acc[i] = (d4){0.0, 0.0, 0.0, 0.0};
+        if (!(gm & (1u << i))) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!(gm & (1u << (4 + j)))) continue;
+            const double *src = phiB + (16 * w + (lane & 15)) * PSTR + j * GINT_ORB + (lane >> 4);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) acc[i] = mfma64(src[4 * s], dreg[i][j][s], acc[i]);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    double *dst = phiB + (16 * w + 4 * (lane >> 4)) * PSTR + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q * PSTR + i * GINT_ORB] = acc[i][q];
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// H_IJR (Eq. 2)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict__ V, double *__restrict__ H) {
+    __shared__ double phiA[GINT_BCPTS * PSTR];
+    __shared__ double phiB[GINT_BCPTS * PSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    const GItem it = P.items[blockIdx.x];
+    const GPair &pr = P.pairs[it.pair];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    d4 acc[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
+
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        stage<1>(P, pr, o, V, phiA, phiB, maskpt);
+        __syncthreads();
+        // wave w owns row atom a_w; k-steps of 4 points along the third axis
+        for (int s = 0; s < 16; ++s) {
+            unsigned m = maskpt[4 * s] | maskpt[4 * s + 1] | maskpt[4 * s + 2] | maskpt[4 * s + 3];
+            m = __builtin_amdgcn_readfirstlane(m);
+            if (!(m & (1u << w))) continue;
+            const int row = (4 * s + (lane >> 4)) * PSTR + (lane & 15);
+            const double a = phiA[row + w * GINT_ORB];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (m & (1u << (4 + j))) acc[j] = mfma64(a, phiB[row + j * GINT_ORB], acc[j]);
+        }
+        __syncthreads();
+    }
+    // tile (a_w, b_j): lane holds rows mu = 4 (lane >> 4) + q, column nu = lane & 15
+    const int ai = pr.a[w];
+    if (ai < 0) return;
+    const int na = P.atoms[ai].norb;
+    const int nu = lane & 15;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int bj = pr.b[j];
+        if (bj < 0) continue;
+        const int nb = P.atoms[bj].norb;
+        const long long o = pr.hoff[w * 4 + j], ot = pr.hoff_t[w * 4 + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mu = 4 * (lane >> 4) + q;
+            if (mu >= na || nu >= nb) continue;
+            const double v = acc[j][q];
+            if (o >= 0) atomicAdd(H + o + (long long)mu * nb + nu, v);
+            if (!pr.self && ot >= 0) atomicAdd(H + ot + (long long)nu * na + mu, v);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// rho_g (Eq. 3): canonical pairs, weight 2 off the self pair
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rho(GDev P, const double *__restrict__ D, double *__restrict__ rho) {
+    __shared__ double phiA[GINT_BCPTS * PSTR];
+    __shared__ double phiB[GINT_BCPTS * PSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ double part[4][GINT_BCPTS];
+    const GItem it = P.items[blockIdx.x];
+    const GPair &pr = P.pairs[it.pair];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double dreg[4][4][4];
+    load_dsym(P, pr, D, dreg);
+    const double weight = pr.self ? 1.0 : 2.0;
+
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        stage<0>(P, pr, o, nullptr, phiA, phiB, maskpt);
+        __syncthreads();
+        psi_tiles(dreg, phiB, maskpt);
+        __syncthreads();
+        // phase 3: wave w = A slot w, lane = point
+        {
+            const double *pa = phiA + lane * PSTR + w * GINT_ORB;
+            const double *ps = phiB + lane * PSTR + w * GINT_ORB;
+            double v = 0.0;
+            if (maskpt[lane] & (1u << w)) {
+#pragma unroll
+                for (int mu = 0; mu < GINT_ORB; ++mu) v += pa[mu] * ps[mu];
+            }
+            part[w][lane] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < GINT_BCPTS) {
+            const int pt = threadIdx.x;
+            const double v = part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt];
+            if ((maskpt[pt] & 0xFu) && (maskpt[pt] & 0xF0u)) {
+                const Pt r = bigcell_point(P, o, pt);
+                atomicAdd(rho + r.g, weight * v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only
+// acc[0..2] F of atom a_w, acc[3..11] Z, acc[12] E
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_force(GDev P, const double *__restrict__ V, const double *__restrict__ D,
+                                               double *__restrict__ F, double *__restrict__ ZE) {
+    __shared__ double phiB[GINT_BCPTS * PSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ double red[4][10];
+    const GItem it = P.items[blockIdx.x];
+    const GPair &pr = P.pairs[it.pair];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double dreg[4][4][4];
+    load_dsym(P, pr, D, dreg);
+    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
+    const int aw = pr.a[w];
+
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt);
+        __syncthreads();
+        psi_tiles(dreg, phiB, maskpt);
+        __syncthreads();
+        if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+            const Pt r = bigcell_point(P, o, lane);
+            const GAtom at = P.atoms[aw];
+            const double x = r.x - at.x - pr.shiftA[0];
+            const double y = r.y - at.y - pr.shiftA[1];
+            const double zz = r.z - at.z - pr.shiftA[2];
+            const double r2 = x * x + y * y + zz * zz;
+            double e, G[3];
+            dot_phi_grad(P.species[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
+            const double wv = P.w * V[r.g];
+            const double c = 2.0 * wv;
+            f[0] += c * G[0];
+            f[1] += c * G[1];
+            f[2] += c * G[2];
+            const double xs[3] = {x, y, zz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) z[3 * a + b] += c * G[a] * xs[b];
+            en += wv * e;
+        }
+        __syncthreads();
+    }
+    // reduce over the wave
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f[a] += __shfl_xor(f[a], off);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) z[a] += __shfl_xor(z[a], off);
+        en += __shfl_xor(en, off);
+    }
+    if (lane == 0) {
+        if (aw >= 0) {
+            atomicAdd(F + 3 * aw + 0, f[0]);
+            atomicAdd(F + 3 * aw + 1, f[1]);
+            atomicAdd(F + 3 * aw + 2, f[2]);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) red[w][a] = z[a];
+        red[w][9] = en;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int k = threadIdx.x;
+        atomicAdd(ZE + k, red[0][k] + red[1][k] + red[2][k] + red[3][k]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// W = sum_g n_orb(g)^2 from the canonical pairs (exact in FP64: integers)
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_work(GDev P, double *__restrict__ W) {
+    __shared__ double red[256];
+    const GItem it = P.items[blockIdx.x];
+    const GPair &pr = P.pairs[it.pair];
+    const double weight = pr.self ? 1.0 : 2.0;
+    double acc = 0.0;
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) {
+            const Pt r = bigcell_point(P, o, threadIdx.x);
+            double na = 0, nb = 0;
+            for (int k = 0; k < GINT_CL; ++k) {
+                if (pr.a[k] >= 0) {
+                    const GAtom at = P.atoms[pr.a[k]];
+                    const double x = r.x - at.x - pr.shiftA[0], y = r.y - at.y - pr.shiftA[1],
+                                 z = r.z - at.z - pr.shiftA[2];
+                    const double r2 = x * x + y * y + z * z;
+                    const GSpecies &sp = P.species[at.species];
+                    if (r2 < sp.rcut2 && sqrt(r2) < sp.rcut) na += at.norb;
+                }
+                if (pr.b[k] >= 0) {
+                    const GAtom at = P.atoms[pr.b[k]];
+                    const double x = r.x - at.x - pr.shiftB[0], y = r.y - at.y - pr.shiftB[1],
+                                 z = r.z - at.z - pr.shiftB[2];
+                    const double r2 = x * x + y * y + z * z;
+                    const GSpecies &sp = P.species[at.species];
+                    if (r2 < sp.rcut2 && sqrt(r2) < sp.rcut) nb += at.norb;
+                }
+            }
+            acc += weight * na * nb;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicAdd(W, red[0]);
+}
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__global__ void k_fill(double *__restrict__ p, long long n, double v) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// partial sums of w * x over a grid array (deterministic two-pass reduction)
+__global__ __launch_bounds__(256) void k_sum_partial(const double *__restrict__ x, long long n, double scale,
+                                                     double *__restrict__ part) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += x[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0] * scale;
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
+// stress = -Z / Omega, energy = E
+__global__ void k_finish_stress(const double *__restrict__ ZE, double inv_omega, double *__restrict__ stress,
+                                double *__restrict__ energy) {
+    const int k = threadIdx.x;
+    if (k < 9) stress[k] = -ZE[k] * inv_omega;
+    if (k == 9 && energy) energy[0] = ZE[9];
+}
+
+// ---------------------------------------------------------------------------
+// launchers (called from the C ABI layer)
+// ---------------------------------------------------------------------------
+hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    long long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s) {
+    if (P.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_vlocal, dim3(P.nitems), dim3(256), 0, s, P, V, H);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s) {
+    if (P.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rho, dim3(P.nitems), dim3(256), 0, s, P, D, rho);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, hipStream_t s) {
+    if (P.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_force, dim3(P.nitems), dim3(256), 0, s, P, V, D, F, ZE);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
+    if (P.nitems <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_work, dim3(P.nitems), dim3(256), 0, s, P, W);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_sum(const double *x, long long n, double scale, double *part, int nparts, double *out,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_sum_partial, dim3(nparts), dim3(256), 0, s, x, n, scale, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, part, nparts, out);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_finish_stress(const double *ZE, double inv_omega, double *stress, double *energy,
+                                     hipStream_t s) {
+    hipLaunchKernelGGL(k_finish_stress, dim3(1), dim3(64), 0, s, ZE, inv_omega, stress, energy);
+    return hipGetLastError();
+}

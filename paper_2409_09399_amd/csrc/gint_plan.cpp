@@ -1,0 +1,456 @@
+// Host plan builder.  See gint_plan.hpp and gint_internal.h for the layout.
+#include "gint_plan.hpp"
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <thread>
+#include <unordered_map>
+
+namespace {
+
+struct Vec3 {
+    double x, y, z;
+};
+
+inline Vec3 sub(Vec3 a, Vec3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline Vec3 add(Vec3 a, Vec3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+inline double dot(Vec3 a, Vec3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+struct Geometry {
+    double cell[9];
+    double inv[9];          // frac = x . inv  (column i of inv is reciprocal vector b_i)
+    double spacing[3];      // interplanar spacings
+    int N[3];
+    Vec3 e[3];              // grid step vectors
+    Vec3 a[3];              // lattice vectors
+    Vec3 lat(int t0, int t1, int t2) const {
+        return {t0 * a[0].x + t1 * a[1].x + t2 * a[2].x, t0 * a[0].y + t1 * a[1].y + t2 * a[2].y,
+                t0 * a[0].z + t1 * a[1].z + t2 * a[2].z};
+    }
+    double frac(Vec3 x, int i) const { return x.x * inv[i] + x.y * inv[3 + i] + x.z * inv[6 + i]; }
+    Vec3 point(double n0, double n1, double n2) const {
+        return {n0 * e[0].x + n1 * e[1].x + n2 * e[2].x, n0 * e[0].y + n1 * e[1].y + n2 * e[2].y,
+                n0 * e[0].z + n1 * e[1].z + n2 * e[2].z};
+    }
+};
+
+bool invert3(const double *a, double *b, double *det) {
+    double d = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+               a[2] * (a[3] * a[7] - a[4] * a[6]);
+    *det = d;
+    if (!(std::fabs(d) > 0.0) || !std::isfinite(d)) return false;
+    b[0] = (a[4] * a[8] - a[5] * a[7]) / d; b[1] = (a[2] * a[7] - a[1] * a[8]) / d; b[2] = (a[1] * a[5] - a[2] * a[4]) / d;
+    b[3] = (a[5] * a[6] - a[3] * a[8]) / d; b[4] = (a[0] * a[8] - a[2] * a[6]) / d; b[5] = (a[2] * a[3] - a[0] * a[5]) / d;
+    b[6] = (a[3] * a[7] - a[4] * a[6]) / d; b[7] = (a[1] * a[6] - a[0] * a[7]) / d; b[8] = (a[0] * a[4] - a[1] * a[3]) / d;
+    return true;
+}
+
+struct BlockKey {
+    int i, j, r0, r1, r2;
+    bool operator==(const BlockKey &o) const {
+        return i == o.i && j == o.j && r0 == o.r0 && r1 == o.r1 && r2 == o.r2;
+    }
+};
+
+struct BlockKeyHash {
+    size_t operator()(const BlockKey &k) const {
+        unsigned long long h = 0x9E3779B97F4A7C15ull;
+        const int v[5] = {k.i, k.j, k.r0, k.r1, k.r2};
+        for (int x : v) {
+            h ^= (unsigned long long)(unsigned)x + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+            h *= 0xBF58476D1CE4E5B9ull;
+        }
+        return (size_t)(h ^ (h >> 31));
+    }
+};
+
+struct BlockMap {
+    std::unordered_map<BlockKey, long long, BlockKeyHash> off;   // (I, J, R) -> element offset
+    long long find(int i, int j, int r0, int r1, int r2) const {
+        auto it = off.find(BlockKey{i, j, r0, r1, r2});
+        return it == off.end() ? -1 : it->second;
+    }
+};
+
+// Recursive bisection of atoms along the longest extent into groups of at
+// most cl atoms; left halves take a multiple of cl atoms so clusters are full.
+void bisect(const std::vector<Vec3> &pos, std::vector<int> idx, int cl, std::vector<std::vector<int>> &out) {
+    if ((int)idx.size() <= cl) {
+        out.push_back(idx);
+        return;
+    }
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i : idx) {
+        const double c[3] = {pos[i].x, pos[i].y, pos[i].z};
+        for (int k = 0; k < 3; ++k) { lo[k] = std::min(lo[k], c[k]); hi[k] = std::max(hi[k], c[k]); }
+    }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+        if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int p, int q) {
+        const double a = ax == 0 ? pos[p].x : ax == 1 ? pos[p].y : pos[p].z;
+        const double b = ax == 0 ? pos[q].x : ax == 1 ? pos[q].y : pos[q].z;
+        return a < b;
+    });
+    const int n = (int)idx.size();
+    int nl = ((n + 2 * cl - 1) / (2 * cl)) * cl;
+    if (nl >= n) nl = n - 1;
+    if (nl < 1) nl = 1;
+    bisect(pos, std::vector<int>(idx.begin(), idx.begin() + nl), cl, out);
+    bisect(pos, std::vector<int>(idx.begin() + nl, idx.end()), cl, out);
+}
+
+struct Cluster {
+    std::vector<int> atoms;
+    Vec3 c;
+    double reach;    // max_a |tau_a - c| + rc_a
+};
+
+struct PairOut {
+    GPair pair;
+    std::vector<GBig> bcs;
+};
+
+}  // namespace
+
+int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPlan &hp) {
+    auto fail = [&](int code, const char *msg) {
+        hp.error = msg;
+        return code;
+    };
+    if (!sys) return fail(GINT_EINVAL, "null system");
+    const int cl = (opt && opt->cluster_atoms > 0) ? opt->cluster_atoms : GINT_CL;
+    if (cl < 1 || cl > GINT_CL) return fail(GINT_EINVAL, "cluster_atoms out of range");
+    const int maxbc = (opt && opt->max_bigcells_per_item > 0) ? opt->max_bigcells_per_item : 512;
+    hp.cluster_atoms = cl;
+    if (sys->natom < 1 || !sys->pos || !sys->species) return fail(GINT_EINVAL, "bad atoms");
+    if (sys->nspecies < 1 || sys->nspecies > GINT_MAXSPECIES || !sys->species_list)
+        return fail(GINT_EINVAL, "bad species list");
+    for (int k = 0; k < 3; ++k)
+        if (sys->grid[k] < 1) return fail(GINT_EINVAL, "grid must be positive");
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(sys->cell[k])) return fail(GINT_EINVAL, "non-finite cell");
+
+    Geometry G;
+    std::memcpy(G.cell, sys->cell, sizeof(G.cell));
+    double det;
+    if (!invert3(G.cell, G.inv, &det)) return fail(GINT_EINVAL, "singular cell");
+    for (int i = 0; i < 3; ++i) {
+        G.N[i] = sys->grid[i];
+        G.a[i] = {G.cell[3 * i], G.cell[3 * i + 1], G.cell[3 * i + 2]};
+        G.e[i] = {G.a[i].x / G.N[i], G.a[i].y / G.N[i], G.a[i].z / G.N[i]};
+        const double bx = G.inv[i], by = G.inv[3 + i], bz = G.inv[6 + i];
+        G.spacing[i] = 1.0 / std::sqrt(bx * bx + by * by + bz * bz);
+    }
+    hp.omega = std::fabs(det);
+    hp.ngrid = (long long)G.N[0] * G.N[1] * G.N[2];
+    hp.w = hp.omega / (double)hp.ngrid;
+    std::memcpy(hp.cell, G.cell, sizeof(hp.cell));
+    for (int i = 0; i < 3; ++i) {
+        hp.N[i] = G.N[i];
+        hp.e[i][0] = G.e[i].x; hp.e[i][1] = G.e[i].y; hp.e[i][2] = G.e[i].z;
+    }
+
+    // ---- species and radial tables ([knot][chan][f, f'] interleaved)
+    hp.species.clear();
+    hp.tab.clear();
+    for (int s = 0; s < sys->nspecies; ++s) {
+        const gint_species &sp = sys->species_list[s];
+        if (!(sp.rcut > 0) || !(sp.dr > 0) || sp.nknots < 2 || sp.nchan < 1 || sp.nchan > GINT_MAXCHAN ||
+            !sp.chan_l || !sp.f || !sp.fp || !std::isfinite(sp.rcut) || !std::isfinite(sp.dr))
+            return fail(GINT_EINVAL, "bad species");
+        if ((sp.nknots - 1) * sp.dr < sp.rcut * (1.0 - 1e-12)) return fail(GINT_EINVAL, "table shorter than rcut");
+        GSpecies g{};
+        g.rcut = sp.rcut;
+        g.rcut2 = sp.rcut * sp.rcut;
+        g.dr = sp.dr;
+        g.inv_dr = 1.0 / sp.dr;
+        g.nknots = sp.nknots;
+        g.nchan = sp.nchan;
+        int norb = 0;
+        for (int c = 0; c < sp.nchan; ++c) {
+            if (sp.chan_l[c] < 0) return fail(GINT_EINVAL, "negative l");
+            if (sp.chan_l[c] > 2) return fail(GINT_EUNSUPPORTED, "l > 2 not supported");
+            g.chan_l[c] = sp.chan_l[c];
+            norb += 2 * sp.chan_l[c] + 1;
+        }
+        if (norb > GINT_ORB) return fail(GINT_EUNSUPPORTED, "more than 16 orbitals per atom");
+        g.norb = norb;
+        g.tab_off = (int)hp.tab.size();
+        for (int k = 0; k < sp.nknots; ++k)
+            for (int c = 0; c < sp.nchan; ++c) {
+                const double f = sp.f[(size_t)c * sp.nknots + k], fp = sp.fp[(size_t)c * sp.nknots + k];
+                if (!std::isfinite(f) || !std::isfinite(fp)) return fail(GINT_EINVAL, "non-finite radial table");
+                hp.tab.push_back(f);
+                hp.tab.push_back(fp);
+            }
+        hp.species.push_back(g);
+    }
+    if (hp.tab.size() > (size_t)0x7fffffff) return fail(GINT_EINVAL, "radial tables too large");
+
+    // ---- atoms
+    const int natom = sys->natom;
+    hp.natom = natom;
+    std::vector<Vec3> pos(natom);
+    std::vector<double> rc(natom);
+    std::vector<int> norb(natom);
+    hp.atoms.resize(natom);
+    double rcmax = 0;
+    for (int i = 0; i < natom; ++i) {
+        const int s = sys->species[i];
+        if (s < 0 || s >= sys->nspecies) return fail(GINT_EINVAL, "species index out of range");
+        pos[i] = {sys->pos[3 * i], sys->pos[3 * i + 1], sys->pos[3 * i + 2]};
+        if (!std::isfinite(pos[i].x) || !std::isfinite(pos[i].y) || !std::isfinite(pos[i].z))
+            return fail(GINT_EINVAL, "non-finite position");
+        rc[i] = hp.species[s].rcut;
+        norb[i] = hp.species[s].norb;
+        rcmax = std::max(rcmax, rc[i]);
+        hp.atoms[i] = {pos[i].x, pos[i].y, pos[i].z, s, norb[i]};
+    }
+    if (natom >= (1 << 22)) return fail(GINT_EINVAL, "too many atoms");
+
+    // ---- pattern
+    if (sys->nblk < 0 || (sys->nblk > 0 && (!sys->blk_i || !sys->blk_j || !sys->blk_r || !sys->blk_off)))
+        return fail(GINT_EINVAL, "bad pattern arrays");
+    BlockMap bm;
+    bm.off.reserve((size_t)sys->nblk * 2 + 16);
+    std::vector<std::pair<long long, long long>> spans;
+    spans.reserve(sys->nblk);
+    long long nnz = 0;
+    for (int b = 0; b < sys->nblk; ++b) {
+        const int i = sys->blk_i[b], j = sys->blk_j[b];
+        const int *r = sys->blk_r + 3 * b;
+        if (i < 0 || i >= natom || j < 0 || j >= natom) return fail(GINT_EINVAL, "block atom out of range");
+        if (std::abs(r[0]) >= 2048 || std::abs(r[1]) >= 2048 || std::abs(r[2]) >= 2048)
+            return fail(GINT_EINVAL, "block R out of range");
+        const long long off = sys->blk_off[b];
+        const long long sz = (long long)norb[i] * norb[j];
+        if (off < 0) return fail(GINT_EINVAL, "negative block offset");
+        if (!bm.off.emplace(BlockKey{i, j, r[0], r[1], r[2]}, off).second) return fail(GINT_EINVAL, "duplicate block");
+        spans.push_back({off, off + sz});
+        nnz = std::max(nnz, off + sz);
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return fail(GINT_EINVAL, "overlapping blocks");
+    for (int b = 0; b < sys->nblk; ++b) {
+        const int *r = sys->blk_r + 3 * b;
+        if (bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]) < 0)
+            return fail(GINT_EPATTERN, "pattern is not transpose-closed");
+    }
+    hp.nnz = nnz;
+
+    // ---- clusters
+    std::vector<std::vector<int>> groups;
+    {
+        std::vector<int> all(natom);
+        for (int i = 0; i < natom; ++i) all[i] = i;
+        bisect(pos, all, cl, groups);
+    }
+    std::vector<Cluster> cls(groups.size());
+    for (size_t c = 0; c < groups.size(); ++c) {
+        Cluster &C = cls[c];
+        C.atoms = groups[c];
+        Vec3 m{0, 0, 0};
+        for (int a : C.atoms) m = add(m, pos[a]);
+        m = {m.x / C.atoms.size(), m.y / C.atoms.size(), m.z / C.atoms.size()};
+        C.c = m;
+        C.reach = 0;
+        for (int a : C.atoms) C.reach = std::max(C.reach, std::sqrt(dot(sub(pos[a], m), sub(pos[a], m))) + rc[a]);
+    }
+    hp.ncluster = (int)cls.size();
+
+    // bigcell circumradius: centre at offset 1.5 grid steps, corners at +-1.5
+    double Rb = 0;
+    for (int q = 0; q < 8; ++q) {
+        const Vec3 d = G.point((q & 1) ? 1.5 : -1.5, (q & 2) ? 1.5 : -1.5, (q & 4) ? 1.5 : -1.5);
+        Rb = std::max(Rb, std::sqrt(dot(d, d)));
+    }
+    Rb *= 1.0 + 1e-12;
+    Rb += 1e-12;
+
+    double maxreach = 0;
+    for (auto &C : cls) maxreach = std::max(maxreach, C.reach);
+
+    // ---- cluster pairs: (A, B, T) with A < B, or A == B and T >= 0 lexicographically
+    const int ncl = (int)cls.size();
+    std::vector<std::vector<PairOut>> per_a(ncl);
+    std::atomic<int> next{0};
+    std::atomic<int> err{GINT_OK};
+    auto worker = [&]() {
+        for (;;) {
+            const int A = next.fetch_add(1);
+            if (A >= ncl || err.load() != GINT_OK) break;
+            const Cluster &CA = cls[A];
+            for (int B = A; B < ncl; ++B) {
+                const Cluster &CB = cls[B];
+                const Vec3 dc = sub(CA.c, CB.c);
+                const double reach = CA.reach + CB.reach;
+                int tlo[3], thi[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double u = G.frac(dc, k);
+                    tlo[k] = (int)std::floor(u - reach / G.spacing[k]) - 1;
+                    thi[k] = (int)std::ceil(u + reach / G.spacing[k]) + 1;
+                }
+                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+                    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+                        for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+                            if (A == B && (t0 < 0 || (t0 == 0 && (t1 < 0 || (t1 == 0 && t2 < 0))))) continue;
+                            const Vec3 sh = G.lat(t0, t1, t2);
+                            const Vec3 cb = add(CB.c, sh);
+                            const Vec3 d = sub(CA.c, cb);
+                            if (dot(d, d) >= reach * reach) continue;
+                            // atom pairs and their blocks
+                            PairOut po;
+                            GPair &P = po.pair;
+                            std::memset(&P, 0, sizeof(P));
+                            for (int k = 0; k < GINT_CL; ++k) { P.a[k] = -1; P.b[k] = -1; }
+                            for (size_t k = 0; k < CA.atoms.size(); ++k) P.a[k] = CA.atoms[k];
+                            for (size_t k = 0; k < CB.atoms.size(); ++k) P.b[k] = CB.atoms[k];
+                            P.shiftA[0] = P.shiftA[1] = P.shiftA[2] = 0.0;
+                            P.shiftB[0] = sh.x; P.shiftB[1] = sh.y; P.shiftB[2] = sh.z;
+                            P.self = (A == B && t0 == 0 && t1 == 0 && t2 == 0) ? 1 : 0;
+                            bool any_overlap = false;
+                            for (int ia = 0; ia < GINT_CL; ++ia)
+                                for (int jb = 0; jb < GINT_CL; ++jb) {
+                                    P.hoff[ia * 4 + jb] = -1;
+                                    P.hoff_t[ia * 4 + jb] = -1;
+                                    const int a = P.a[ia], b = P.b[jb];
+                                    if (a < 0 || b < 0) continue;
+                                    const Vec3 dab = sub(pos[a], add(pos[b], sh));
+                                    const bool near = dot(dab, dab) < (rc[a] + rc[b]) * (rc[a] + rc[b]);
+                                    const long long o = bm.find(a, b, t0, t1, t2);
+                                    const long long ot = bm.find(b, a, -t0, -t1, -t2);
+                                    P.hoff[ia * 4 + jb] = o;
+                                    P.hoff_t[ia * 4 + jb] = ot;
+                                    if (near) {
+                                        any_overlap = true;
+                                        if (o < 0 || ot < 0) {
+                                            // missing block: an error only if some grid point lies in both spheres
+                                            const double ra = rc[a], rbb = rc[b];
+                                            const Vec3 pb = add(pos[b], sh);
+                                            long long lo[3], hi[3];
+                                            for (int k = 0; k < 3; ++k) {
+                                                const double u = G.frac(pos[a], k), ext = ra / G.spacing[k];
+                                                lo[k] = (long long)std::floor((u - ext) * G.N[k]) - 1;
+                                                hi[k] = (long long)std::ceil((u + ext) * G.N[k]) + 1;
+                                            }
+                                            bool hit = false;
+                                            for (long long n0 = lo[0]; n0 <= hi[0] && !hit; ++n0)
+                                                for (long long n1 = lo[1]; n1 <= hi[1] && !hit; ++n1)
+                                                    for (long long n2 = lo[2]; n2 <= hi[2] && !hit; ++n2) {
+                                                        const Vec3 r = G.point((double)n0, (double)n1, (double)n2);
+                                                        const Vec3 xa = sub(r, pos[a]), xb = sub(r, pb);
+                                                        if (std::sqrt(dot(xa, xa)) < ra && std::sqrt(dot(xb, xb)) < rbb) hit = true;
+                                                    }
+                                            if (hit) {
+                                                int expected = GINT_OK;
+                                                err.compare_exchange_strong(expected, GINT_EPATTERN);
+                                            }
+                                        }
+                                    }
+                                }
+                            if (!any_overlap) continue;
+                            // bigcells in the intersection of the two clusters' reach
+                            long long blo[3], bhi[3];
+                            for (int k = 0; k < 3; ++k) {
+                                const double ua = G.frac(CA.c, k), ub = G.frac(cb, k);
+                                const double ea = (CA.reach + Rb) / G.spacing[k], eb = (CB.reach + Rb) / G.spacing[k];
+                                const double lo = std::max(ua - ea, ub - eb), hi = std::min(ua + ea, ub + eb);
+                                blo[k] = (long long)std::floor(lo * G.N[k] / GINT_BC) - 1;
+                                bhi[k] = (long long)std::ceil(hi * G.N[k] / GINT_BC) + 1;
+                            }
+                            for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
+                                for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
+                                    for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
+                                        const Vec3 ctr = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, GINT_BC * b2 + 1.5);
+                                        bool ina = false, inb = false;
+                                        for (int a : CA.atoms) {
+                                            const Vec3 x = sub(ctr, pos[a]);
+                                            const double R = rc[a] + Rb;
+                                            if (dot(x, x) < R * R) { ina = true; break; }
+                                        }
+                                        if (!ina) continue;
+                                        for (int b : CB.atoms) {
+                                            const Vec3 x = sub(ctr, add(pos[b], sh));
+                                            const double R = rc[b] + Rb;
+                                            if (dot(x, x) < R * R) { inb = true; break; }
+                                        }
+                                        if (!inb) continue;
+                                        if (std::llabs(b0) > (1LL << 28) || std::llabs(b1) > (1LL << 28) || std::llabs(b2) > (1LL << 28)) {
+                                            int expected = GINT_OK;
+                                            err.compare_exchange_strong(expected, GINT_EINVAL);
+                                            continue;
+                                        }
+                                        po.bcs.push_back({(int)(GINT_BC * b0), (int)(GINT_BC * b1), (int)(GINT_BC * b2), 0});
+                                    }
+                            if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
+                        }
+            }
+        }
+    };
+    unsigned nth = std::thread::hardware_concurrency();
+    if (nth == 0) nth = 4;
+    nth = std::min(nth, 16u);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t) th.emplace_back(worker);
+    for (auto &t : th) t.join();
+    if (err.load() != GINT_OK)
+        return fail(err.load(), err.load() == GINT_EPATTERN ? "an overlapping (I,J,R) block is missing from the pattern"
+                                                            : "grid index out of range");
+
+    // ---- flatten: canonical pairs, then their swapped copies
+    hp.pairs.clear();
+    hp.bigcells.clear();
+    std::vector<std::pair<int, int>> ranges;   // per canonical pair: bigcell begin, count
+    for (int A = 0; A < ncl; ++A)
+        for (auto &po : per_a[A]) {
+            ranges.push_back({(int)hp.bigcells.size(), (int)po.bcs.size()});
+            hp.bigcells.insert(hp.bigcells.end(), po.bcs.begin(), po.bcs.end());
+            hp.pairs.push_back(po.pair);
+            if (hp.bigcells.size() > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
+        }
+    hp.ncanon = (int)hp.pairs.size();
+    std::vector<int> swapped_of(hp.ncanon, -1);
+    for (int p = 0; p < hp.ncanon; ++p) {
+        const GPair &P = hp.pairs[p];
+        if (P.self) continue;
+        GPair S;
+        std::memset(&S, 0, sizeof(S));
+        for (int k = 0; k < GINT_CL; ++k) { S.a[k] = P.b[k]; S.b[k] = P.a[k]; }
+        for (int k = 0; k < 3; ++k) { S.shiftA[k] = P.shiftB[k]; S.shiftB[k] = P.shiftA[k]; }
+        S.self = 0;
+        for (int i = 0; i < GINT_CL; ++i)
+            for (int j = 0; j < GINT_CL; ++j) {
+                S.hoff[i * 4 + j] = P.hoff_t[j * 4 + i];
+                S.hoff_t[i * 4 + j] = P.hoff[j * 4 + i];
+            }
+        swapped_of[p] = (int)hp.pairs.size();
+        hp.pairs.push_back(S);
+    }
+
+    // ---- work items: runs of at most maxbc bigcells, longest first
+    hp.items_canon.clear();
+    hp.items_ordered.clear();
+    for (int p = 0; p < hp.ncanon; ++p) {
+        const int beg = ranges[p].first, cnt = ranges[p].second;
+        const int nchunk = (cnt + maxbc - 1) / maxbc;
+        for (int c = 0; c < nchunk; ++c) {
+            const int b0 = beg + (int)((long long)cnt * c / nchunk);
+            const int b1 = beg + (int)((long long)cnt * (c + 1) / nchunk);
+            hp.items_canon.push_back({p, b0, b1 - b0, 0});
+            hp.items_ordered.push_back({p, b0, b1 - b0, 0});
+            if (swapped_of[p] >= 0) hp.items_ordered.push_back({swapped_of[p], b0, b1 - b0, 0});
+        }
+    }
+    auto longer = [](const GItem &x, const GItem &y) {
+        if (x.bc_count != y.bc_count) return x.bc_count > y.bc_count;
+        if (x.pair != y.pair) return x.pair < y.pair;
+        return x.bc_begin < y.bc_begin;
+    };
+    std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
+    std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
+    return GINT_OK;
+}

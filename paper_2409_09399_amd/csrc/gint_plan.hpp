@@ -1,0 +1,35 @@
+// Host-side plan builder: sub-task division and descriptor generation
+// (paper: "Computational Collaboration Between Host and Device" — grid
+// batches plus their neighbouring atoms, with the GEMM descriptors stored
+// contiguously by integer index).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "gint.h"
+#include "gint_internal.h"
+
+struct HostPlan {
+    std::vector<GSpecies> species;
+    std::vector<GAtom> atoms;
+    std::vector<double> tab;
+    std::vector<GPair> pairs;        // [0, ncanon): canonical; [ncanon, ..): swapped copies
+    std::vector<GBig> bigcells;
+    std::vector<GItem> items_canon;  // canonical pairs, longest first
+    std::vector<GItem> items_ordered;// canonical + swapped, longest first
+    int ncanon = 0;
+    int ncluster = 0;
+    int natom = 0;
+    int N[3] = {0, 0, 0};
+    double cell[9] = {0};
+    double e[3][3] = {{0}};
+    double omega = 0.0;
+    double w = 0.0;
+    long long nnz = 0;
+    long long ngrid = 0;
+    int cluster_atoms = GINT_CL;
+    std::string error;
+};
+
+// Returns GINT_OK or a negative gint error code (hp.error holds a message).
+int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPlan &hp);

@@ -1,0 +1,225 @@
+"""Thin ctypes binding of libgint.so (include/gint.h).
+
+Argument marshalling only: every step of grid integration runs in the HIP
+library.  PyTorch supplies device memory and the current stream.  There is no
+CPU fallback: if the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgint.so")
+
+GINT_OK, GINT_EINVAL, GINT_EPATTERN, GINT_ENOMEM, GINT_EHIP, GINT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+GINT_FP64 = 0
+
+
+class GintError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = _lib.gint_strerror(code).decode() if _lib is not None else str(code)
+        if code == GINT_EHIP:
+            msg += f" (hip error {_lib.gint_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]" if what else f"{msg} [{code}]")
+
+
+class gint_species(C.Structure):
+    _fields_ = [("rcut", C.c_double), ("dr", C.c_double), ("nknots", C.c_int), ("nchan", C.c_int),
+                ("chan_l", C.c_void_p), ("f", C.c_void_p), ("fp", C.c_void_p)]
+
+
+class gint_system(C.Structure):
+    _fields_ = [("cell", C.c_double * 9), ("natom", C.c_int), ("pos", C.c_void_p), ("species", C.c_void_p),
+                ("nspecies", C.c_int), ("species_list", C.c_void_p), ("grid", C.c_int * 3),
+                ("nblk", C.c_int), ("blk_i", C.c_void_p), ("blk_j", C.c_void_p), ("blk_r", C.c_void_p),
+                ("blk_off", C.c_void_p)]
+
+
+class gint_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("cluster_atoms", C.c_int), ("max_bigcells_per_item", C.c_int),
+                ("reserved", C.c_int * 5)]
+
+
+class gint_sizes(C.Structure):
+    _fields_ = [("ngrid", C.c_int64), ("nnz", C.c_int64), ("natom", C.c_int), ("ncluster", C.c_int),
+                ("npairs", C.c_int64), ("nitems", C.c_int64), ("nbigcells", C.c_int64),
+                ("work_units", C.c_double), ("volume", C.c_double), ("device_bytes", C.c_int64),
+                ("build_seconds", C.c_double)]
+
+
+EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
+            "gint_plan_query", "gint_plan_destroy", "gint_strerror", "gint_last_hip_error"]
+
+
+def _hip_runtimes():
+    """Files of libamdhip64 mapped into this process."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                p = line.split()[-1] if line.strip() else ""
+                if "libamdhip64.so" in os.path.basename(p):
+                    found.add(os.path.realpath(p))
+    except OSError:
+        pass
+    return found
+
+
+def _load():
+    # PyTorch-ROCm ships its own HIP runtime (soname libamdhip64.so.7).  Load
+    # it first so that libgint.so binds to the same runtime that owns the
+    # tensors and streams it is handed; two runtimes in one process do not
+    # share devices, memory or streams.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+    lib = C.CDLL(LIB_PATH)
+    rts = _hip_runtimes()
+    if len(rts) > 1:
+        raise ImportError(f"two HIP runtimes are loaded ({sorted(rts)}); libgint.so must share torch's")
+    P = C.c_void_p
+    lib.gint_plan_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(gint_system), C.c_int,
+                                     C.POINTER(gint_options), P]
+    lib.gint_plan_create.restype = C.c_int
+    for name in ("gint_vlocal",):
+        getattr(lib, name).argtypes = [P, P, P, P]
+    lib.gint_rho.argtypes = [P, P, P, P, P]
+    lib.gint_force_stress.argtypes = [P, P, P, P, P, P, P]
+    lib.gint_work_units.argtypes = [P, P, P]
+    lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
+    lib.gint_plan_destroy.argtypes = [P]
+    lib.gint_plan_destroy.restype = None
+    lib.gint_strerror.argtypes = [C.c_int]
+    lib.gint_strerror.restype = C.c_char_p
+    lib.gint_last_hip_error.argtypes = []
+    for name in EXPORTED:
+        if name not in ("gint_plan_destroy", "gint_strerror"):
+            getattr(lib, name).restype = C.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int, what: str):
+    if rc != GINT_OK:
+        raise GintError(rc, what)
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev_ptr(t, n: int, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A gint plan for one system (paper_2409_09399_amd.inputs.System or any
+    object with the same fields), built on the current HIP device."""
+
+    def __init__(self, system, cluster_atoms: int = 0, max_bigcells_per_item: int = 0,
+                 precision: int = GINT_FP64, stream=None):
+        s = system
+        keep = []
+
+        def arr(x, dt):
+            a = np.ascontiguousarray(np.asarray(x), dtype=dt)
+            keep.append(a)
+            return a.ctypes.data_as(C.c_void_p)
+
+        sps = (gint_species * len(s.species_list))()
+        for k, sp in enumerate(s.species_list):
+            sps[k].rcut = sp.rcut
+            sps[k].dr = sp.dr
+            sps[k].nknots = sp.nknots
+            sps[k].nchan = sp.nchan
+            sps[k].chan_l = arr(sp.ls, np.int32)
+            sps[k].f = arr(sp.f, np.float64)
+            sps[k].fp = arr(sp.fp, np.float64)
+        st = gint_system()
+        cell = np.ascontiguousarray(s.cell, dtype=np.float64).ravel()
+        for k in range(9):
+            st.cell[k] = float(cell[k])
+        st.natom = int(s.pos.shape[0])
+        st.pos = arr(s.pos, np.float64)
+        st.species = arr(s.species, np.int32)
+        st.nspecies = len(s.species_list)
+        st.species_list = C.cast(sps, C.c_void_p)
+        for k in range(3):
+            st.grid[k] = int(s.grid[k])
+        st.nblk = int(s.blk_i.shape[0])
+        st.blk_i = arr(s.blk_i, np.int32)
+        st.blk_j = arr(s.blk_j, np.int32)
+        st.blk_r = arr(s.blk_r, np.int32)
+        st.blk_off = arr(s.blk_off, np.int64)
+        opt = gint_options()
+        opt.precision = precision
+        opt.cluster_atoms = cluster_atoms
+        opt.max_bigcells_per_item = max_bigcells_per_item
+        ptr = C.c_void_p()
+        rc = _lib.gint_plan_create(C.byref(ptr), C.byref(st), 1, C.byref(opt),
+                                   _stream(stream) if stream is not None else None)
+        _check(rc, "gint_plan_create")
+        self._p = ptr
+        q = gint_sizes()
+        _check(_lib.gint_plan_query(self._p, C.byref(q)), "gint_plan_query")
+        self.sizes = q
+        self.natom = int(q.natom)
+        self.ngrid = int(q.ngrid)
+        self.nnz = int(q.nnz)
+        self.volume = float(q.volume)
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.gint_plan_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        q = self.sizes
+        return {f: getattr(q, f) for f, _ in gint_sizes._fields_}
+
+
+def gint_vlocal(plan: Plan, v_loc, h_vals, stream=None):
+    _check(_lib.gint_vlocal(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"), _dev_ptr(h_vals, plan.nnz, "h_vals"),
+                            _stream(stream)), "gint_vlocal")
+
+
+def gint_rho(plan: Plan, d_vals, rho, n_elec=None, stream=None):
+    ne = _dev_ptr(n_elec, 1, "n_elec") if n_elec is not None else None
+    _check(_lib.gint_rho(plan._p, _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(rho, plan.ngrid, "rho"), ne,
+                         _stream(stream)), "gint_rho")
+
+
+def gint_force_stress(plan: Plan, v_loc, d_vals, force, stress, energy=None, stream=None):
+    en = _dev_ptr(energy, 1, "energy") if energy is not None else None
+    _check(_lib.gint_force_stress(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"),
+                                  _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(force, 3 * plan.natom, "force"),
+                                  _dev_ptr(stress, 9, "stress"), en, _stream(stream)), "gint_force_stress")
+
+
+def gint_work_units(plan: Plan, w_out, stream=None):
+    _check(_lib.gint_work_units(plan._p, _dev_ptr(w_out, 1, "w_out"), _stream(stream)), "gint_work_units")

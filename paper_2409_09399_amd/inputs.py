@@ -317,12 +317,16 @@ def frac_grid(grid) -> np.ndarray:
 
 
 def plane_wave_potential(grid, millers: np.ndarray, amps: np.ndarray, phases: np.ndarray) -> np.ndarray:
-    """V(s_g) = sum_k amp_k cos(2 pi m_k . s_g + phase_k) on the fractional grid."""
-    s = frac_grid(grid)
-    v = np.zeros(s.shape[0])
+    """V(s_g) = sum_k amp_k cos(2 pi m_k . s_g + phase_k) on the fractional
+    grid s_g = n/N, evaluated as the real part of one inverse FFT of the
+    sparse coefficient array (the Miller indices must be distinct)."""
+    n = tuple(int(x) for x in grid)
+    coef = np.zeros(n, dtype=np.complex128)
     for m, a, p in zip(millers, amps, phases):
-        v += a * np.cos(2.0 * np.pi * (s @ m) + p)
-    return v
+        idx = tuple(int(m[k]) % n[k] for k in range(3))
+        coef[idx] += a * np.exp(1j * p)
+    v = np.fft.ifftn(coef).real * float(np.prod(n))
+    return np.ascontiguousarray(v.ravel())
 
 
 def random_millers_box(rng, n_waves: int, mmax: int) -> np.ndarray:
