@@ -284,11 +284,12 @@ __device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const
         }
     }
     __builtin_amdgcn_wave_barrier();
-    double *dst = phiB + (16 * w + 4 * (lane >> 4)) * PSTR + (lane & 15);
+    // FP64 16x16x4 result layout: lane l, register q holds row 4q + (l >> 4), column l & 15
+    double *dst = phiB + (16 * w + (lane >> 4)) * PSTR + (lane & 15);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q * PSTR + i * GINT_ORB] = acc[i][q];
+        for (int q = 0; q < 4; ++q) dst[4 * q * PSTR + i * GINT_ORB] = acc[i][q];
 }
 
 }  // namespace
@@ -326,7 +327,7 @@ __global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict
         }
         __syncthreads();
     }
-    // tile (a_w, b_j): lane holds rows mu = 4 (lane >> 4) + q, column nu = lane & 15
+    // tile (a_w, b_j): lane l, register q holds row mu = 4 q + (l >> 4), column nu = l & 15
     const int ai = pr.a[w];
     if (ai < 0) return;
     const int na = P.atoms[ai].norb;
@@ -339,7 +340,7 @@ __global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict
         const long long o = pr.hoff[w * 4 + j], ot = pr.hoff_t[w * 4 + j];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int mu = 4 * (lane >> 4) + q;
+            const int mu = 4 * q + (lane >> 4);
             if (mu >= na || nu >= nb) continue;
             const double v = acc[j][q];
             if (o >= 0) atomicAdd(H + o + (long long)mu * nb + nu, v);
