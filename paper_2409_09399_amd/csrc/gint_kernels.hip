@@ -265,31 +265,34 @@ __device__ inline void load_dsym(const GDev &P, const GPair &pr, const double *_
 
 // Phase 2 of rho/force: wave w computes psi[pt][a_i][mu] = sum_{b_j, nu}
 // phi_B[pt][b_j][nu] D_sym[a_i mu][b_j nu] for its 16 points and writes it
-// over its own rows of phiB (no other wave reads those rows).
+// over its own rows of phiB (no other wave reads those rows).  All operand
+// reads are issued before the MFMAs; each B-atom operand feeds all 4 A atoms.
 __device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const unsigned *maskpt) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     unsigned gm = or16(maskpt[16 * w + (lane & 15)]);
     gm = __builtin_amdgcn_readfirstlane(gm);
-    d4 acc[4];
+    const double *base = phiB + (16 * w + (lane & 15)) * PSTR + (lane >> 4);
+    double src[4][4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        acc[i] = (d4){0.0, 0.0, 0.0, 0.0};
-        if (!(gm & (1u << i))) continue;
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (!(gm & (1u << (4 + j)))) continue;
-            const double *src = phiB + (16 * w + (lane & 15)) * PSTR + j * GINT_ORB + (lane >> 4);
-#pragma unroll
-            for (int s = 0; s < 4; ++s) acc[i] = mfma64(src[4 * s], dreg[i][j][s], acc[i]);
-        }
-    }
+        for (int s = 0; s < 4; ++s) src[j][s] = base[j * GINT_ORB + 4 * s];
     __builtin_amdgcn_wave_barrier();
     // FP64 16x16x4 result layout: lane l, register q holds row 4q + (l >> 4), column l & 15
     double *dst = phiB + (16 * w + (lane >> 4)) * PSTR + (lane & 15);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+        if (!(gm & (1u << i))) continue;   // psi of an inactive A atom is never read
+        d4 c = (d4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[4 * q * PSTR + i * GINT_ORB] = acc[i][q];
+        for (int j = 0; j < 4; ++j) {
+            if (!(gm & (1u << (4 + j)))) continue;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c = mfma64(src[j][s], dreg[i][j][s], c);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[4 * q * PSTR + i * GINT_ORB] = c[q];
+    }
 }
 
 }  // namespace
@@ -314,16 +317,40 @@ __global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict
         __syncthreads();
         stage<1>(P, pr, o, V, phiA, phiB, maskpt);
         __syncthreads();
-        // wave w owns row atom a_w; k-steps of 4 points along the third axis
-        for (int s = 0; s < 16; ++s) {
-            unsigned m = maskpt[4 * s] | maskpt[4 * s + 1] | maskpt[4 * s + 2] | maskpt[4 * s + 3];
-            m = __builtin_amdgcn_readfirstlane(m);
-            if (!(m & (1u << w))) continue;
-            const int row = (4 * s + (lane >> 4)) * PSTR + (lane & 15);
-            const double a = phiA[row + w * GINT_ORB];
+        // wave w owns row atom a_w; k-steps of 4 points along the third axis.
+        // Activity of every k-step comes from one ballot per atom; only k-steps
+        // where a_w is active are visited, two at a time with their operand
+        // reads issued before the MFMAs.
+        {
+            const unsigned mp = maskpt[lane];
+            unsigned mk = mp | __shfl_xor(mp, 1);
+            mk |= __shfl_xor(mk, 2);
+            unsigned long long rowk = __ballot(mk & (1u << w)) & 0x1111111111111111ull;
+            unsigned long long colk[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (m & (1u << (4 + j))) acc[j] = mfma64(a, phiB[row + j * GINT_ORB], acc[j]);
+            for (int j = 0; j < 4; ++j) colk[j] = __ballot(mk & (1u << (4 + j)));
+            const double *pa = phiA + (lane >> 4) * PSTR + w * GINT_ORB + (lane & 15);
+            const double *pb = phiB + (lane >> 4) * PSTR + (lane & 15);
+            // one tile at a time over the k-steps where both atoms are active;
+            // two independent accumulator chains, the odd tail is a zero operand
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                unsigned long long m = rowk & colk[j];
+                const double *pbj = pb + j * GINT_ORB;
+                d4 c0 = acc[j], c1 = (d4){0.0, 0.0, 0.0, 0.0};
+                while (m) {
+                    const int s0 = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const int s1 = m ? __builtin_ctzll(m) : s0;
+                    const double z = m ? 1.0 : 0.0;
+                    m &= m - 1;
+                    const double a0 = pa[s0 * PSTR], b0 = pbj[s0 * PSTR];
+                    const double a1 = pa[s1 * PSTR], b1 = pbj[s1 * PSTR] * z;
+                    c0 = mfma64(a0, b0, c0);
+                    c1 = mfma64(a1, b1, c1);
+                }
+                acc[j] = c0 + c1;
+            }
         }
         __syncthreads();
     }
