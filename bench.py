@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
+PEAK_FP16_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 matrix
+PRECISIONS = {"fp64": 0, "fp16x3": 1, "bf16x3": 2}
 
 
 def log(msg):
@@ -60,6 +62,19 @@ def cpu_baseline(system, target_seconds: float = 15.0):
             "seconds": dt}
 
 
+def workload_name(cfg, systems, precision):
+    s = systems[0]
+    if cfg == 3:
+        return (f"batch of {len(systems)} random C/H/O crystals ({min(x.natom for x in systems)}-"
+                f"{max(x.natom for x in systems)} atoms, 13/5/13 orbitals, rcut 7/6/8 Bohr, grids "
+                f"{min(int(x.grid[0]) for x in systems)}^3-{max(int(x.grid[0]) for x in systems)}^3), "
+                f"{precision} path")
+    if cfg == 1:
+        return f"jittered diamond, 8 C atoms, grid 32^3, 13 orbitals/atom, rcut 6 Bohr, {precision} path"
+    return (f"twisted bilayer graphene ({s.natom} C atoms), grid {'x'.join(str(int(x)) for x in s.grid)}, "
+            f"13 orbitals/atom, rcut 8 Bohr, {precision} path")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,6 +85,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cluster-atoms", type=int, default=0)
     ap.add_argument("--max-bigcells", type=int, default=0)
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp64")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -81,27 +97,35 @@ def main():
     from paper_2409_09399_amd import inputs as I
 
     dev = torch.device("cuda:0")
+    prec = PRECISIONS[args.precision]
     t = time.perf_counter()
-    s = I.make_config(args.config)
-    log(f"[bench] inputs {s.name}: natom={s.natom} grid={tuple(int(x) for x in s.grid)} nnz={s.nnz} "
+    cfg = I.make_config(args.config)
+    systems = cfg if isinstance(cfg, list) else [cfg]
+    s = systems[0]
+    natom = sum(x.natom for x in systems)
+    ngrid = sum(x.ngrid for x in systems)
+    nnz = sum(x.nnz for x in systems)
+    log(f"[bench] inputs {len(systems)} system(s), first {s.name}: natom={natom} ngrid={ngrid} nnz={nnz} "
         f"({time.perf_counter() - t:.1f} s)")
     t = time.perf_counter()
-    plan = G.Plan(s, cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells)
+    plan = G.Plan(systems if len(systems) > 1 else s, cluster_atoms=args.cluster_atoms,
+                  max_bigcells_per_item=args.max_bigcells, precision=prec)
     plan_s = time.perf_counter() - t
     log(f"[bench] plan {plan.info()} wall {plan_s:.2f} s")
+    n = plan.n_sys
 
-    v = torch.tensor(s.v, device=dev)
-    d = torch.tensor(s.d, device=dev)
-    h = torch.empty(s.nnz, dtype=torch.float64, device=dev)
-    rho = torch.empty(s.ngrid, dtype=torch.float64, device=dev)
-    ne = torch.empty(1, dtype=torch.float64, device=dev)
-    F = torch.empty(3 * s.natom, dtype=torch.float64, device=dev)
-    sig = torch.empty(9, dtype=torch.float64, device=dev)
-    E = torch.empty(1, dtype=torch.float64, device=dev)
-    Wt = torch.empty(1, dtype=torch.float64, device=dev)
+    v = torch.tensor(np.concatenate([x.v for x in systems]), device=dev)
+    d = torch.tensor(np.concatenate([x.d for x in systems]), device=dev)
+    h = torch.empty(nnz, dtype=torch.float64, device=dev)
+    rho = torch.empty(ngrid, dtype=torch.float64, device=dev)
+    ne = torch.empty(n, dtype=torch.float64, device=dev)
+    F = torch.empty(3 * natom, dtype=torch.float64, device=dev)
+    sig = torch.empty(9 * n, dtype=torch.float64, device=dev)
+    E = torch.empty(n, dtype=torch.float64, device=dev)
+    Wt = torch.empty(n, dtype=torch.float64, device=dev)
     G.gint_work_units(plan, Wt)
     torch.cuda.synchronize()
-    W = float(Wt.cpu()[0])
+    W = float(Wt.cpu().sum())
     log(f"[bench] W = {W:.6g}")
 
     stream = torch.cuda.current_stream()
@@ -141,16 +165,17 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     value = W * args.steps / elapsed
 
-    # dominant kernel against the FP64 roofline: 2 flops per unit of W
+    # dominant kernel against its contraction roofline: 2 flops per unit of W
     dom = max(kern_ms, key=kern_ms.get)
+    peak = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP16_TFLOPS
     achieved = 2.0 * W / (kern_ms[dom] * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None}
+    roofline = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
 
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
-        cpu = cpu_baseline(s, args.cpu_seconds)
+        cpu = cpu_baseline(s, args.cpu_seconds)   # first system of a batch
         log(f"[bench] cpu baseline {cpu}")
         cpu.pop("seconds", None)
 
@@ -165,11 +190,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {0: "f64", 1: "f16x3 (f32 acc)", 2: "bf16x3 (f32 acc)"}[prec],
         "data": "synthetic",
-        "config": {"workload": f"twisted bilayer graphene i=8 ({s.natom} C atoms, 3.89 deg), "
-                               f"grid {'x'.join(str(int(x)) for x in s.grid)}, 13 orbitals/atom, rcut 8 Bohr, "
-                               f"FP64 path", "W": W, "natom": s.natom, "ngrid": s.ngrid, "nnz": s.nnz},
+        "config": {"workload": workload_name(args.config, systems, args.precision), "W": W, "natom": natom,
+                   "ngrid": ngrid, "nnz": nnz, "n_sys": n},
         "kernel_ms": kern_ms,
         "plan_seconds": plan_s,
         "roofline": roofline,

@@ -58,7 +58,10 @@ enum {
 };
 
 enum {
-    GINT_FP64 = 0            /* plain path: FP64 orbitals, FP64 MFMA contractions */
+    GINT_FP64 = 0,           /* plain path: FP64 orbitals, FP64 MFMA contractions */
+    GINT_MIXED_FP16X3 = 1,   /* FP32 orbitals; FP16 hi+lo split operands, 3 FP16 MFMA products,
+                                FP32 accumulation per bigcell, FP64 across bigcells and for E, N_e */
+    GINT_MIXED_BF16X3 = 2    /* as GINT_MIXED_FP16X3 with BF16 hi+lo splits (wider range, ~16 bits) */
 };
 
 typedef struct gint_plan gint_plan;
@@ -98,7 +101,7 @@ typedef struct {
 
 /* Plan options; pass NULL for defaults. */
 typedef struct {
-    int precision;           /* GINT_FP64 */
+    int precision;           /* GINT_FP64, GINT_MIXED_FP16X3 or GINT_MIXED_BF16X3 */
     int cluster_atoms;       /* atoms per cluster tile, 1..4 (0 = default 4) */
     int max_bigcells_per_item; /* work-item length cap (0 = default) */
     int reserved[5];
@@ -116,40 +119,108 @@ typedef struct {
     double work_units;       /* W = sum_g n_orb(g)^2 (0 unless computed) */
     double volume;           /* Omega */
     int64_t device_bytes;    /* device memory held by the plan */
+    int precision;           /* the plan's precision form */
     double build_seconds;    /* host time of gint_plan_create */
+    int n_sys;               /* systems in the plan (packed buffers when > 1) */
 } gint_sizes;
 
-/* Build a plan for n_sys systems (n_sys == 1 in this version): validates
- * the inputs, groups atoms into clusters, enumerates cluster-image pairs and
- * the bigcells (4x4x4 grid points) where their orbitals overlap, maps every
- * overlapping atom pair to its pattern block (paper: sub-task division and
- * sub-task descriptors, "Computational Collaboration Between Host and
- * Device"), and uploads the descriptors to the current device.  Synchronous.
- * On success *out owns device memory until gint_plan_destroy. */
+/* Where system i of a plan lives in the packed buffers (host struct filled by
+ * gint_plan_query_system).  For a single-system plan every offset is 0. */
+typedef struct {
+    int64_t g_off;           /* first element of the system in v_loc / rho */
+    int64_t ngrid;           /* its N1 N2 N3 */
+    int64_t nnz_off;         /* first element in h_vals / d_vals */
+    int64_t nnz;
+    int atom_off;            /* first atom (row) in force */
+    int natom;
+    int grid[3];
+    double volume;
+} gint_system_sizes;
+
+/* Build a plan for n_sys >= 1 systems: validates the inputs, groups atoms
+ * into clusters, enumerates cluster-image pairs and the bigcells (4x4x4 grid
+ * points) where their orbitals overlap, maps every overlapping atom pair to
+ * its pattern block (paper: sub-task division and sub-task descriptors,
+ * "Computational Collaboration Between Host and Device"), and uploads the
+ * descriptors to the current device.  Synchronous.  With n_sys > 1 the
+ * systems' work items form one queue served by one persistent launch per
+ * call, and every data array is packed: system i occupies the slice given by
+ * gint_plan_query_system (v_loc, rho: grid points; h_vals, d_vals: block
+ * elements; force: atoms), and the scalar outputs n_elec, energy and
+ * w_out hold n_sys values, stress n_sys 3x3 matrices.  Each system keeps its
+ * own cell, grid, species and pattern.  On success *out owns device memory
+ * until gint_plan_destroy. */
 int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys,
                      const gint_options *opt, void *stream);
 
 /* H_IJR (Eq. 2) for every block of the pattern.  v_loc: device f64[N_g].
- * h_vals: device f64[nnz], overwritten (blocks with no overlap become 0). */
+ * h_vals: device f64[nnz], overwritten (blocks with no overlap become 0).
+ * (N_g, nnz, natom below: the plan's totals over its systems.) */
 int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream);
 
 /* rho_g (Eq. 3).  d_vals: device f64[nnz].  rho: device f64[N_g], overwritten.
- * n_elec: device f64[1] receiving sum_g w rho_g, or NULL. */
+ * n_elec: device f64[n_sys] receiving sum_g w rho_g per system, or NULL. */
 int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, void *stream);
 
 /* Grid Pulay force and stress (Eq. 4-5).  force: device f64[natom][3],
- * F_K = -dE/dtau_K.  stress: device f64[3][3], sigma = -Z/Omega with
- * Z_ab = dE/d(eps_ab) at fixed w (unsymmetrised).  energy: device f64[1]
- * receiving E = sum_g w V_g rho_g, or NULL.  All outputs overwritten. */
+ * F_K = -dE/dtau_K.  stress: device f64[n_sys][3][3], sigma = -Z/Omega with
+ * Z_ab = dE/d(eps_ab) at fixed w (unsymmetrised).  energy: device
+ * f64[n_sys] receiving E = sum_g w V_g rho_g, or NULL.  All outputs
+ * overwritten. */
 int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals,
                       double *force, double *stress, double *energy, void *stream);
 
 /* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
  * the unit of work of the throughput metric, counted exactly from the plan's
- * neighbour lists.  w_out: device f64[1], overwritten. */
+ * neighbour lists.  w_out: device f64[n_sys], overwritten. */
 int gint_work_units(gint_plan *p, double *w_out, void *stream);
 
+/* One full step captured into a HIP graph (paper: device work launched with
+ * few host interactions, "Computational Collaboration Between Host and
+ * Device"; replay removes the per-call launch overhead, which dominates for
+ * batches of small structures).  The graph enqueues, in this order,
+ * gint_vlocal (if h_vals), gint_rho (if rho) and gint_force_stress (if
+ * force; stress must then be given too) with exactly these device buffers;
+ * it is captured on a private stream and nothing runs until
+ * gint_graph_launch.  The buffers and the plan must outlive the graph.  A
+ * replay overwrites the outputs like the eager calls.  Replays of graphs of
+ * one plan share its workspace: they must be serialised (one stream, or
+ * events), as eager calls on one plan must.  The graph is bound to the
+ * plan's device (GINT_EINVAL if another device is current). */
+typedef struct gint_graph gint_graph;
+int gint_graph_create(gint_graph **out, gint_plan *p, const double *v_loc, const double *d_vals,
+                      double *h_vals, double *rho, double *n_elec, double *force, double *stress,
+                      double *energy);
+/* Enqueue one replay on `stream` (NULL = default stream). */
+int gint_graph_launch(gint_graph *g, void *stream);
+void gint_graph_destroy(gint_graph *g);
+
+/* Autotuner of the tile shape (paper: short timed trials pick the kernel
+ * parameters, "Performance Evaluation").  Candidates of (cluster_atoms,
+ * max_bigcells_per_item) are tried in a fixed order; for each a plan is
+ * built and one full step (Vlocal, rho, force/stress on constant V and D in
+ * scratch buffers the tuner allocates and frees) is timed with HIP events on
+ * `stream`.  No new candidate starts once budget_seconds of wall time have
+ * passed (the first always runs).  On input opt->precision selects the form;
+ * on success opt->cluster_atoms and opt->max_bigcells_per_item hold the
+ * fastest candidate and *report every trial.  Synchronous. */
+#define GINT_TUNE_MAX 16
+typedef struct {
+    int ntrials;                         /* candidates timed */
+    int best;                            /* index of the chosen one */
+    int cluster_atoms[GINT_TUNE_MAX];
+    int max_bigcells_per_item[GINT_TUNE_MAX];
+    double step_ms[GINT_TUNE_MAX];       /* one Vlocal + rho + force/stress pass */
+    double seconds;                      /* wall time of the search */
+} gint_tune_report;
+int gint_autotune(const gint_system *sys, int n_sys, gint_options *opt, double budget_seconds,
+                  void *stream, gint_tune_report *report);
+
+/* Totals of a plan.  GINT_EINVAL on NULL arguments. */
 int gint_plan_query(const gint_plan *p, gint_sizes *out);
+/* Offsets and sizes of system i (0 <= i < n_sys) in the packed buffers.
+ * GINT_EINVAL if i is out of range. */
+int gint_plan_query_system(const gint_plan *p, int i, gint_system_sizes *out);
 void gint_plan_destroy(gint_plan *p);
 const char *gint_strerror(int code);
 /* Last HIP error code recorded by a failing call (0 if none). */

@@ -15,15 +15,21 @@ hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStre
 hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s);
 hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, hipStream_t s);
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s);
-hipError_t gint_launch_sum(const double *x, long long n, double scale, double *part, int nparts, double *out,
-                           hipStream_t s);
-hipError_t gint_launch_finish_stress(const double *ZE, double inv_omega, double *stress, double *energy,
+hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
+                               hipStream_t s);
+hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
                                      hipStream_t s);
+void gint_prime_grids_fp64();
+void gint_prime_grids_mx(int prec);
+hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, double *H, hipStream_t s);
+hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s);
+hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
+                                hipStream_t s);
 
 namespace {
 
 thread_local int g_last_hip = 0;
-constexpr int kParts = 1024;
+constexpr int kParts = 256;   // partial sums per system for N_e
 
 struct DevBuf {
     void *p = nullptr;
@@ -36,9 +42,13 @@ struct gint_plan {
     int device = 0;
     GDev canon{};      // canonical items (vlocal, rho, work)
     GDev ordered{};    // canonical + swapped items (force)
-    DevBuf species, atoms, tab, pairs, bigcells, items_canon, items_ordered, ws;
-    double *ZE = nullptr;      // [10]: Z (9) and E
-    double *part = nullptr;    // [kParts]
+    DevBuf species, atoms, tab, tab32, pairs, bigcells, items_canon, items_ordered, sys, ws;
+    int precision = GINT_FP64;
+    int n_sys = 1;
+    int *counter = nullptr;    // work counter of the persistent launches
+    double *ZE = nullptr;      // [n_sys][10]: Z (9) and E
+    double *part = nullptr;    // [n_sys][kParts]
+    std::vector<GSys> sys_host;
     gint_sizes sizes{};
 };
 
@@ -68,8 +78,8 @@ int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
 }
 
 void release(gint_plan *p) {
-    DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->pairs, &p->bigcells, &p->items_canon, &p->items_ordered,
-                      &p->ws};
+    DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->tab32, &p->pairs, &p->bigcells, &p->items_canon,
+                      &p->items_ordered, &p->sys, &p->ws};
     for (DevBuf *b : bufs)
         if (b->p) {
             (void)hipFree(b->p);
@@ -83,14 +93,14 @@ extern "C" {
 
 int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const gint_options *opt, void *stream) {
     (void)stream;
-    if (!out || !sys) return GINT_EINVAL;
-    if (n_sys != 1) return n_sys < 1 ? GINT_EINVAL : GINT_EUNSUPPORTED;
-    if (opt && opt->precision != GINT_FP64) return GINT_EUNSUPPORTED;
+    if (!out || !sys || n_sys < 1) return GINT_EINVAL;
+    const int prec = opt ? opt->precision : GINT_FP64;
+    if (prec != GINT_FP64 && prec != GINT_MIXED_FP16X3 && prec != GINT_MIXED_BF16X3) return GINT_EUNSUPPORTED;
     const auto t0 = std::chrono::steady_clock::now();
     HostPlan hp;
     int rc;
     try {
-        rc = gint_build_host_plan(sys, opt, hp);
+        rc = gint_build_host_plan(sys, n_sys, opt, hp);
     } catch (const std::bad_alloc &) {
         return GINT_ENOMEM;
     } catch (...) {
@@ -107,24 +117,38 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         return hip_fail(e);
     }
     size_t total = 0;
-    std::vector<double> wsinit(10 + kParts, 0.0);
+    // workspace: [0] work counter (an int in the first 4 bytes), then ZE, then partial sums
+    std::vector<double> wsinit(1 + (size_t)n_sys * (10 + kParts), 0.0);
     if ((rc = upload(p->species, hp.species, total)) || (rc = upload(p->atoms, hp.atoms, total)) ||
-        (rc = upload(p->tab, hp.tab, total)) || (rc = upload(p->pairs, hp.pairs, total)) ||
+        (rc = upload(p->tab, hp.tab, total)) || (rc = upload(p->tab32, hp.tab32, total)) ||
+        (rc = upload(p->pairs, hp.pairs, total)) ||
         (rc = upload(p->bigcells, hp.bigcells, total)) || (rc = upload(p->items_canon, hp.items_canon, total)) ||
-        (rc = upload(p->items_ordered, hp.items_ordered, total)) || (rc = upload(p->ws, wsinit, total))) {
+        (rc = upload(p->items_ordered, hp.items_ordered, total)) || (rc = upload(p->sys, hp.sys, total)) ||
+        (rc = upload(p->ws, wsinit, total))) {
         release(p);
         delete p;
         return rc;
     }
-    p->ZE = (double *)p->ws.p;
-    p->part = p->ZE + 10;
+    p->n_sys = n_sys;
+    p->sys_host = hp.sys;
+    // resident-block counts of the persistent kernels, queried once here so
+    // that no launch (eager or captured) needs a device query
+    gint_prime_grids_fp64();   // k_work serves every precision form
+    if (prec != GINT_FP64) gint_prime_grids_mx(prec);
+    p->counter = (int *)p->ws.p;
+    p->ZE = (double *)p->ws.p + 1;
+    p->part = p->ZE + 10 * n_sys;
 
     GDev d{};
     d.species = (const GSpecies *)p->species.p;
     d.atoms = (const GAtom *)p->atoms.p;
     d.tab = (const double *)p->tab.p;
+    d.tab32 = (const float *)p->tab32.p;
     d.pairs = (const GPair *)p->pairs.p;
     d.bigcells = (const GBig *)p->bigcells.p;
+    d.sys = (const GSys *)p->sys.p;
+    d.counter = p->counter;
+    d.nsys = n_sys;
     d.natom = hp.natom;
     for (int i = 0; i < 3; ++i) {
         d.N[i] = hp.N[i];
@@ -149,6 +173,9 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     s.work_units = 0.0;
     s.volume = hp.omega;
     s.device_bytes = (int64_t)total;
+    s.precision = prec;
+    s.n_sys = n_sys;
+    p->precision = prec;
     s.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
     return GINT_OK;
@@ -159,7 +186,8 @@ int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream)
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(h_vals, p->sizes.nnz, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
-    e = gint_launch_vlocal(p->canon, v_loc, h_vals, s);
+    e = p->precision == GINT_FP64 ? gint_launch_vlocal(p->canon, v_loc, h_vals, s)
+                                  : gint_launch_vlocal_mx(p->canon, p->precision, v_loc, h_vals, s);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }
@@ -169,10 +197,11 @@ int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, vo
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
-    e = gint_launch_rho(p->canon, d_vals, rho, s);
+    e = p->precision == GINT_FP64 ? gint_launch_rho(p->canon, d_vals, rho, s)
+                                  : gint_launch_rho_mx(p->canon, p->precision, d_vals, rho, s);
     if (e != hipSuccess) return hip_fail(e);
     if (n_elec) {
-        e = gint_launch_sum(rho, p->sizes.ngrid, p->canon.w, p->part, kParts, n_elec, s);
+        e = gint_launch_seg_sum(p->canon, rho, p->part, kParts, n_elec, s);
         if (e != hipSuccess) return hip_fail(e);
     }
     return GINT_OK;
@@ -183,9 +212,11 @@ int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, d
     if (!p || !v_loc || !d_vals || !force || !stress) return GINT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(force, 3LL * p->sizes.natom, 0.0, s);
-    if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10, 0.0, s);
-    if (e == hipSuccess) e = gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, s);
-    if (e == hipSuccess) e = gint_launch_finish_stress(p->ZE, 1.0 / p->sizes.volume, stress, energy, s);
+    if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10LL * p->n_sys, 0.0, s);
+    if (e == hipSuccess)
+        e = p->precision == GINT_FP64 ? gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, s)
+                                      : gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, s);
+    if (e == hipSuccess) e = gint_launch_finish_stress(p->ordered, p->ZE, stress, energy, s);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }
@@ -194,15 +225,104 @@ int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, d
 int gint_work_units(gint_plan *p, double *w_out, void *stream) {
     if (!p || !w_out) return GINT_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = gint_launch_fill(w_out, 1, 0.0, s);
+    hipError_t e = gint_launch_fill(w_out, p->n_sys, 0.0, s);
     if (e == hipSuccess) e = gint_launch_work(p->canon, w_out, s);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }
 
+struct gint_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+};
+
+int gint_graph_create(gint_graph **out, gint_plan *p, const double *v_loc, const double *d_vals, double *h_vals,
+                      double *rho, double *n_elec, double *force, double *stress, double *energy) {
+    if (!out || !p) return GINT_EINVAL;
+    if ((h_vals || force) && !v_loc) return GINT_EINVAL;
+    if ((rho || force) && !d_vals) return GINT_EINVAL;
+    if (!!force != !!stress) return GINT_EINVAL;
+    if (!rho && n_elec) return GINT_EINVAL;
+    if (!h_vals && !rho && !force) return GINT_EINVAL;
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e);
+    if (cur != p->device) return GINT_EINVAL;
+    hipStream_t cs = nullptr;
+    e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(e);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e);
+    }
+    int rc = GINT_OK;
+    if (h_vals) rc = gint_vlocal(p, v_loc, h_vals, cs);
+    if (rc == GINT_OK && rho) rc = gint_rho(p, d_vals, rho, n_elec, cs);
+    if (rc == GINT_OK && force) rc = gint_force_stress(p, v_loc, d_vals, force, stress, energy, cs);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (rc != GINT_OK || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc != GINT_OK ? rc : hip_fail(e);
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e);
+    }
+    gint_graph *g = new (std::nothrow) gint_graph();
+    if (!g) {
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        return GINT_ENOMEM;
+    }
+    g->graph = graph;
+    g->exec = exec;
+    g->device = cur;
+    *out = g;
+    return GINT_OK;
+}
+
+int gint_graph_launch(gint_graph *g, void *stream) {
+    if (!g) return GINT_EINVAL;
+    hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return GINT_OK;
+}
+
+void gint_graph_destroy(gint_graph *g) {
+    if (!g) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    (void)hipSetDevice(cur);
+    delete g;
+}
+
 int gint_plan_query(const gint_plan *p, gint_sizes *out) {
     if (!p || !out) return GINT_EINVAL;
     *out = p->sizes;
+    return GINT_OK;
+}
+
+int gint_plan_query_system(const gint_plan *p, int i, gint_system_sizes *out) {
+    if (!p || !out || i < 0 || i >= p->n_sys) return GINT_EINVAL;
+    const GSys &S = p->sys_host[i];
+    const long long nnz_end = i + 1 < p->n_sys ? p->sys_host[i + 1].nnz_off : p->sizes.nnz;
+    out->g_off = S.g_off;
+    out->ngrid = (int64_t)S.N[0] * S.N[1] * S.N[2];
+    out->nnz_off = S.nnz_off;
+    out->nnz = nnz_end - S.nnz_off;
+    out->atom_off = S.atom_off;
+    out->natom = S.natom;
+    for (int k = 0; k < 3; ++k) out->grid[k] = S.N[k];
+    out->volume = S.volume;
     return GINT_OK;
 }
 

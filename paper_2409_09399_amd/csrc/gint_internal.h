@@ -46,7 +46,7 @@ struct GPair {
     double shiftA[3];            // TA.h added to A-atom positions
     double shiftB[3];            // TB.h added to B-atom positions
     int self;                    // 1: A == B with TA == TB (tiles cover both orders)
-    int pad;
+    int sys;                     // system of a batched plan
     long long hoff[GINT_CL * GINT_CL];
     long long hoff_t[GINT_CL * GINT_CL];
 };
@@ -59,6 +59,20 @@ struct GItem {
     int pair;
     int bc_begin;
     int bc_count;
+    int pad;                     // 1: the item covers its whole pair (H written with plain stores)
+};
+
+// Geometry of one system of a (possibly batched) plan and the offsets of its
+// data in the packed grid arrays (V, rho) and per-system scalars.
+struct GSys {
+    int N[3];
+    int natom;
+    double e[3][3];              // grid step vectors e_i = a_i / N_i (rows)
+    double w;                    // volume per grid point
+    double volume;
+    long long g_off;             // first grid point in packed V / rho
+    long long nnz_off;           // first element in packed H / D
+    int atom_off;                // first atom in packed F
     int pad;
 };
 
@@ -67,10 +81,14 @@ struct GDev {
     const GSpecies *species;
     const GAtom *atoms;
     const double *tab;           // interleaved radial tables
+    const float *tab32;          // the same tables rounded to FP32 (mixed precision)
     const GPair *pairs;
     const GBig *bigcells;
     const GItem *items;
+    const GSys *sys;             // per-system geometry (one entry for a single system)
+    int *counter;                // work counter of persistent launches (reset before each launch)
     int nitems;
+    int nsys;
     int natom;
     int N[3];
     double e[3][3];              // grid step vectors e_i = a_i / N_i (rows)

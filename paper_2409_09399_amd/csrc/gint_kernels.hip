@@ -13,6 +13,10 @@
 // the whole item (wave i owns row atom a_i) and writes them once at the end.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <utility>
+#include <vector>
+
 #include "gint_internal.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -26,6 +30,31 @@ constexpr double kC1 = 0.48860251190291992;    // sqrt(3/(4 pi))
 constexpr double kC2a = 1.0925484305920792;    // sqrt(15/pi)/2
 constexpr double kC2b = 0.31539156525252005;   // sqrt(5/pi)/4
 constexpr double kC2c = 0.54627421529603959;   // sqrt(15/pi)/4
+
+// Wave index as a wave-uniform value: lets the compiler keep everything
+// indexed by it (atom slots, species descriptors, channel loops) in scalar
+// registers and scalar branches.
+__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Persistent work loop: items are claimed from a device counter (reset to 0
+// before every launch); each item binds its system's geometry.
+__device__ inline int claim_item(int *counter, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    return *slot;
+}
+
+__device__ inline void bind_system(GDev &P, int s) {
+    const GSys &S = P.sys[s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.N[k] = S.N[k];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) P.e[k][m] = S.e[k][m];
+    }
+    P.w = S.w;
+}
 
 __device__ inline int wrap(int n, int N) {
     int m = n % N;
@@ -189,7 +218,7 @@ template <int MODE>
 __device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, const double *__restrict__ V,
                              double *phiA, double *phiB, unsigned *maskpt) {
     const int t = threadIdx.x;
-    const int pt = t & 63, slot = t >> 6;
+    const int pt = t & 63, slot = wave_id();
     const Pt r = bigcell_point(P, o, pt);
     unsigned bits = 0;
     {
@@ -268,7 +297,7 @@ __device__ inline void load_dsym(const GDev &P, const GPair &pr, const double *_
 // over its own rows of phiB (no other wave reads those rows).  All operand
 // reads are issued before the MFMAs; each B-atom operand feeds all 4 A atoms.
 __device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const unsigned *maskpt) {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, w = wave_id();
     unsigned gm = or16(maskpt[16 * w + (lane & 15)]);
     gm = __builtin_amdgcn_readfirstlane(gm);
     const double *base = phiB + (16 * w + (lane & 15)) * PSTR + (lane >> 4);
@@ -300,16 +329,28 @@ __device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const
 // ---------------------------------------------------------------------------
 // H_IJR (Eq. 2)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict__ V, double *__restrict__ H) {
+__global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
     __shared__ double phiA[GINT_BCPTS * PSTR];
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
-    const GItem it = P.items[blockIdx.x];
-    const GPair &pr = P.pairs[it.pair];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    d4 acc[4];
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    const double *V = V0 + SY.g_off;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    // split-K: wave w owns k-steps 4w..4w+3 (points 16w..16w+15) of every
+    // bigcell and accumulates all 16 (a_i, b_j) tiles
+    d4 acc[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = P.bigcells[it.bc_begin + bc];
@@ -317,76 +358,95 @@ __global__ __launch_bounds__(256) void k_vlocal(GDev P, const double *__restrict
         __syncthreads();
         stage<1>(P, pr, o, V, phiA, phiB, maskpt);
         __syncthreads();
-        // wave w owns row atom a_w; k-steps of 4 points along the third axis.
-        // Activity of every k-step comes from one ballot per atom; only k-steps
-        // where a_w is active are visited, two at a time with their operand
-        // reads issued before the MFMAs.
-        {
-            const unsigned mp = maskpt[lane];
-            unsigned mk = mp | __shfl_xor(mp, 1);
-            mk |= __shfl_xor(mk, 2);
-            unsigned long long rowk = __ballot(mk & (1u << w)) & 0x1111111111111111ull;
-            unsigned long long colk[4];
+        // k-step t of this wave = points 16w + 4t .. +3; its activity mask is the
+        // OR over those 4 points, read into scalar registers once
+        const unsigned mp = maskpt[16 * w + (lane & 15)];
+        unsigned mk = mp | __shfl_xor(mp, 1);
+        mk |= __shfl_xor(mk, 2);
+        unsigned km[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) colk[j] = __ballot(mk & (1u << (4 + j)));
-            const double *pa = phiA + (lane >> 4) * PSTR + w * GINT_ORB + (lane & 15);
-            const double *pb = phiB + (lane >> 4) * PSTR + (lane & 15);
-            // one tile at a time over the k-steps where both atoms are active;
-            // two independent accumulator chains, the odd tail is a zero operand
+        for (int t = 0; t < 4; ++t) km[t] = __builtin_amdgcn_readlane(mk, 4 * t);
+        // all operands of the wave's 4 k-steps in one batch of LDS reads
+        double a[4][4], b[4][4];
+        const int row0 = (16 * w + (lane >> 4)) * PSTR + (lane & 15);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                unsigned long long m = rowk & colk[j];
-                const double *pbj = pb + j * GINT_ORB;
-                d4 c0 = acc[j], c1 = (d4){0.0, 0.0, 0.0, 0.0};
-                while (m) {
-                    const int s0 = __builtin_ctzll(m);
-                    m &= m - 1;
-                    const int s1 = m ? __builtin_ctzll(m) : s0;
-                    const double z = m ? 1.0 : 0.0;
-                    m &= m - 1;
-                    const double a0 = pa[s0 * PSTR], b0 = pbj[s0 * PSTR];
-                    const double a1 = pa[s1 * PSTR], b1 = pbj[s1 * PSTR] * z;
-                    c0 = mfma64(a0, b0, c0);
-                    c1 = mfma64(a1, b1, c1);
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[t][i] = phiA[row0 + 4 * t * PSTR + i * GINT_ORB];
+                b[t][i] = phiB[row0 + 4 * t * PSTR + i * GINT_ORB];
+            }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (!(km[t] & (1u << i))) continue;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (km[t] & (1u << (4 + j))) acc[i][j] = mfma64(a[t][i], b[t][j], acc[i][j]);
+            }
+        __syncthreads();
+    }
+    // reduce the 4 waves' partial tiles through LDS, one row atom at a time,
+    // then write each (a_i, b_j) block once (plain stores when the item covers
+    // the whole pair, atomics otherwise), plus its transpose (b_j, a_i, -R)
+    double *red = phiA;    // [wave][j][q][lane] = 4*4*4*64 doubles
+    const bool exclusive = it.pad != 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[((w * 4 + j) * 4 + q) * 64 + lane] = acc[i][j][q];
+        __syncthreads();
+        const int ai = pr.a[i];
+        if (ai >= 0) {
+            const int na = P.atoms[ai].norb;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int e = threadIdx.x + 256 * k;    // (j, q, l)
+                const int j = e >> 8, q = (e >> 6) & 3, l = e & 63;
+                const int bj = pr.b[j];
+                if (bj < 0) continue;
+                const int nb = P.atoms[bj].norb;
+                const int mu = 4 * q + (l >> 4), nu = l & 15;
+                if (mu >= na || nu >= nb) continue;
+                const double v = red[((0 * 4 + j) * 4 + q) * 64 + l] + red[((1 * 4 + j) * 4 + q) * 64 + l] +
+                                 red[((2 * 4 + j) * 4 + q) * 64 + l] + red[((3 * 4 + j) * 4 + q) * 64 + l];
+                const long long off = pr.hoff[i * 4 + j], offt = pr.hoff_t[i * 4 + j];
+                if (exclusive) {
+                    if (off >= 0) H[off + (long long)mu * nb + nu] = v;
+                    if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
+                } else {
+                    if (off >= 0) atomicAdd(H + off + (long long)mu * nb + nu, v);
+                    if (!pr.self && offt >= 0) atomicAdd(H + offt + (long long)nu * na + mu, v);
                 }
-                acc[j] = c0 + c1;
             }
         }
         __syncthreads();
     }
-    // tile (a_w, b_j): lane l, register q holds row mu = 4 q + (l >> 4), column nu = l & 15
-    const int ai = pr.a[w];
-    if (ai < 0) return;
-    const int na = P.atoms[ai].norb;
-    const int nu = lane & 15;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int bj = pr.b[j];
-        if (bj < 0) continue;
-        const int nb = P.atoms[bj].norb;
-        const long long o = pr.hoff[w * 4 + j], ot = pr.hoff_t[w * 4 + j];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int mu = 4 * q + (lane >> 4);
-            if (mu >= na || nu >= nb) continue;
-            const double v = acc[j][q];
-            if (o >= 0) atomicAdd(H + o + (long long)mu * nb + nu, v);
-            if (!pr.self && ot >= 0) atomicAdd(H + ot + (long long)nu * na + mu, v);
-        }
     }
 }
 
 // ---------------------------------------------------------------------------
 // rho_g (Eq. 3): canonical pairs, weight 2 off the self pair
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rho(GDev P, const double *__restrict__ D, double *__restrict__ rho) {
+__global__ __launch_bounds__(256) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiA[GINT_BCPTS * PSTR];
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ double part[4][GINT_BCPTS];
-    const GItem it = P.items[blockIdx.x];
-    const GPair &pr = P.pairs[it.pair];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    double *rho = rho0 + SY.g_off;
+    const int lane = threadIdx.x & 63, w = wave_id();
     double dreg[4][4][4];
     load_dsym(P, pr, D, dreg);
     const double weight = pr.self ? 1.0 : 2.0;
@@ -421,20 +481,30 @@ __global__ __launch_bounds__(256) void k_rho(GDev P, const double *__restrict__ 
         }
         __syncthreads();
     }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only
 // acc[0..2] F of atom a_w, acc[3..11] Z, acc[12] E
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_force(GDev P, const double *__restrict__ V, const double *__restrict__ D,
-                                               double *__restrict__ F, double *__restrict__ ZE) {
+__global__ __launch_bounds__(256) void k_force(GDev P0, const double *__restrict__ V0, const double *__restrict__ D,
+                                               double *__restrict__ F, double *__restrict__ ZE0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ double red[4][10];
-    const GItem it = P.items[blockIdx.x];
-    const GPair &pr = P.pairs[it.pair];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    const double *V = V0 + SY.g_off;
+    double *ZE = ZE0 + 10 * pr.sys;
+    const int lane = threadIdx.x & 63, w = wave_id();
     double dreg[4][4][4];
     load_dsym(P, pr, D, dreg);
     double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
@@ -494,15 +564,24 @@ __global__ __launch_bounds__(256) void k_force(GDev P, const double *__restrict_
         const int k = threadIdx.x;
         atomicAdd(ZE + k, red[0][k] + red[1][k] + red[2][k] + red[3][k]);
     }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // W = sum_g n_orb(g)^2 from the canonical pairs (exact in FP64: integers)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_work(GDev P, double *__restrict__ W) {
+__global__ __launch_bounds__(256) void k_work(GDev P0, double *__restrict__ W0) {
     __shared__ double red[256];
-    const GItem it = P.items[blockIdx.x];
-    const GPair &pr = P.pairs[it.pair];
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    double *W = W0 + pr.sys;
     const double weight = pr.self ? 1.0 : 2.0;
     double acc = 0.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
@@ -538,6 +617,7 @@ __global__ __launch_bounds__(256) void k_work(GDev P, double *__restrict__ W) {
         __syncthreads();
     }
     if (threadIdx.x == 0) atomicAdd(W, red[0]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -548,45 +628,87 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
         p[i] = v;
 }
 
-// partial sums of w * x over a grid array (deterministic two-pass reduction)
-__global__ __launch_bounds__(256) void k_sum_partial(const double *__restrict__ x, long long n, double scale,
-                                                     double *__restrict__ part) {
+// Per-system sums of w_s * x over each system's grid range (two passes,
+// deterministic): part[s * nparts + b] then out[s].
+__global__ __launch_bounds__(256) void k_seg_sum_partial(GDev P, const double *__restrict__ x, int nparts,
+                                                         double *__restrict__ part) {
     __shared__ double red[256];
+    const GSys &S = P.sys[blockIdx.y];
+    const long long n = (long long)S.N[0] * S.N[1] * S.N[2];
+    const double *xs = x + S.g_off;
     double acc = 0.0;
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += x[i];
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += xs[i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0] * scale;
+    if (threadIdx.x == 0) part[(long long)blockIdx.y * nparts + blockIdx.x] = red[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ part, int n, double *__restrict__ out) {
+__global__ __launch_bounds__(256) void k_seg_sum_final(GDev P, const double *__restrict__ part, int nparts,
+                                                       double *__restrict__ out) {
     __shared__ double red[256];
+    const int sy = blockIdx.x;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+    for (int i = threadIdx.x; i < nparts; i += 256) acc += part[(long long)sy * nparts + i];
     red[threadIdx.x] = acc;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[0] = red[0];
+    if (threadIdx.x == 0) out[sy] = red[0] * P.sys[sy].w;
 }
 
-// stress = -Z / Omega, energy = E
-__global__ void k_finish_stress(const double *__restrict__ ZE, double inv_omega, double *__restrict__ stress,
+// stress_s = -Z_s / Omega_s, energy_s = E_s
+__global__ void k_finish_stress(GDev P, const double *__restrict__ ZE, double *__restrict__ stress,
                                 double *__restrict__ energy) {
-    const int k = threadIdx.x;
-    if (k < 9) stress[k] = -ZE[k] * inv_omega;
-    if (k == 9 && energy) energy[0] = ZE[9];
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int sy = t / 10, k = t % 10;
+    if (sy >= P.nsys) return;
+    if (k < 9) stress[9 * sy + k] = -ZE[10 * sy + k] / P.sys[sy].volume;
+    else if (energy) energy[sy] = ZE[10 * sy + 9];
 }
 
 // ---------------------------------------------------------------------------
 // launchers (called from the C ABI layer)
 // ---------------------------------------------------------------------------
+// Resident workgroups per device for a kernel (CUs x occupancy), cached so
+// that launches inside a stream capture make no device queries.
+namespace {
+struct GridKey {
+    const void *kernel;
+    int device;
+};
+std::mutex g_grid_mu;
+std::vector<std::pair<GridKey, int>> g_grid_cache;
+}  // namespace
+
+int gint_resident_blocks(const void *kernel) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = -1;
+    {
+        std::lock_guard<std::mutex> lk(g_grid_mu);
+        for (const auto &e : g_grid_cache)
+            if (e.first.kernel == kernel && e.first.device == dev) return e.second;
+    }
+    int cus = 0, per_cu = 0;
+    if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    const int slots = cus * per_cu;
+    std::lock_guard<std::mutex> lk(g_grid_mu);
+    g_grid_cache.push_back({GridKey{kernel, dev}, slots});
+    return slots;
+}
+
+int gint_persistent_grid(const void *kernel, int nitems) {
+    const int slots = gint_resident_blocks(kernel);
+    return nitems < slots ? nitems : slots;
+}
+
 hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     long long blocks = (n + 255) / 256;
@@ -595,41 +717,53 @@ hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Reset the work counter, then one persistent launch over all items.
+#define GINT_PERSISTENT_LAUNCH(KERNEL, P, s, ...)                                                    \
+    do {                                                                                            \
+        if ((P).nitems <= 0) return hipSuccess;                                                     \
+        hipError_t e_ = gint_launch_fill((double *)(P).counter, 1, 0.0, s);                         \
+        if (e_ != hipSuccess) return e_;                                                            \
+        const int grid_ = gint_persistent_grid((const void *)KERNEL, (P).nitems);                   \
+        hipLaunchKernelGGL(KERNEL, dim3(grid_), dim3(256), 0, s, P, __VA_ARGS__);                    \
+        return hipGetLastError();                                                                   \
+    } while (0)
+
 hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s) {
-    if (P.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_vlocal, dim3(P.nitems), dim3(256), 0, s, P, V, H);
-    return hipGetLastError();
+    GINT_PERSISTENT_LAUNCH(k_vlocal, P, s, V, H);
 }
 
 hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s) {
-    if (P.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rho, dim3(P.nitems), dim3(256), 0, s, P, D, rho);
-    return hipGetLastError();
+    GINT_PERSISTENT_LAUNCH(k_rho, P, s, D, rho);
 }
 
 hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, hipStream_t s) {
-    if (P.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_force, dim3(P.nitems), dim3(256), 0, s, P, V, D, F, ZE);
-    return hipGetLastError();
+    GINT_PERSISTENT_LAUNCH(k_force, P, s, V, D, F, ZE);
 }
 
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
-    if (P.nitems <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_work, dim3(P.nitems), dim3(256), 0, s, P, W);
-    return hipGetLastError();
+    GINT_PERSISTENT_LAUNCH(k_work, P, s, W);
 }
 
-hipError_t gint_launch_sum(const double *x, long long n, double scale, double *part, int nparts, double *out,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partial, dim3(nparts), dim3(256), 0, s, x, n, scale, part);
+hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_sum_partial, dim3(nparts, P.nsys), dim3(256), 0, s, P, x, nparts, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, part, nparts, out);
+    hipLaunchKernelGGL(k_seg_sum_final, dim3(P.nsys), dim3(256), 0, s, P, part, nparts, out);
     return hipGetLastError();
 }
 
-hipError_t gint_launch_finish_stress(const double *ZE, double inv_omega, double *stress, double *energy,
+hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
                                      hipStream_t s) {
-    hipLaunchKernelGGL(k_finish_stress, dim3(1), dim3(64), 0, s, ZE, inv_omega, stress, energy);
+    const int n = 10 * P.nsys;
+    hipLaunchKernelGGL(k_finish_stress, dim3((n + 255) / 256), dim3(256), 0, s, P, ZE, stress, energy);
     return hipGetLastError();
+}
+
+// Fill the resident-block cache for every kernel of a precision form.
+void gint_prime_grids_fp64() {
+    gint_resident_blocks((const void *)k_vlocal);
+    gint_resident_blocks((const void *)k_rho);
+    gint_resident_blocks((const void *)k_force);
+    gint_resident_blocks((const void *)k_work);
 }

@@ -1,0 +1,669 @@
+// Mixed-precision grid integration on CDNA4 (gfx950).
+//
+// Same work decomposition as the FP64 kernels (cluster-pair items over
+// 4x4x4-point bigcells, see gint_internal.h), different arithmetic:
+//   - orbitals are evaluated in FP32 from FP32 radial tables;
+//   - every MFMA operand x is split into 16-bit parts x = x_hi + x_lo
+//     (FP16 or BF16) and a product is a_hi b_hi + a_hi b_lo + a_lo b_hi on
+//     v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation (the dropped
+//     a_lo b_lo term is below the split's own rounding);
+//   - FP32 partial sums of one bigcell are folded into FP64 accumulators,
+//     and H, rho, F, Z, E and N_e are reduced in FP64.
+// The local potential enters the Vlocal operand as V (not w V) so that the
+// 16-bit parts stay in range; the constant w is applied in FP64.
+#include <hip/hip_runtime.h>
+
+#include "gint_internal.h"
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr float kC0f = 0.28209479177387814f;
+constexpr float kC1f = 0.48860251190291992f;
+constexpr float kC2af = 1.0925484305920792f;
+constexpr float kC2bf = 0.31539156525252005f;
+constexpr float kC2cf = 0.54627421529603959f;
+
+template <class T>
+struct Split16;
+
+template <>
+struct Split16<_Float16> {
+    typedef h8v vec;
+    __device__ static inline void split(float v, _Float16 &hi, _Float16 &lo) {
+        hi = (_Float16)v;
+        lo = (_Float16)(v - (float)hi);
+    }
+    __device__ static inline f4v mfma(vec a, vec b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+template <>
+struct Split16<__bf16> {
+    typedef b8v vec;
+    __device__ static inline void split(float v, __bf16 &hi, __bf16 &lo) {
+        hi = (__bf16)v;
+        lo = (__bf16)(v - (float)hi);
+    }
+    __device__ static inline f4v mfma(vec a, vec b, f4v c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+__device__ inline int wave_idx() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Persistent work loop: items are claimed from a device counter (reset to 0
+// before every launch); each item binds its system's geometry.
+__device__ inline int claim_item(int *counter, int *slot) {
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
+    __syncthreads();
+    return *slot;
+}
+
+__device__ inline void bind_system(GDev &P, int s) {
+    const GSys &S = P.sys[s];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        P.N[k] = S.N[k];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) P.e[k][m] = S.e[k][m];
+    }
+    P.w = S.w;
+}
+
+__device__ inline int wrapi(int n, int N) {
+    int m = n % N;
+    return m < 0 ? m + N : m;
+}
+
+struct P3 {
+    double x, y, z;
+    long long g;
+};
+
+__device__ inline P3 point_of(const GDev &P, const GBig &o, int pt) {
+    const int n0 = o.x + (pt >> 4), n1 = o.y + ((pt >> 2) & 3), n2 = o.z + (pt & 3);
+    P3 r;
+    r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
+    r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
+    r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
+    r.g = ((long long)wrapi(n0, P.N[0]) * P.N[1] + wrapi(n1, P.N[1])) * P.N[2] + wrapi(n2, P.N[2]);
+    return r;
+}
+
+// Cubic Hermite on the FP32 table: knot rows k, k+1 ([chan][f, f']) and weights.
+struct Herm32 {
+    const float *row0, *row1;
+    float h00, h10, h01, h11, d00, d10, d01, d11;
+};
+
+__device__ inline Herm32 hermite32(const GSpecies &sp, const float *tab, float r) {
+    float t = r * (float)sp.inv_dr;
+    int k = (int)t;
+    if (k > sp.nknots - 2) k = sp.nknots - 2;
+    t -= (float)k;
+    const float t2 = t * t, t3 = t2 * t, dr = (float)sp.dr, idr = (float)sp.inv_dr;
+    Herm32 h;
+    h.row0 = tab + sp.tab_off + (size_t)k * sp.nchan * 2;
+    h.row1 = h.row0 + sp.nchan * 2;
+    h.h00 = 2.f * t3 - 3.f * t2 + 1.f;
+    h.h10 = (t3 - 2.f * t2 + t) * dr;
+    h.h01 = 3.f * t2 - 2.f * t3;
+    h.h11 = (t3 - t2) * dr;
+    h.d00 = (6.f * t2 - 6.f * t) * idr;
+    h.d10 = 3.f * t2 - 4.f * t + 1.f;
+    h.d01 = -h.d00;
+    h.d11 = 3.f * t2 - 2.f * t;
+    return h;
+}
+
+// phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v).
+template <class Emit>
+__device__ inline void eval32(const GSpecies &sp, const float *tab, float x, float y, float z, float r2, float scale,
+                              Emit emit) {
+    const float r = sqrtf(r2);
+    const Herm32 h = hermite32(sp, tab, r);
+    const float S1y = kC1f * y, S1z = kC1f * z, S1x = kC1f * x;
+    const float S20 = kC2af * x * y, S21 = kC2af * y * z, S22 = kC2bf * (2.f * z * z - x * x - y * y),
+                S23 = kC2af * x * z, S24 = kC2cf * (x * x - y * y);
+    int slot = 0;
+    for (int c = 0; c < sp.nchan; ++c) {
+        const float p = (h.h00 * h.row0[2 * c] + h.h10 * h.row0[2 * c + 1] + h.h01 * h.row1[2 * c] +
+                         h.h11 * h.row1[2 * c + 1]) * scale;
+        const int l = sp.chan_l[c];
+        if (l == 0) {
+            emit(slot, p * kC0f);
+            slot += 1;
+        } else if (l == 1) {
+            emit(slot, p * S1y);
+            emit(slot + 1, p * S1z);
+            emit(slot + 2, p * S1x);
+            slot += 3;
+        } else {
+            emit(slot, p * S20);
+            emit(slot + 1, p * S21);
+            emit(slot + 2, p * S22);
+            emit(slot + 3, p * S23);
+            emit(slot + 4, p * S24);
+            slot += 5;
+        }
+    }
+    for (; slot < GINT_ORB; ++slot) emit(slot, 0.f);
+}
+
+// sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu, FP32.
+__device__ inline void dot_grad32(const GSpecies &sp, const float *tab, float x, float y, float z, float r2,
+                                  const float *psi, float &e, float G[3]) {
+    const float r = sqrtf(r2);
+    const Herm32 h = hermite32(sp, tab, r);
+    const float inv_r = r > 0.f ? 1.f / r : 0.f;
+    e = 0.f;
+    G[0] = G[1] = G[2] = 0.f;
+    int slot = 0;
+    for (int c = 0; c < sp.nchan; ++c) {
+        const float f0 = h.row0[2 * c], fp0 = h.row0[2 * c + 1], f1 = h.row1[2 * c], fp1 = h.row1[2 * c + 1];
+        const float p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
+        const float q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
+        const int l = sp.chan_l[c];
+        float A, Bx, By, Bz;
+        if (l == 0) {
+            A = psi[slot] * kC0f;
+            Bx = By = Bz = 0.f;
+            slot += 1;
+        } else if (l == 1) {
+            const float p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2];
+            A = kC1f * (p0 * y + p1 * z + p2 * x);
+            Bx = kC1f * p2;
+            By = kC1f * p0;
+            Bz = kC1f * p1;
+            slot += 3;
+        } else {
+            const float p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2], p3 = psi[slot + 3], p4 = psi[slot + 4];
+            A = kC2af * (p0 * x * y + p1 * y * z + p3 * x * z) + kC2bf * p2 * (2.f * z * z - x * x - y * y) +
+                kC2cf * p4 * (x * x - y * y);
+            Bx = kC2af * (p0 * y + p3 * z) - 2.f * kC2bf * p2 * x + 2.f * kC2cf * p4 * x;
+            By = kC2af * (p0 * x + p1 * z) - 2.f * kC2bf * p2 * y - 2.f * kC2cf * p4 * y;
+            Bz = kC2af * (p1 * y + p3 * x) + 4.f * kC2bf * p2 * z;
+            slot += 5;
+        }
+        e += p * A;
+        G[0] += q * A * x + p * Bx;
+        G[1] += q * A * y + p * By;
+        G[2] += q * A * z + p * Bz;
+    }
+}
+
+// Activity of one atom at one point; x is the FP32 displacement.
+struct Disp {
+    float x, y, z, r2;
+    bool in;
+};
+
+__device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, const double *shift) {
+    Disp d{0.f, 0.f, 0.f, 0.f, false};
+    if (atom < 0) return d;
+    const GAtom at = P.atoms[atom];
+    const double dx = r.x - at.x - shift[0], dy = r.y - at.y - shift[1], dz = r.z - at.z - shift[2];
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    const GSpecies &sp = P.species[at.species];
+    d.in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+    d.x = (float)dx;
+    d.y = (float)dy;
+    d.z = (float)dz;
+    d.r2 = (float)r2;
+    return d;
+}
+
+constexpr int TSTR = 72;   // 16-bit elements per tile row (64 points + 8): conflict-free 16-byte reads
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// H_IJR (Eq. 2), mixed precision.  Tiles [hi/lo][slot][orbital][point]; wave
+// w owns the diagonal tiles (a_i, b_{(w-i)&3}); two k-steps of 32 points.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
+    typedef Split16<T> S;
+    typedef typename S::vec vec;
+    __shared__ __attribute__((aligned(16))) T tA[2][4][16][TSTR];
+    __shared__ __attribute__((aligned(16))) T tB[2][4][16][TSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    const double *V = V0 + SY.g_off;
+    const int lane = threadIdx.x & 63, w = wave_idx();
+    d4v acc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[i] = (d4v){0.0, 0.0, 0.0, 0.0};
+
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        {
+            // phase 1: A atom (slot w) and B atom (slot w) at point lane
+            const int pt = lane;
+            const P3 r = point_of(P, o, pt);
+            unsigned bits = 0;
+            const int a = pr.a[w], b = pr.b[w];
+            const Disp da = disp_of(P, r, a, pr.shiftA);
+            if (da.in) {
+                const GSpecies &sp = P.species[P.atoms[a].species];
+                eval32(sp, P.tab32, da.x, da.y, da.z, da.r2, 1.f, [&](int mu, float v) {
+                    T hi, lo;
+                    S::split(v, hi, lo);
+                    tA[0][w][mu][pt] = hi;
+                    tA[1][w][mu][pt] = lo;
+                });
+                bits |= 1u << w;
+            } else {
+#pragma unroll
+                for (int mu = 0; mu < 16; ++mu) {
+                    tA[0][w][mu][pt] = (T)0.f;
+                    tA[1][w][mu][pt] = (T)0.f;
+                }
+            }
+            const Disp db = disp_of(P, r, b, pr.shiftB);
+            if (db.in) {
+                const GSpecies &sp = P.species[P.atoms[b].species];
+                const float vg = (float)V[r.g];
+                eval32(sp, P.tab32, db.x, db.y, db.z, db.r2, vg, [&](int mu, float v) {
+                    T hi, lo;
+                    S::split(v, hi, lo);
+                    tB[0][w][mu][pt] = hi;
+                    tB[1][w][mu][pt] = lo;
+                });
+                bits |= 1u << (4 + w);
+            } else {
+#pragma unroll
+                for (int mu = 0; mu < 16; ++mu) {
+                    tB[0][w][mu][pt] = (T)0.f;
+                    tB[1][w][mu][pt] = (T)0.f;
+                }
+            }
+            if (bits) atomicOr(&maskpt[pt], bits);
+        }
+        __syncthreads();
+        // phase 2: activity of the two 32-point k-steps
+        const unsigned mp = maskpt[lane];
+        unsigned km[2] = {0u, 0u};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const unsigned long long bl = __ballot((mp >> b) & 1u);
+            if (bl & 0xffffffffull) km[0] |= 1u << b;
+            if (bl >> 32) km[1] |= 1u << b;
+        }
+        f4v c32[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) c32[i] = (f4v){0.f, 0.f, 0.f, 0.f};
+        const int row = lane & 15, col = 8 * (lane >> 4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int j = (w - i) & 3;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                if (!((km[kk] >> i) & 1u) || !((km[kk] >> (4 + j)) & 1u)) continue;
+                const vec ahi = *(const vec *)&tA[0][i][row][32 * kk + col];
+                const vec alo = *(const vec *)&tA[1][i][row][32 * kk + col];
+                const vec bhi = *(const vec *)&tB[0][j][row][32 * kk + col];
+                const vec blo = *(const vec *)&tB[1][j][row][32 * kk + col];
+                c32[i] = S::mfma(ahi, bhi, c32[i]);
+                c32[i] = S::mfma(ahi, blo, c32[i]);
+                c32[i] = S::mfma(alo, bhi, c32[i]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][q] += (double)c32[i][q];
+        __syncthreads();
+    }
+    // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
+    const bool exclusive = it.pad != 0;
+    const int nu = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int j = (w - i) & 3;
+        const int ai = pr.a[i], bj = pr.b[j];
+        if (ai < 0 || bj < 0) continue;
+        const int na = P.atoms[ai].norb, nb = P.atoms[bj].norb;
+        const long long off = pr.hoff[i * 4 + j], offt = pr.hoff_t[i * 4 + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mu = 4 * (lane >> 4) + q;
+            if (mu >= na || nu >= nb) continue;
+            const double v = P.w * acc[i][q];
+            if (exclusive) {
+                if (off >= 0) H[off + (long long)mu * nb + nu] = v;
+                if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
+            } else {
+                if (off >= 0) atomicAdd(H + off + (long long)mu * nb + nu, v);
+                if (!pr.self && offt >= 0) atomicAdd(H + offt + (long long)nu * na + mu, v);
+            }
+        }
+    }
+    }
+}
+
+namespace {
+
+// D_sym blocks as 16-bit hi/lo MFMA B operands for psi = phi_B D^T:
+// k-step kk covers B atoms 2kk, 2kk+1; lane l holds mu = l & 15 and
+// nu' = 8 (l >> 4) + e, i.e. atom 2kk + (l >> 5), orbital 8 ((l >> 4) & 1) + e.
+template <class T>
+__device__ inline void load_dsym16(const GDev &P, const GPair &pr, const double *__restrict__ D,
+                                   typename Split16<T>::vec dh[4][2], typename Split16<T>::vec dl[4][2]) {
+    const int lane = threadIdx.x & 63;
+    const int mu = lane & 15;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int j = 2 * kk + (lane >> 5);
+            const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
+            const int na = pr.a[i] >= 0 ? P.atoms[pr.a[i]].norb : 0;
+            const int nb = pr.b[j] >= 0 ? P.atoms[pr.b[j]].norb : 0;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int nu = 8 * ((lane >> 4) & 1) + e;
+                float v = 0.f;
+                if (o >= 0 && ot >= 0 && mu < na && nu < nb)
+                    v = (float)(0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]));
+                T hi, lo;
+                Split16<T>::split(v, hi, lo);
+                dh[i][kk][e] = hi;
+                dl[i][kk][e] = lo;
+            }
+        }
+}
+
+constexpr int RSTR = 72;   // 16-bit elements per point row of the B tile (4 slots x 16 + 8)
+constexpr int FSTR = 65;   // floats per point row of FP32 tiles
+
+// Phase 1 of rho/force: B orbitals as 16-bit hi/lo rows [h][point][slot*16+mu];
+// A orbitals in FP32 (rho) or only their activity (force).
+template <class T, bool WANT_A>
+__device__ inline void stage_rho(const GDev &P, const GPair &pr, const GBig &o, T (*tB)[GINT_BCPTS][RSTR],
+                                 float *pA, unsigned *maskpt) {
+    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int pt = lane;
+    const P3 r = point_of(P, o, pt);
+    unsigned bits = 0;
+    const int a = pr.a[w], b = pr.b[w];
+    const Disp da = disp_of(P, r, a, pr.shiftA);
+    if (WANT_A) {
+        float *dst = pA + pt * FSTR + w * 16;
+        if (da.in) {
+            const GSpecies &sp = P.species[P.atoms[a].species];
+            eval32(sp, P.tab32, da.x, da.y, da.z, da.r2, 1.f, [&](int mu, float v) { dst[mu] = v; });
+        } else {
+#pragma unroll
+            for (int mu = 0; mu < 16; ++mu) dst[mu] = 0.f;
+        }
+    }
+    if (da.in) bits |= 1u << w;
+    const Disp db = disp_of(P, r, b, pr.shiftB);
+    T *h0 = &tB[0][pt][w * 16];
+    T *h1 = &tB[1][pt][w * 16];
+    if (db.in) {
+        const GSpecies &sp = P.species[P.atoms[b].species];
+        eval32(sp, P.tab32, db.x, db.y, db.z, db.r2, 1.f, [&](int mu, float v) {
+            T hi, lo;
+            Split16<T>::split(v, hi, lo);
+            h0[mu] = hi;
+            h1[mu] = lo;
+        });
+        bits |= 1u << (4 + w);
+    } else {
+#pragma unroll
+        for (int mu = 0; mu < 16; ++mu) {
+            h0[mu] = (T)0.f;
+            h1[mu] = (T)0.f;
+        }
+    }
+    if (bits) atomicOr(&maskpt[pt], bits);
+}
+
+// Phase 2: psi[pt][a_i][mu] = sum_{b, nu} phi_B[pt][b][nu] D_sym[a_i mu][b nu] for
+// the wave's 16 points (FP32 result into psi rows of FSTR floats).
+template <class T>
+__device__ inline void psi_mx(const typename Split16<T>::vec dh[4][2], const typename Split16<T>::vec dl[4][2],
+                              T (*tB)[GINT_BCPTS][RSTR], float *psi, const unsigned *maskpt) {
+    typedef typename Split16<T>::vec vec;
+    const int lane = threadIdx.x & 63, w = wave_idx();
+    unsigned gm = maskpt[16 * w + (lane & 15)];
+    gm |= __shfl_xor(gm, 1);
+    gm |= __shfl_xor(gm, 2);
+    gm |= __shfl_xor(gm, 4);
+    gm |= __shfl_xor(gm, 8);
+    gm = __builtin_amdgcn_readfirstlane(gm);
+    const int pt = 16 * w + (lane & 15);
+    const int off = 32 * 0 + 16 * (lane >> 5) + 8 * ((lane >> 4) & 1);   // within a 2-atom k-step
+    vec bh[2], bl[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+        bh[kk] = *(const vec *)&tB[0][pt][32 * kk + off];
+        bl[kk] = *(const vec *)&tB[1][pt][32 * kk + off];
+    }
+    float *dst = psi + (16 * w + 4 * (lane >> 4)) * FSTR + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (!(gm & (1u << i))) continue;
+        f4v c = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            if (!(gm & (3u << (4 + 2 * kk)))) continue;
+            c = Split16<T>::mfma(bh[kk], dh[i][kk], c);
+            c = Split16<T>::mfma(bh[kk], dl[i][kk], c);
+            c = Split16<T>::mfma(bl[kk], dh[i][kk], c);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q * FSTR + i * 16] = c[q];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// rho_g (Eq. 3), mixed precision: canonical pairs, weight 2 off the self pair
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+    typedef typename Split16<T>::vec vec;
+    __shared__ __attribute__((aligned(16))) T tB[2][GINT_BCPTS][RSTR];
+    __shared__ float pA[GINT_BCPTS * FSTR];
+    __shared__ float psi[GINT_BCPTS * FSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ float part[4][GINT_BCPTS];
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    double *rho = rho0 + SY.g_off;
+    const int lane = threadIdx.x & 63, w = wave_idx();
+    vec dh[4][2], dl[4][2];
+    load_dsym16<T>(P, pr, D, dh, dl);
+    const double weight = pr.self ? 1.0 : 2.0;
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        stage_rho<T, true>(P, pr, o, tB, pA, maskpt);
+        __syncthreads();
+        psi_mx<T>(dh, dl, tB, psi, maskpt);
+        __syncthreads();
+        {
+            float v = 0.f;
+            if (maskpt[lane] & (1u << w)) {
+                const float *a = pA + lane * FSTR + w * 16;
+                const float *s = psi + lane * FSTR + w * 16;
+#pragma unroll
+                for (int mu = 0; mu < 16; ++mu) v += a[mu] * s[mu];
+            }
+            part[w][lane] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < GINT_BCPTS) {
+            const int pt = threadIdx.x;
+            const unsigned m = maskpt[pt];
+            if ((m & 0xFu) && (m & 0xF0u)) {
+                const double v = (double)part[0][pt] + (double)part[1][pt] + (double)part[2][pt] + (double)part[3][pt];
+                const P3 r = point_of(P, o, pt);
+                atomicAdd(rho + r.g, weight * v);
+            }
+        }
+        __syncthreads();
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pulay force and strain derivative (Eq. 4-5), mixed precision: ordered
+// pairs, A side; FP32 per-point terms, FP64 accumulation.
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__restrict__ V0,
+                                                     const double *__restrict__ D, double *__restrict__ F,
+                                                     double *__restrict__ ZE0) {
+    typedef typename Split16<T>::vec vec;
+    __shared__ __attribute__((aligned(16))) T tB[2][GINT_BCPTS][RSTR];
+    __shared__ float psi[GINT_BCPTS * FSTR];
+    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ double red[4][10];
+    __shared__ int s_item;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = P0.items[item_];
+    const GPair &pr = P0.pairs[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    const GSys &SY = P0.sys[pr.sys];
+    const double *V = V0 + SY.g_off;
+    double *ZE = ZE0 + 10 * pr.sys;
+    const int lane = threadIdx.x & 63, w = wave_idx();
+    vec dh[4][2], dl[4][2];
+    load_dsym16<T>(P, pr, D, dh, dl);
+    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
+    const int aw = pr.a[w];
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = P.bigcells[it.bc_begin + bc];
+        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        __syncthreads();
+        stage_rho<T, false>(P, pr, o, tB, nullptr, maskpt);
+        __syncthreads();
+        psi_mx<T>(dh, dl, tB, psi, maskpt);
+        __syncthreads();
+        if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+            const P3 r = point_of(P, o, lane);
+            const GAtom at = P.atoms[aw];
+            const double dx = r.x - at.x - pr.shiftA[0], dy = r.y - at.y - pr.shiftA[1],
+                         dz = r.z - at.z - pr.shiftA[2];
+            const float x = (float)dx, y = (float)dy, zz = (float)dz;
+            float e, G[3];
+            dot_grad32(P.species[at.species], P.tab32, x, y, zz, (float)(dx * dx + dy * dy + dz * dz),
+                       psi + lane * FSTR + w * 16, e, G);
+            const double wv = P.w * V[r.g];
+            const double c = 2.0 * wv;
+            const double g0 = G[0], g1 = G[1], g2 = G[2];
+            f[0] += c * g0;
+            f[1] += c * g1;
+            f[2] += c * g2;
+            const double gs[3] = {g0, g1, g2}, xs[3] = {dx, dy, dz};
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b) z[3 * a + b] += c * gs[a] * xs[b];
+            en += wv * (double)e;
+        }
+        __syncthreads();
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) f[a] += __shfl_xor(f[a], off);
+#pragma unroll
+        for (int a = 0; a < 9; ++a) z[a] += __shfl_xor(z[a], off);
+        en += __shfl_xor(en, off);
+    }
+    if (lane == 0) {
+        if (aw >= 0) {
+            atomicAdd(F + 3 * aw + 0, f[0]);
+            atomicAdd(F + 3 * aw + 1, f[1]);
+            atomicAdd(F + 3 * aw + 2, f[2]);
+        }
+#pragma unroll
+        for (int a = 0; a < 9; ++a) red[w][a] = z[a];
+        red[w][9] = en;
+    }
+    __syncthreads();
+    if (threadIdx.x < 10) {
+        const int k = threadIdx.x;
+        atomicAdd(ZE + k, red[0][k] + red[1][k] + red[2][k] + red[3][k]);
+    }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int gint_persistent_grid(const void *kernel, int nitems);
+hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
+
+template <class K, class... Args>
+static hipError_t launch_persistent(K kernel, const GDev &P, hipStream_t s, Args... args) {
+    if (P.nitems <= 0) return hipSuccess;
+    hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
+    if (e != hipSuccess) return e;
+    const int grid = gint_persistent_grid((const void *)kernel, P.nitems);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, s, P, args...);
+    return hipGetLastError();
+}
+
+hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, double *H, hipStream_t s) {
+    return prec == 2 ? launch_persistent(k_vlocal_mx<__bf16>, P, s, V, H)
+                     : launch_persistent(k_vlocal_mx<_Float16>, P, s, V, H);
+}
+
+hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s) {
+    return prec == 2 ? launch_persistent(k_rho_mx<__bf16>, P, s, D, rho)
+                     : launch_persistent(k_rho_mx<_Float16>, P, s, D, rho);
+}
+
+hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
+                                hipStream_t s) {
+    return prec == 2 ? launch_persistent(k_force_mx<__bf16>, P, s, V, D, F, ZE)
+                     : launch_persistent(k_force_mx<_Float16>, P, s, V, D, F, ZE);
+}
+
+int gint_resident_blocks(const void *kernel);
+
+void gint_prime_grids_mx(int prec) {
+    if (prec == 2) {
+        gint_resident_blocks((const void *)k_vlocal_mx<__bf16>);
+        gint_resident_blocks((const void *)k_rho_mx<__bf16>);
+        gint_resident_blocks((const void *)k_force_mx<__bf16>);
+    } else {
+        gint_resident_blocks((const void *)k_vlocal_mx<_Float16>);
+        gint_resident_blocks((const void *)k_rho_mx<_Float16>);
+        gint_resident_blocks((const void *)k_force_mx<_Float16>);
+    }
+}

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <thread>
+#include <string>
 #include <unordered_map>
 
 namespace {
@@ -115,7 +116,7 @@ struct PairOut {
 
 }  // namespace
 
-int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPlan &hp) {
+static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &hp) {
     auto fail = [&](int code, const char *msg) {
         hp.error = msg;
         return code;
@@ -123,7 +124,7 @@ int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPl
     if (!sys) return fail(GINT_EINVAL, "null system");
     const int cl = (opt && opt->cluster_atoms > 0) ? opt->cluster_atoms : GINT_CL;
     if (cl < 1 || cl > GINT_CL) return fail(GINT_EINVAL, "cluster_atoms out of range");
-    const int maxbc = (opt && opt->max_bigcells_per_item > 0) ? opt->max_bigcells_per_item : 512;
+    const int maxbc_opt = (opt && opt->max_bigcells_per_item > 0) ? opt->max_bigcells_per_item : 0;
     hp.cluster_atoms = cl;
     if (sys->natom < 1 || !sys->pos || !sys->species) return fail(GINT_EINVAL, "bad atoms");
     if (sys->nspecies < 1 || sys->nspecies > GINT_MAXSPECIES || !sys->species_list)
@@ -189,6 +190,7 @@ int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPl
         hp.species.push_back(g);
     }
     if (hp.tab.size() > (size_t)0x7fffffff) return fail(GINT_EINVAL, "radial tables too large");
+    hp.tab32.assign(hp.tab.begin(), hp.tab.end());
 
     // ---- atoms
     const int natom = sys->natom;
@@ -431,18 +433,35 @@ int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPl
         hp.pairs.push_back(S);
     }
 
-    // ---- work items: runs of at most maxbc bigcells, longest first
+    // ---- work items: runs of at most maxbc bigcells, longest first.  With
+    // enough pairs to fill the GPU several times over, a pair is one item
+    // (exclusive: its H blocks are written with plain stores); otherwise long
+    // pairs are split for load balance.
+    long long total_bc = 0;
+    int longest = 0;
+    for (int p = 0; p < hp.ncanon; ++p) {
+        total_bc += ranges[p].second;
+        longest = std::max(longest, ranges[p].second);
+    }
+    int maxbc = maxbc_opt;
+    if (maxbc <= 0) {
+        const long long slots = 2048;    // resident workgroups of a large GPU, with margin
+        const long long per_slot = (total_bc + slots - 1) / slots;
+        maxbc = (int)std::max<long long>(64, std::min<long long>(std::max<long long>(per_slot, 64), 1LL << 30));
+        if (longest <= per_slot * 2) maxbc = std::max(maxbc, longest);
+    }
     hp.items_canon.clear();
     hp.items_ordered.clear();
     for (int p = 0; p < hp.ncanon; ++p) {
         const int beg = ranges[p].first, cnt = ranges[p].second;
         const int nchunk = (cnt + maxbc - 1) / maxbc;
+        const int excl = nchunk == 1 ? 1 : 0;
         for (int c = 0; c < nchunk; ++c) {
             const int b0 = beg + (int)((long long)cnt * c / nchunk);
             const int b1 = beg + (int)((long long)cnt * (c + 1) / nchunk);
-            hp.items_canon.push_back({p, b0, b1 - b0, 0});
-            hp.items_ordered.push_back({p, b0, b1 - b0, 0});
-            if (swapped_of[p] >= 0) hp.items_ordered.push_back({swapped_of[p], b0, b1 - b0, 0});
+            hp.items_canon.push_back({p, b0, b1 - b0, excl});
+            hp.items_ordered.push_back({p, b0, b1 - b0, excl});
+            if (swapped_of[p] >= 0) hp.items_ordered.push_back({swapped_of[p], b0, b1 - b0, excl});
         }
     }
     auto longer = [](const GItem &x, const GItem &y) {
@@ -452,5 +471,109 @@ int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPl
     };
     std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
     std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
+    return GINT_OK;
+}
+
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, HostPlan &hp) {
+    if (!sys || n_sys < 1) {
+        hp.error = "no systems";
+        return GINT_EINVAL;
+    }
+    hp = HostPlan();
+    long long g_off = 0, nnz_off = 0;
+    int atom_off = 0, species_off = 0, nitems_ordered = 0;
+    long long tab_off = 0;
+    for (int i = 0; i < n_sys; ++i) {
+        HostPlan one;
+        const int rc = build_one(sys + i, opt, one);
+        if (rc != GINT_OK) {
+            hp.error = "system " + std::to_string(i) + ": " + one.error;
+            return rc;
+        }
+        GSys S{};
+        for (int k = 0; k < 3; ++k) {
+            S.N[k] = one.N[k];
+            for (int m = 0; m < 3; ++m) S.e[k][m] = one.e[k][m];
+        }
+        S.natom = one.natom;
+        S.w = one.w;
+        S.volume = one.omega;
+        S.g_off = g_off;
+        S.nnz_off = nnz_off;
+        S.atom_off = atom_off;
+        if (i == 0) {
+            for (int k = 0; k < 3; ++k) hp.N[k] = one.N[k];
+            std::memcpy(hp.e, one.e, sizeof(hp.e));
+            std::memcpy(hp.cell, one.cell, sizeof(hp.cell));
+            hp.w = one.w;
+            hp.omega = one.omega;
+            hp.cluster_atoms = one.cluster_atoms;
+        }
+        hp.sys.push_back(S);
+        for (GSpecies sp : one.species) {
+            sp.tab_off += (int)tab_off;
+            hp.species.push_back(sp);
+        }
+        hp.tab.insert(hp.tab.end(), one.tab.begin(), one.tab.end());
+        hp.tab32.insert(hp.tab32.end(), one.tab32.begin(), one.tab32.end());
+        for (GAtom at : one.atoms) {
+            at.species += species_off;
+            hp.atoms.push_back(at);
+        }
+        const int pair_off = (int)hp.pairs.size();
+        const int bc_off = (int)hp.bigcells.size();
+        if (hp.bigcells.size() + one.bigcells.size() > (size_t)0x7fffffff) {
+            hp.error = "too many bigcells";
+            return GINT_ENOMEM;
+        }
+        for (GPair P : one.pairs) {
+            for (int k = 0; k < GINT_CL; ++k) {
+                if (P.a[k] >= 0) P.a[k] += atom_off;
+                if (P.b[k] >= 0) P.b[k] += atom_off;
+            }
+            for (int k = 0; k < GINT_CL * GINT_CL; ++k) {
+                if (P.hoff[k] >= 0) P.hoff[k] += nnz_off;
+                if (P.hoff_t[k] >= 0) P.hoff_t[k] += nnz_off;
+            }
+            P.sys = i;
+            hp.pairs.push_back(P);
+        }
+        hp.bigcells.insert(hp.bigcells.end(), one.bigcells.begin(), one.bigcells.end());
+        for (GItem it : one.items_canon) {
+            it.pair += pair_off;
+            it.bc_begin += bc_off;
+            hp.items_canon.push_back(it);
+        }
+        for (GItem it : one.items_ordered) {
+            it.pair += pair_off;
+            it.bc_begin += bc_off;
+            hp.items_ordered.push_back(it);
+        }
+        nitems_ordered += (int)one.items_ordered.size();
+        hp.ncanon += one.ncanon;
+        hp.ncluster += one.ncluster;
+        hp.natom += one.natom;
+        hp.ngrid += one.ngrid;
+        hp.nnz += one.nnz;
+        g_off += one.ngrid;
+        nnz_off += one.nnz;
+        atom_off += one.natom;
+        species_off += (int)one.species.size();
+        tab_off += (long long)one.tab.size();
+        if (tab_off > 0x7fffffffLL) {
+            hp.error = "radial tables too large";
+            return GINT_EINVAL;
+        }
+    }
+    (void)nitems_ordered;
+    if (n_sys > 1) {
+        auto longer = [](const GItem &x, const GItem &y) {
+            if (x.bc_count != y.bc_count) return x.bc_count > y.bc_count;
+            if (x.pair != y.pair) return x.pair < y.pair;
+            return x.bc_begin < y.bc_begin;
+        };
+        std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
+        std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
+    }
     return GINT_OK;
 }

@@ -13,10 +13,12 @@ struct HostPlan {
     std::vector<GSpecies> species;
     std::vector<GAtom> atoms;
     std::vector<double> tab;
+    std::vector<float> tab32;
     std::vector<GPair> pairs;        // [0, ncanon): canonical; [ncanon, ..): swapped copies
     std::vector<GBig> bigcells;
     std::vector<GItem> items_canon;  // canonical pairs, longest first
     std::vector<GItem> items_ordered;// canonical + swapped, longest first
+    std::vector<GSys> sys;           // one per system
     int ncanon = 0;
     int ncluster = 0;
     int natom = 0;
@@ -31,5 +33,6 @@ struct HostPlan {
     std::string error;
 };
 
+// Builds the plan of n_sys systems (their work items merged into one queue).
 // Returns GINT_OK or a negative gint error code (hp.error holds a message).
-int gint_build_host_plan(const gint_system *sys, const gint_options *opt, HostPlan &hp);
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, HostPlan &hp);

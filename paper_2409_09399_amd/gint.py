@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libgint.so")
 
 GINT_OK, GINT_EINVAL, GINT_EPATTERN, GINT_ENOMEM, GINT_EHIP, GINT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-GINT_FP64 = 0
+GINT_FP64, GINT_MIXED_FP16X3, GINT_MIXED_BF16X3 = 0, 1, 2
 
 
 class GintError(RuntimeError):
@@ -49,11 +49,27 @@ class gint_sizes(C.Structure):
     _fields_ = [("ngrid", C.c_int64), ("nnz", C.c_int64), ("natom", C.c_int), ("ncluster", C.c_int),
                 ("npairs", C.c_int64), ("nitems", C.c_int64), ("nbigcells", C.c_int64),
                 ("work_units", C.c_double), ("volume", C.c_double), ("device_bytes", C.c_int64),
-                ("build_seconds", C.c_double)]
+                ("precision", C.c_int), ("build_seconds", C.c_double), ("n_sys", C.c_int)]
+
+
+class gint_system_sizes(C.Structure):
+    _fields_ = [("g_off", C.c_int64), ("ngrid", C.c_int64), ("nnz_off", C.c_int64), ("nnz", C.c_int64),
+                ("atom_off", C.c_int), ("natom", C.c_int), ("grid", C.c_int * 3), ("volume", C.c_double)]
+
+
+GINT_TUNE_MAX = 16
+
+
+class gint_tune_report(C.Structure):
+    _fields_ = [("ntrials", C.c_int), ("best", C.c_int), ("cluster_atoms", C.c_int * GINT_TUNE_MAX),
+                ("max_bigcells_per_item", C.c_int * GINT_TUNE_MAX), ("step_ms", C.c_double * GINT_TUNE_MAX),
+                ("seconds", C.c_double)]
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
-            "gint_plan_query", "gint_plan_destroy", "gint_strerror", "gint_last_hip_error"]
+            "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
+            "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
+            "gint_last_hip_error"]
 
 
 def _hip_runtimes():
@@ -92,13 +108,20 @@ def _load():
     lib.gint_force_stress.argtypes = [P, P, P, P, P, P, P]
     lib.gint_work_units.argtypes = [P, P, P]
     lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
+    lib.gint_plan_query_system.argtypes = [P, C.c_int, C.POINTER(gint_system_sizes)]
     lib.gint_plan_destroy.argtypes = [P]
     lib.gint_plan_destroy.restype = None
+    lib.gint_graph_create.argtypes = [C.POINTER(C.c_void_p)] + [P] * 9
+    lib.gint_graph_launch.argtypes = [P, P]
+    lib.gint_graph_destroy.argtypes = [P]
+    lib.gint_graph_destroy.restype = None
+    lib.gint_autotune.argtypes = [C.POINTER(gint_system), C.c_int, C.POINTER(gint_options), C.c_double, P,
+                                  C.POINTER(gint_tune_report)]
     lib.gint_strerror.argtypes = [C.c_int]
     lib.gint_strerror.restype = C.c_char_p
     lib.gint_last_hip_error.argtypes = []
     for name in EXPORTED:
-        if name not in ("gint_plan_destroy", "gint_strerror"):
+        if name not in ("gint_plan_destroy", "gint_strerror", "gint_graph_destroy"):
             getattr(lib, name).restype = C.c_int
     return lib
 
@@ -131,61 +154,85 @@ def _dev_ptr(t, n: int, name: str):
     return C.c_void_p(t.data_ptr())
 
 
+def _marshal_system(s, keep):
+    def arr(x, dt):
+        a = np.ascontiguousarray(np.asarray(x), dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.c_void_p)
+
+    sps = (gint_species * len(s.species_list))()
+    keep.append(sps)
+    for k, sp in enumerate(s.species_list):
+        sps[k].rcut = sp.rcut
+        sps[k].dr = sp.dr
+        sps[k].nknots = sp.nknots
+        sps[k].nchan = sp.nchan
+        sps[k].chan_l = arr(sp.ls, np.int32)
+        sps[k].f = arr(sp.f, np.float64)
+        sps[k].fp = arr(sp.fp, np.float64)
+    st = gint_system()
+    cell = np.ascontiguousarray(s.cell, dtype=np.float64).ravel()
+    for k in range(9):
+        st.cell[k] = float(cell[k])
+    st.natom = int(s.pos.shape[0])
+    st.pos = arr(s.pos, np.float64)
+    st.species = arr(s.species, np.int32)
+    st.nspecies = len(s.species_list)
+    st.species_list = C.cast(sps, C.c_void_p)
+    for k in range(3):
+        st.grid[k] = int(s.grid[k])
+    st.nblk = int(s.blk_i.shape[0])
+    st.blk_i = arr(s.blk_i, np.int32)
+    st.blk_j = arr(s.blk_j, np.int32)
+    st.blk_r = arr(s.blk_r, np.int32)
+    st.blk_off = arr(s.blk_off, np.int64)
+    return st
+
+
+def _marshal_batch(system):
+    batch = list(system) if isinstance(system, (list, tuple)) else [system]
+    if not batch:
+        raise ValueError("empty batch")
+    keep = []
+    sts = (gint_system * len(batch))()
+    for i, s in enumerate(batch):
+        sts[i] = _marshal_system(s, keep)
+    return sts, keep, len(batch)
+
+
 class Plan:
-    """A gint plan for one system (paper_2409_09399_amd.inputs.System or any
-    object with the same fields), built on the current HIP device."""
+    """A gint plan for one system or a batch of systems
+    (paper_2409_09399_amd.inputs.System or any object with the same fields),
+    built on the current HIP device.  A batch uses packed buffers; the slices
+    of system i are given by `systems[i]` (dicts of offsets and sizes)."""
 
     def __init__(self, system, cluster_atoms: int = 0, max_bigcells_per_item: int = 0,
                  precision: int = GINT_FP64, stream=None):
-        s = system
-        keep = []
-
-        def arr(x, dt):
-            a = np.ascontiguousarray(np.asarray(x), dtype=dt)
-            keep.append(a)
-            return a.ctypes.data_as(C.c_void_p)
-
-        sps = (gint_species * len(s.species_list))()
-        for k, sp in enumerate(s.species_list):
-            sps[k].rcut = sp.rcut
-            sps[k].dr = sp.dr
-            sps[k].nknots = sp.nknots
-            sps[k].nchan = sp.nchan
-            sps[k].chan_l = arr(sp.ls, np.int32)
-            sps[k].f = arr(sp.f, np.float64)
-            sps[k].fp = arr(sp.fp, np.float64)
-        st = gint_system()
-        cell = np.ascontiguousarray(s.cell, dtype=np.float64).ravel()
-        for k in range(9):
-            st.cell[k] = float(cell[k])
-        st.natom = int(s.pos.shape[0])
-        st.pos = arr(s.pos, np.float64)
-        st.species = arr(s.species, np.int32)
-        st.nspecies = len(s.species_list)
-        st.species_list = C.cast(sps, C.c_void_p)
-        for k in range(3):
-            st.grid[k] = int(s.grid[k])
-        st.nblk = int(s.blk_i.shape[0])
-        st.blk_i = arr(s.blk_i, np.int32)
-        st.blk_j = arr(s.blk_j, np.int32)
-        st.blk_r = arr(s.blk_r, np.int32)
-        st.blk_off = arr(s.blk_off, np.int64)
+        sts, keep, n = _marshal_batch(system)
         opt = gint_options()
         opt.precision = precision
         opt.cluster_atoms = cluster_atoms
         opt.max_bigcells_per_item = max_bigcells_per_item
         ptr = C.c_void_p()
-        rc = _lib.gint_plan_create(C.byref(ptr), C.byref(st), 1, C.byref(opt),
+        rc = _lib.gint_plan_create(C.byref(ptr), sts, n, C.byref(opt),
                                    _stream(stream) if stream is not None else None)
         _check(rc, "gint_plan_create")
         self._p = ptr
         q = gint_sizes()
         _check(_lib.gint_plan_query(self._p, C.byref(q)), "gint_plan_query")
         self.sizes = q
+        self.n_sys = int(q.n_sys)
         self.natom = int(q.natom)
         self.ngrid = int(q.ngrid)
         self.nnz = int(q.nnz)
         self.volume = float(q.volume)
+        self.systems = []
+        for i in range(self.n_sys):
+            ss = gint_system_sizes()
+            _check(_lib.gint_plan_query_system(self._p, i, C.byref(ss)), "gint_plan_query_system")
+            self.systems.append({"g_off": int(ss.g_off), "ngrid": int(ss.ngrid), "nnz_off": int(ss.nnz_off),
+                                 "nnz": int(ss.nnz), "atom_off": int(ss.atom_off), "natom": int(ss.natom),
+                                 "grid": tuple(int(x) for x in ss.grid), "volume": float(ss.volume)})
 
     def close(self):
         if getattr(self, "_p", None):
@@ -209,17 +256,69 @@ def gint_vlocal(plan: Plan, v_loc, h_vals, stream=None):
 
 
 def gint_rho(plan: Plan, d_vals, rho, n_elec=None, stream=None):
-    ne = _dev_ptr(n_elec, 1, "n_elec") if n_elec is not None else None
+    ne = _dev_ptr(n_elec, plan.n_sys, "n_elec") if n_elec is not None else None
     _check(_lib.gint_rho(plan._p, _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(rho, plan.ngrid, "rho"), ne,
                          _stream(stream)), "gint_rho")
 
 
 def gint_force_stress(plan: Plan, v_loc, d_vals, force, stress, energy=None, stream=None):
-    en = _dev_ptr(energy, 1, "energy") if energy is not None else None
+    en = _dev_ptr(energy, plan.n_sys, "energy") if energy is not None else None
     _check(_lib.gint_force_stress(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"),
                                   _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(force, 3 * plan.natom, "force"),
-                                  _dev_ptr(stress, 9, "stress"), en, _stream(stream)), "gint_force_stress")
+                                  _dev_ptr(stress, 9 * plan.n_sys, "stress"), en, _stream(stream)), "gint_force_stress")
 
 
 def gint_work_units(plan: Plan, w_out, stream=None):
-    _check(_lib.gint_work_units(plan._p, _dev_ptr(w_out, 1, "w_out"), _stream(stream)), "gint_work_units")
+    _check(_lib.gint_work_units(plan._p, _dev_ptr(w_out, plan.n_sys, "w_out"), _stream(stream)), "gint_work_units")
+
+
+class Graph:
+    """One captured step of a plan (gint_graph_create): Vlocal into h_vals,
+    rho (and n_elec) into rho, force/stress (and energy) into force/stress,
+    each stage present when its output is given.  Keeps the buffers alive."""
+
+    def __init__(self, plan: Plan, v_loc=None, d_vals=None, h_vals=None, rho=None, n_elec=None, force=None,
+                 stress=None, energy=None):
+        n = plan.n_sys
+        args = [_dev_ptr(v_loc, plan.ngrid, "v_loc") if v_loc is not None else None,
+                _dev_ptr(d_vals, plan.nnz, "d_vals") if d_vals is not None else None,
+                _dev_ptr(h_vals, plan.nnz, "h_vals") if h_vals is not None else None,
+                _dev_ptr(rho, plan.ngrid, "rho") if rho is not None else None,
+                _dev_ptr(n_elec, n, "n_elec") if n_elec is not None else None,
+                _dev_ptr(force, 3 * plan.natom, "force") if force is not None else None,
+                _dev_ptr(stress, 9 * n, "stress") if stress is not None else None,
+                _dev_ptr(energy, n, "energy") if energy is not None else None]
+        self._keep = (plan, v_loc, d_vals, h_vals, rho, n_elec, force, stress, energy)
+        ptr = C.c_void_p()
+        _check(_lib.gint_graph_create(C.byref(ptr), plan._p, *args), "gint_graph_create")
+        self._g = ptr
+
+    def launch(self, stream=None):
+        _check(_lib.gint_graph_launch(self._g, _stream(stream)), "gint_graph_launch")
+
+    def close(self):
+        if getattr(self, "_g", None):
+            _lib.gint_graph_destroy(self._g)
+            self._g = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(system, precision: int = GINT_FP64, budget_seconds: float = 2.0, stream=None):
+    """Pick cluster_atoms and max_bigcells_per_item by timed trials
+    (gint_autotune).  Returns (options dict for Plan, report dict)."""
+    sts, keep, n = _marshal_batch(system)
+    opt = gint_options()
+    opt.precision = precision
+    rep = gint_tune_report()
+    _check(_lib.gint_autotune(sts, n, C.byref(opt), float(budget_seconds), _stream(stream), C.byref(rep)),
+           "gint_autotune")
+    trials = [{"cluster_atoms": rep.cluster_atoms[k], "max_bigcells_per_item": rep.max_bigcells_per_item[k],
+               "step_ms": rep.step_ms[k]} for k in range(rep.ntrials)]
+    return ({"cluster_atoms": int(opt.cluster_atoms), "max_bigcells_per_item": int(opt.max_bigcells_per_item),
+             "precision": precision},
+            {"trials": trials, "best": int(rep.best), "seconds": float(rep.seconds)})

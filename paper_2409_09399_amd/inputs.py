@@ -246,23 +246,17 @@ def build_pattern(cell, pos, rcut_atom, skin: float = 0.5):
     rr = np.stack(np.meshgrid(*[np.arange(-n, n + 1) for n in nr], indexing="ij"), -1).reshape(-1, 3)
     shifts = rr @ cell
     img = (pos[None, :, :] + shifts[:, None, :]).reshape(-1, 3)
-    tree = cKDTree(img)
-    out_i, out_j, out_r = [], [], []
-    hits = tree.query_ball_point(pos, reach)
-    for i in range(natom):
-        h = np.asarray(hits[i], dtype=np.int64)
-        if h.size == 0:
-            continue
-        j = h % natom
-        r = rr[h // natom]
-        dist = np.linalg.norm(img[h] - pos[i], axis=1)
-        keep = dist < rcut_atom[i] + rcut_atom[j] + skin
-        out_i.append(np.full(int(keep.sum()), i))
-        out_j.append(j[keep])
-        out_r.append(r[keep])
-    bi = np.concatenate(out_i).astype(np.int32)
-    bj = np.concatenate(out_j).astype(np.int32)
-    br = np.concatenate(out_r).astype(np.int32)
+    pairs = cKDTree(pos).query_ball_tree(cKDTree(img), reach)
+    cnt = np.fromiter((len(h) for h in pairs), dtype=np.int64, count=natom)
+    i = np.repeat(np.arange(natom, dtype=np.int64), cnt)
+    h = np.fromiter((x for hh in pairs for x in hh), dtype=np.int64, count=int(cnt.sum()))
+    j = h % natom
+    r = rr[h // natom]
+    dist = np.linalg.norm(img[h] - pos[i], axis=1)
+    keep = dist < rcut_atom[i] + rcut_atom[j] + skin
+    bi = i[keep].astype(np.int32)
+    bj = j[keep].astype(np.int32)
+    br = r[keep].astype(np.int32)
     order = np.lexsort((br[:, 2], br[:, 1], br[:, 0], bj, bi))
     return bi[order], bj[order], br[order]
 
@@ -287,25 +281,60 @@ def block_index(bi, bj, br) -> dict:
             for k, (i, j, r) in enumerate(zip(bi, bj, br))}
 
 
+def _block_keys(bi, bj, br, natom: int, m: int) -> np.ndarray:
+    """int64 keys that sort like (I, J, R) lexicographically, for |R_i| <= m."""
+    base = 2 * m + 1
+    if float(natom) ** 2 * float(base) ** 3 >= 2.0 ** 62:
+        raise ValueError("pattern too large for int64 block keys")
+    k = bi.astype(np.int64) * natom + bj.astype(np.int64)
+    for c in range(3):
+        k = k * base + (br[:, c].astype(np.int64) + m)
+    return k
+
+
+def transpose_index(bi, bj, br, natom: int) -> np.ndarray:
+    """For each block (I, J, R) the index of (J, I, -R); -1 if absent.
+    Blocks must be in (I, J, R) lexicographic order."""
+    m = int(np.abs(br).max()) if br.size else 0
+    keys = _block_keys(bi, bj, br, natom, m)
+    kt = _block_keys(bj, bi, -br, natom, m)
+    pos = np.searchsorted(keys, kt)
+    pos = np.minimum(pos, keys.shape[0] - 1)
+    return np.where(keys[pos] == kt, pos, -1)
+
+
 def random_density_matrix(cell, pos, bi, bj, br, off, norb_atom, rng, decay=3.0):
     """D_IJR[mu,nu] = u exp(-|d_IJR|/decay), u ~ U[-1/2, 1/2], drawn on the
-    canonical half and transposed into the other half; the (I,I,0) blocks are
-    symmetrised and get +1 on the diagonal.  Satisfies D_JI(-R) = D_IJR^T."""
+    canonical half (block by block in pattern order, each row-major) and
+    transposed into the other half; the (I,I,0) blocks are symmetrised and
+    get +1 on the diagonal.  Satisfies D_JI(-R) = D_IJR^T."""
+    natom = pos.shape[0]
     nnz = int(off[-1] + norb_atom[bi[-1]] * norb_atom[bj[-1]])
     d = np.zeros(nnz)
-    idx = block_index(bi, bj, br)
-    canon = _canonical(bi, bj, br)
-    for k in np.nonzero(canon)[0]:
-        i, j, r = int(bi[k]), int(bj[k]), br[k]
-        ni, nj = int(norb_atom[i]), int(norb_atom[j])
-        dist = float(np.linalg.norm(pos[j] + r @ cell - pos[i]))
-        blk = rng.uniform(-0.5, 0.5, size=(ni, nj)) * math.exp(-dist / decay)
-        if i == j and not r.any():
-            blk = 0.5 * (blk + blk.T) + np.eye(ni)
-        d[off[k]:off[k] + ni * nj] = blk.ravel()
-        kt = idx[(j, i, -int(r[0]), -int(r[1]), -int(r[2]))]
-        if kt != k:
-            d[off[kt]:off[kt] + ni * nj] = blk.T.ravel()
+    tr = transpose_index(bi, bj, br, natom)
+    if np.any(tr < 0):
+        raise ValueError("pattern is not transpose-closed")
+    ks = np.nonzero(_canonical(bi, bj, br))[0]
+    ni = norb_atom[bi[ks]].astype(np.int64)
+    nj = norb_atom[bj[ks]].astype(np.int64)
+    size = ni * nj
+    ustart = np.zeros(ks.shape[0], dtype=np.int64)
+    ustart[1:] = np.cumsum(size)[:-1]
+    u = rng.uniform(-0.5, 0.5, size=int(size.sum()))
+    dist = np.linalg.norm(pos[bj[ks]] + br[ks] @ cell - pos[bi[ks]], axis=1)
+    fac = np.exp(-dist / decay)
+    onsite = (bi[ks] == bj[ks]) & ~np.any(br[ks] != 0, axis=1)
+    for a, b in sorted(set(zip(ni.tolist(), nj.tolist()))):
+        sel = np.nonzero((ni == a) & (nj == b))[0]
+        blk = u[ustart[sel][:, None] + np.arange(a * b)[None, :]].reshape(-1, a, b) * fac[sel][:, None, None]
+        if a == b:
+            on = onsite[sel]
+            if on.any():
+                blk[on] = 0.5 * (blk[on] + np.swapaxes(blk[on], 1, 2)) + np.eye(a)
+        k = ks[sel]
+        d[off[k][:, None] + np.arange(a * b)[None, :]] = blk.reshape(-1, a * b)
+        kt = tr[k]
+        d[off[kt][:, None] + np.arange(a * b)[None, :]] = np.swapaxes(blk, 1, 2).reshape(-1, a * b)
     return d
 
 
@@ -406,23 +435,20 @@ def random_molecular_crystal(seed: int, natom: Optional[int] = None, nmin: int =
         natom = int(rng.integers(nmin, nmax + 1))
     L = (vol_per_atom * natom) ** (1.0 / 3.0)
     cell = np.eye(3) * L
-    pos = []
+    placed = np.zeros((natom, 3))
+    n = 0
     tries = 0
-    while len(pos) < natom:
+    while n < natom:
         tries += 1
         if tries > 200000:
             raise RuntimeError("could not place atoms")
         p = rng.uniform(0, L, size=3)
-        ok = True
-        for q in pos:
-            dvec = p - q
-            dvec -= L * np.round(dvec / L)
-            if dvec @ dvec < min_sep * min_sep:
-                ok = False
-                break
-        if ok:
-            pos.append(p)
-    pos = np.array(pos)
+        dvec = p[None, :] - placed[:n]
+        dvec -= L * np.round(dvec / L)
+        if n == 0 or np.min(np.einsum("ij,ij->i", dvec, dvec)) >= min_sep * min_sep:
+            placed[n] = p
+            n += 1
+    pos = placed
     kinds = rng.choice(3, size=natom, p=[0.4, 0.4, 0.2])   # 0=C, 1=H, 2=O
     species_list = [make_species("C", "2s2p1d", 7.0, dr, rng),
                     make_species("H", "2s1p", 6.0, dr, rng),
@@ -436,13 +462,22 @@ def random_molecular_crystal(seed: int, natom: Optional[int] = None, nmin: int =
                     name=f"molcrystal{natom}_seed{seed}")
 
 
-def make_config(k: int, seed: int = 0) -> System:
+def molecular_batch(n: int = 64, seed: int = 0, nmin: int = 40, nmax: int = 600) -> list:
+    """n independent random C/H/O crystals with atom counts uniform in
+    [nmin, nmax] (one seed stream per structure)."""
+    return [random_molecular_crystal(seed * 100003 + 17 * i + 1, nmin=nmin, nmax=nmax) for i in range(n)]
+
+
+def make_config(k: int, seed: int = 0):
     """Named workloads: 1 = jittered diamond (parity), 2 = TBG i=8 (868
-    atoms, 3.89 deg), 5 = TBG i=29 (10,444 atoms, 1.12 deg)."""
+    atoms, 3.89 deg), 3 = batch of 64 random C/H/O crystals of 40-600 atoms
+    (a list of systems), 5 = TBG i=29 (10,444 atoms, 1.12 deg)."""
     if k == 1:
         return diamond8(seed)
     if k == 2:
         return tbg_system(8, seed)
+    if k == 3:
+        return molecular_batch(64, seed)
     if k == 5:
         return tbg_system(29, seed)
     raise ValueError(f"unknown config {k}")

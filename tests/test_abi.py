@@ -108,3 +108,34 @@ def test_rejects_duplicate_and_overlapping_blocks(G):
     assert _create(G, t) == G.GINT_EINVAL
     t = _tiny(); t.blk_off = t.blk_off.copy(); t.blk_off[1] = t.blk_off[0] + 1
     assert _create(G, t) == G.GINT_EINVAL
+
+
+def test_batch_errors_name_the_system(G):
+    """A batch fails as a whole when any system is invalid; nothing is built."""
+    good = _tiny()
+    bad = _tiny(); bad.grid = np.array([8, 8, -1], np.int32)
+    assert _create(G, [good, bad]) == G.GINT_EINVAL
+    bad = _tiny()
+    keep = np.ones(len(bad.blk_i), bool); keep[5] = False
+    bad.blk_i, bad.blk_j, bad.blk_r = bad.blk_i[keep], bad.blk_j[keep], bad.blk_r[keep]
+    bad.blk_off = bad.blk_off[keep]
+    assert _create(G, [good, bad, good]) == G.GINT_EPATTERN
+    with pytest.raises(ValueError):
+        G.Plan([])
+
+
+def test_null_arguments(G):
+    lib = G._lib
+    sts, keep, n = G._marshal_batch(_tiny())
+    opt = G.gint_options()
+    out = C.c_void_p()
+    assert lib.gint_plan_create(C.byref(out), sts, 0, C.byref(opt), None) == G.GINT_EINVAL
+    assert lib.gint_plan_create(None, sts, 1, C.byref(opt), None) == G.GINT_EINVAL
+    assert lib.gint_graph_create(C.byref(out), None, *([None] * 8)) == G.GINT_EINVAL
+    assert lib.gint_graph_launch(None, None) == G.GINT_EINVAL
+    rep = G.gint_tune_report()
+    assert lib.gint_autotune(sts, 1, None, 1.0, None, C.byref(rep)) == G.GINT_EINVAL
+    assert lib.gint_autotune(sts, 1, C.byref(opt), -1.0, None, C.byref(rep)) == G.GINT_EINVAL
+    assert lib.gint_plan_query_system(None, 0, C.byref(G.gint_system_sizes())) == G.GINT_EINVAL
+    lib.gint_graph_destroy(None)
+    lib.gint_plan_destroy(None)

@@ -1,0 +1,203 @@
+"""Batched plans: several independent systems in one plan, one persistent
+launch per call, packed buffers (through the C ABI).
+
+Each system's slice of the packed outputs is compared with the FP64 oracle of
+that system alone, to the plain path's bar (max-norm relative 1e-11; W
+exact).  The 64-structure batch of random C/H/O crystals (40-600 atoms, grids
+32^3-96^3) is checked on sampled outputs the oracle computes one by one, and
+its mixed-precision form against the FP64 batch at the mixed bounds.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-11
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def pack(systems, attr):
+    return np.concatenate([np.asarray(getattr(s, attr), dtype=np.float64).ravel() for s in systems])
+
+
+def run_batch(G, torch, dev, systems, **kw):
+    names = [s.name for s in systems]
+    print(f"[gpu] batch of {len(systems)}: {names[:6]}{'...' if len(names) > 6 else ''} opts={kw}", flush=True)
+    plan = G.Plan(systems, **kw)
+    n = plan.n_sys
+    assert n == len(systems)
+    for s, q in zip(systems, plan.systems):
+        assert q["ngrid"] == s.ngrid and q["nnz"] == s.nnz and q["natom"] == s.natom
+    v = torch.tensor(pack(systems, "v"), device=dev)
+    d = torch.tensor(pack(systems, "d"), device=dev)
+    h = torch.full((plan.nnz,), float("nan"), dtype=torch.float64, device=dev)
+    rho = torch.full((plan.ngrid,), float("nan"), dtype=torch.float64, device=dev)
+    ne = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+    F = torch.full((plan.natom * 3,), float("nan"), dtype=torch.float64, device=dev)
+    sig = torch.full((9 * n,), float("nan"), dtype=torch.float64, device=dev)
+    E = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+    W = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+    G.gint_vlocal(plan, v, h)
+    G.gint_rho(plan, d, rho, ne)
+    G.gint_force_stress(plan, v, d, F, sig, E)
+    G.gint_work_units(plan, W)
+    torch.cuda.synchronize()
+    h, rho, F = h.cpu().numpy(), rho.cpu().numpy(), F.cpu().numpy().reshape(-1, 3)
+    ne, sig, E, W = ne.cpu().numpy(), sig.cpu().numpy().reshape(n, 3, 3), E.cpu().numpy(), W.cpu().numpy()
+    out = []
+    for i, q in enumerate(plan.systems):
+        out.append(dict(h=h[q["nnz_off"]:q["nnz_off"] + q["nnz"]], rho=rho[q["g_off"]:q["g_off"] + q["ngrid"]],
+                        F=F[q["atom_off"]:q["atom_off"] + q["natom"]], sig=sig[i], E=float(E[i]),
+                        ne=float(ne[i]), W=float(W[i])))
+    plan.close()
+    return out
+
+
+def small_batch():
+    from paper_2409_09399_amd import inputs as I
+    rng = np.random.default_rng(11)
+    sp = [I.make_species("X", "spd", 4.1, 0.01, rng), I.make_species("Y", "sp", 3.3, 0.02, rng)]
+    cell = np.array([[5.1, 0.0, 0.0], [1.2, 4.6, 0.0], [0.4, -0.7, 5.5]])
+    grid = (20, 18, 22)
+    v = I.plane_wave_potential(grid, I.random_millers_box(rng, 8, 2), np.full(8, 0.3), rng.uniform(0, 6.28, 8))
+    mixed = I.assemble(cell, rng.uniform(0, 1, size=(4, 3)) @ cell, np.array([0, 1, 1, 0]), sp, grid, v, rng,
+                       name="mixed4")
+    sp1 = I.make_species("C", "2s2p1d", 4.0, 0.01, rng)
+    grid1 = (24, 24, 24)
+    v1 = I.plane_wave_potential(grid1, I.random_millers_box(rng, 6, 2), np.full(6, 0.5), rng.uniform(0, 6, 6))
+    one = I.assemble(np.eye(3) * 9.0, np.array([[3.0, 4.5, 6.0]]), np.array([0]), [sp1], grid1, v1, rng,
+                     name="one_atom")
+    return [I.diamond8(1), I.random_molecular_crystal(3, natom=40), mixed, one,
+            I.diamond8(2, grid=(30, 27, 33))]
+
+
+@pytest.fixture(scope="module")
+def small(oracle_mod):
+    systems = small_batch()
+    refs = []
+    for s in systems:
+        o = oracle_mod.Oracle(s)
+        F, Z, E, sig = o.force_stress()
+        rho = o.rho()
+        refs.append(dict(h=o.vlocal(), rho=rho, ne=float(rho.sum()) * s.volume / s.ngrid, F=F, sig=sig, E=E,
+                         W=o.work()))
+    return systems, refs
+
+
+def check(gpu, ref, name):
+    errs = {k: rel(gpu[k], ref[k]) for k in ("h", "rho", "F", "sig")}
+    errs["E"] = abs(gpu["E"] - ref["E"]) / abs(ref["E"])
+    errs["ne"] = abs(gpu["ne"] - ref["ne"]) / abs(ref["ne"])
+    print(f"[gpu] {name} errors {errs}", flush=True)
+    for k, e in errs.items():
+        assert e <= TOL, (name, k, e)
+    assert gpu["W"] == ref["W"], name
+
+
+def test_small_batch_fp64(G_mod, torch_dev, small):
+    """Five systems with different cells, grids (incl. ragged), species sets
+    and sizes (down to one atom) in one plan."""
+    torch, dev = torch_dev
+    systems, refs = small
+    for s, g, r in zip(systems, run_batch(G_mod, torch, dev, systems), refs):
+        check(g, r, s.name)
+
+
+def test_small_batch_options(G_mod, torch_dev, small):
+    """Cluster size and item length do not change a batched result."""
+    torch, dev = torch_dev
+    systems, refs = small
+    for cl, mb in ((3, 5), (1, 0)):
+        for s, g, r in zip(systems, run_batch(G_mod, torch, dev, systems, cluster_atoms=cl,
+                                              max_bigcells_per_item=mb), refs):
+            check(g, r, f"{s.name} cl={cl} mb={mb}")
+
+
+def test_batch_of_one_equals_single(G_mod, torch_dev, small):
+    """A batch equals the same systems planned one by one."""
+    torch, dev = torch_dev
+    systems, _ = small
+    batched = run_batch(G_mod, torch, dev, systems[:3])
+    for s, b in zip(systems[:3], batched):
+        single = run_batch(G_mod, torch, dev, [s])[0]
+        for k in ("h", "rho", "F", "sig"):
+            assert rel(b[k], single[k]) <= 1e-13, (s.name, k)
+        assert b["W"] == single["W"]
+
+
+@pytest.fixture(scope="module")
+def G_mod():
+    from paper_2409_09399_amd import gint
+    return gint
+
+
+@pytest.fixture(scope="module")
+def batch64(G_mod, torch_dev):
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    systems = I.make_config(3)
+    return systems, run_batch(G_mod, torch, dev, systems)
+
+
+def test_batch64_sampled(batch64, oracle_mod):
+    """The 64-structure batch: for 6 systems (smallest, largest and four
+    others), rho at sampled points, sampled H blocks and forces on sampled
+    atoms from the oracle one by one; N_e and E identities on all 64."""
+    systems, out = batch64
+    order = np.argsort([s.natom for s in systems])
+    pick = [order[0], order[-1], order[13], order[27], order[41], order[55]]
+    rng = np.random.default_rng(1)
+    for k in pick:
+        s, g = systems[k], out[k]
+        print(f"[gpu] batch64 sample system {k} natom={s.natom} grid={tuple(int(x) for x in s.grid)}", flush=True)
+        o = oracle_mod.Oracle(s)
+        gi = rng.choice(s.ngrid, 60, replace=False)
+        r_or = o.rho_points(gi)
+        assert np.abs(g["rho"][gi] - r_or).max() <= TOL * np.abs(g["rho"]).max()
+        blks = rng.choice(len(s.blk_i), 8, replace=False)
+        hmax = np.abs(g["h"]).max()
+        for b, ref in zip(blks, o.vlocal_blocks(blks)):
+            got = g["h"][s.blk_off[b]:s.blk_off[b] + ref.size].reshape(ref.shape)
+            assert np.abs(got - ref).max() <= TOL * hmax
+        atoms = rng.choice(s.natom, 2, replace=False)
+        Fo, _ = o.force_atoms(atoms)
+        assert np.abs(g["F"][atoms] - Fo).max() <= TOL * np.abs(g["F"]).max()
+    for s, g in zip(systems, out):
+        w = s.volume / s.ngrid
+        assert abs(float(np.dot(s.d, g["h"])) - g["E"]) <= 1e-11 * abs(g["E"])
+        assert abs(float(np.dot(s.v, g["rho"])) * w - g["E"]) <= 1e-11 * abs(g["E"])
+        assert abs(float(g["rho"].sum()) * w - g["ne"]) <= 1e-11 * abs(g["ne"])
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
+def test_batch64_mixed(G_mod, torch_dev, batch64, prec):
+    """The mixed forms of the 64-structure batch against its FP64 result
+    (itself within 1e-11 of the oracle), at the mixed-precision bounds."""
+    torch, dev = torch_dev
+    systems, ref = batch64
+    got = run_batch(G_mod, torch, dev, systems, precision=prec)
+    bounds = {1: dict(H_abs=1e-6, F_abs=1e-5, rel=1e-5), 2: dict(H_abs=1e-4, F_abs=1e-3, rel=1e-3)}[prec]
+    worst = dict(H_abs=0.0, F_abs=0.0, rho_rel=0.0, sigma_rel=0.0, E_rel=0.0)
+    for g, r in zip(got, ref):
+        worst["H_abs"] = max(worst["H_abs"], float(np.abs(g["h"] - r["h"]).max()))
+        worst["F_abs"] = max(worst["F_abs"], float(np.abs(g["F"] - r["F"]).max()))
+        worst["rho_rel"] = max(worst["rho_rel"], rel(g["rho"], r["rho"]))
+        worst["sigma_rel"] = max(worst["sigma_rel"], rel(g["sig"], r["sig"]))
+        worst["E_rel"] = max(worst["E_rel"], abs(g["E"] - r["E"]) / abs(r["E"]))
+    print(f"[mixed] batch64 prec={prec} worst {worst}", flush=True)
+    assert worst["H_abs"] <= bounds["H_abs"]
+    assert worst["F_abs"] <= bounds["F_abs"]
+    for k in ("rho_rel", "sigma_rel", "E_rel"):
+        assert worst[k] <= bounds["rel"], k

@@ -1,0 +1,108 @@
+"""Mixed-precision forms against the FP64 oracle (through the C ABI).
+
+GINT_MIXED_FP16X3: FP32 orbitals, FP16 hi+lo split operands with three FP16
+MFMA products and FP32 accumulation per bigcell, FP64 across bigcells.
+Targets: |H - H_oracle| <= 1e-6 Ha and |F - F_oracle| <= 1e-5 Ha/Bohr; the
+rho and stress errors are stated (asserted against bounds derived from the
+FP32 evaluation, relative 1e-5 of the max-norm).
+GINT_MIXED_BF16X3 (about 16 significant bits per operand) is checked against
+bounds 100x looser.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch, torch.device("cuda:0")
+
+
+def run(G, torch, dev, s, precision):
+    plan = G.Plan(s, precision=precision)
+    v = torch.tensor(s.v, device=dev)
+    d = torch.tensor(s.d, device=dev)
+    h = torch.full((s.nnz,), float("nan"), dtype=torch.float64, device=dev)
+    rho = torch.full((s.ngrid,), float("nan"), dtype=torch.float64, device=dev)
+    F = torch.full((s.natom * 3,), float("nan"), dtype=torch.float64, device=dev)
+    sig = torch.full((9,), float("nan"), dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    G.gint_vlocal(plan, v, h)
+    G.gint_rho(plan, d, rho)
+    G.gint_force_stress(plan, v, d, F, sig, E)
+    torch.cuda.synchronize()
+    out = dict(h=h.cpu().numpy(), rho=rho.cpu().numpy(), F=F.cpu().numpy().reshape(-1, 3),
+               sig=sig.cpu().numpy().reshape(3, 3), E=float(E.cpu()[0]))
+    plan.close()
+    return out
+
+
+def errors(gpu, ref):
+    e = {}
+    e["H_abs"] = float(np.abs(gpu["h"] - ref["h"]).max())
+    e["rho_rel"] = float(np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max())
+    e["F_abs"] = float(np.abs(gpu["F"] - ref["F"]).max())
+    e["sigma_rel"] = float(np.abs(gpu["sig"] - ref["sig"]).max() / np.abs(ref["sig"]).max())
+    e["E_rel"] = abs(gpu["E"] - ref["E"]) / abs(ref["E"])
+    return e
+
+
+BOUNDS = {1: dict(H_abs=1e-6, F_abs=1e-5, rho_rel=1e-5, sigma_rel=1e-5, E_rel=1e-5),
+          2: dict(H_abs=1e-4, F_abs=1e-3, rho_rel=1e-3, sigma_rel=1e-3, E_rel=1e-3)}
+
+
+def record(name, prec, errs):
+    d = os.environ.get("GINT_ERROR_LOG")
+    if d:
+        with open(d, "a") as f:
+            f.write(json.dumps({"case": name, "precision": prec, **errs}) + "\n")
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
+def test_mixed_diamond(torch_dev, oracle_mod, prec):
+    from paper_2409_09399_amd import gint as G
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.diamond8(0)
+    o = oracle_mod.Oracle(s)
+    F, Z, E, sig = o.force_stress()
+    ref = dict(h=o.vlocal(), rho=o.rho(), F=F, sig=sig, E=E)
+    errs = errors(run(G, torch, dev, s, prec), ref)
+    print("[mixed] diamond", prec, errs, flush=True)
+    record("diamond8", prec, errs)
+    for k, b in BOUNDS[prec].items():
+        assert errs[k] <= b, (k, errs[k], b)
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
+def test_mixed_tbg868_sampled(torch_dev, oracle_mod, prec):
+    """The benchmark workload in mixed precision: sampled rho points, H
+    blocks and atom forces from the oracle."""
+    from paper_2409_09399_amd import gint as G
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.make_config(2)
+    gpu = run(G, torch, dev, s, prec)
+    o = oracle_mod.Oracle(s)
+    rng = np.random.default_rng(1)
+    g = rng.choice(s.ngrid, 200, replace=False)
+    r_or = o.rho_points(g)
+    blks = rng.choice(len(s.blk_i), 16, replace=False)
+    herr = 0.0
+    for b, ref in zip(blks, o.vlocal_blocks(blks)):
+        got = gpu["h"][s.blk_off[b]:s.blk_off[b] + ref.size].reshape(ref.shape)
+        herr = max(herr, float(np.abs(got - ref).max()))
+    atoms = rng.choice(s.natom, 3, replace=False)
+    Fo, _ = o.force_atoms(atoms)
+    errs = {"H_abs": herr, "rho_rel": float(np.abs(gpu["rho"][g] - r_or).max() / np.abs(gpu["rho"]).max()),
+            "F_abs": float(np.abs(gpu["F"][atoms] - Fo).max())}
+    print("[mixed] tbg868", prec, errs, flush=True)
+    record("tbg868_sampled", prec, errs)
+    for k in errs:
+        assert errs[k] <= BOUNDS[prec][k], (k, errs[k])
