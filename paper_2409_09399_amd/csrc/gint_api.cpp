@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <new>
 
@@ -21,7 +22,8 @@ hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *st
                                      hipStream_t s);
 void gint_prime_grids_fp64();
 void gint_prime_grids_mx(int prec);
-hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, double *H, hipStream_t s);
+hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
+                                 hipStream_t s);
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s);
 hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
                                 hipStream_t s);
@@ -117,8 +119,9 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         return hip_fail(e);
     }
     size_t total = 0;
-    // workspace: [0] work counter (an int in the first 4 bytes), then ZE, then partial sums
-    std::vector<double> wsinit(1 + (size_t)n_sys * (10 + kParts), 0.0);
+    // workspace: [0] work counter (an int in the first 4 bytes), [1] max |V|,
+    // then ZE, then partial sums
+    std::vector<double> wsinit(2 + (size_t)n_sys * (10 + kParts), 0.0);
     if ((rc = upload(p->species, hp.species, total)) || (rc = upload(p->atoms, hp.atoms, total)) ||
         (rc = upload(p->tab, hp.tab, total)) || (rc = upload(p->tab32, hp.tab32, total)) ||
         (rc = upload(p->pairs, hp.pairs, total)) ||
@@ -136,7 +139,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     gint_prime_grids_fp64();   // k_work serves every precision form
     if (prec != GINT_FP64) gint_prime_grids_mx(prec);
     p->counter = (int *)p->ws.p;
-    p->ZE = (double *)p->ws.p + 1;
+    p->ZE = (double *)p->ws.p + 2;
     p->part = p->ZE + 10 * n_sys;
 
     GDev d{};
@@ -155,6 +158,15 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         for (int k = 0; k < 3; ++k) d.e[i][k] = hp.e[i][k];
     }
     d.w = hp.w;
+    {
+        // power of two with phi_max * phi_scale in [2^12, 2^13)
+        int e = 0;
+        if (hp.phi_max > 0.0 && std::isfinite(hp.phi_max)) (void)std::frexp(hp.phi_max, &e);
+        int k = hp.phi_max > 0.0 ? 13 - e : 0;
+        k = k < -60 ? -60 : (k > 60 ? 60 : k);
+        d.phi_scale = std::ldexp(1.0, k);
+    }
+    d.vmax = (const double *)p->ws.p + 1;
     p->canon = d;
     p->canon.items = (const GItem *)p->items_canon.p;
     p->canon.nitems = (int)hp.items_canon.size();
@@ -187,7 +199,7 @@ int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream)
     hipError_t e = gint_launch_fill(h_vals, p->sizes.nnz, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
     e = p->precision == GINT_FP64 ? gint_launch_vlocal(p->canon, v_loc, h_vals, s)
-                                  : gint_launch_vlocal_mx(p->canon, p->precision, v_loc, h_vals, s);
+                                  : gint_launch_vlocal_mx(p->canon, p->precision, v_loc, p->sizes.ngrid, h_vals, s);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }

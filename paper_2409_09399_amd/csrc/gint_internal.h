@@ -93,4 +93,10 @@ struct GDev {
     int N[3];
     double e[3][3];              // grid step vectors e_i = a_i / N_i (rows)
     double w;                    // volume per grid point
+    // mixed precision: orbitals enter the 16-bit MFMA operands multiplied by
+    // phi_scale (a power of two with |phi| phi_scale <= 2^13), so that their
+    // hi/lo splits stay clear of the FP16 subnormal range; vmax points to
+    // max_g |V_g| of the current call (reduced on the device)
+    double phi_scale;
+    const double *vmax;
 };

@@ -17,7 +17,7 @@
 #include <utility>
 #include <vector>
 
-#include "gint_internal.h"
+#include "gint_device.h"
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
@@ -31,30 +31,6 @@ constexpr double kC2a = 1.0925484305920792;    // sqrt(15/pi)/2
 constexpr double kC2b = 0.31539156525252005;   // sqrt(5/pi)/4
 constexpr double kC2c = 0.54627421529603959;   // sqrt(15/pi)/4
 
-// Wave index as a wave-uniform value: lets the compiler keep everything
-// indexed by it (atom slots, species descriptors, channel loops) in scalar
-// registers and scalar branches.
-__device__ inline int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// Persistent work loop: items are claimed from a device counter (reset to 0
-// before every launch); each item binds its system's geometry.
-__device__ inline int claim_item(int *counter, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
-    __syncthreads();
-    return *slot;
-}
-
-__device__ inline void bind_system(GDev &P, int s) {
-    const GSys &S = P.sys[s];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        P.N[k] = S.N[k];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) P.e[k][m] = S.e[k][m];
-    }
-    P.w = S.w;
-}
 
 __device__ inline int wrap(int n, int N) {
     int m = n % N;
@@ -85,7 +61,7 @@ struct Herm {
     double d00, d10, d01, d11;     // derivative weights (per unit r)
 };
 
-__device__ inline Herm hermite(const GSpecies &sp, const double *tab, double r) {
+__device__ inline Herm hermite(CSpecies &sp, const double *tab, double r) {
     double t = r * sp.inv_dr;
     int k = (int)t;
     if (k > sp.nknots - 2) k = sp.nknots - 2;
@@ -119,7 +95,7 @@ __device__ inline void solid9(double x, double y, double z, double S[9]) {
 
 // phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
 // (LDS); slots past the atom's orbitals are zero.
-__device__ inline void eval_phi(const GSpecies &sp, const double *tab, double x, double y, double z, double r2,
+__device__ inline void eval_phi(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
                                 double scale, double *dst) {
     const double r = sqrt(r2);
     const Herm h = hermite(sp, tab, r);
@@ -157,7 +133,7 @@ __device__ inline void zero16(double *dst) {
 
 // sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu for one atom at x
 // (grad phi = (p'/r) x S + p grad S; the first term is 0 at r = 0).
-__device__ inline void dot_phi_grad(const GSpecies &sp, const double *tab, double x, double y, double z, double r2,
+__device__ inline void dot_phi_grad(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
                                     const double *psi, double &e, double G[3]) {
     const double r = sqrt(r2);
     const Herm h = hermite(sp, tab, r);
@@ -215,7 +191,7 @@ __device__ inline unsigned or16(unsigned m) {
 // mode 0: A and B unscaled; mode 1: B scaled by w V_g; mode 2: B only, A
 // gets the activity bit only.
 template <int MODE>
-__device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, const double *__restrict__ V,
+__device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
                              double *phiA, double *phiB, unsigned *maskpt) {
     const int t = threadIdx.x;
     const int pt = t & 63, slot = wave_id();
@@ -227,12 +203,12 @@ __device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, cons
         bool in = false;
         double x = 0, y = 0, z = 0, r2 = 0;
         if (a >= 0) {
-            const GAtom at = P.atoms[a];
+            const GAtom at = ldc(P.atoms + (a));
             x = r.x - at.x - pr.shiftA[0];
             y = r.y - at.y - pr.shiftA[1];
             z = r.z - at.z - pr.shiftA[2];
             r2 = x * x + y * y + z * z;
-            const GSpecies &sp = P.species[at.species];
+            CSpecies &sp = cst(P.species)[at.species];
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
             if (MODE != 2) {
                 if (in) eval_phi(sp, P.tab, x, y, z, r2, 1.0, dst);
@@ -248,12 +224,12 @@ __device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, cons
         double *dst = phiB + pt * PSTR + slot * GINT_ORB;
         bool in = false;
         if (b >= 0) {
-            const GAtom at = P.atoms[b];
+            const GAtom at = ldc(P.atoms + (b));
             const double x = r.x - at.x - pr.shiftB[0];
             const double y = r.y - at.y - pr.shiftB[1];
             const double z = r.z - at.z - pr.shiftB[2];
             const double r2 = x * x + y * y + z * z;
-            const GSpecies &sp = P.species[at.species];
+            CSpecies &sp = cst(P.species)[at.species];
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
             if (in) {
                 const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
@@ -271,7 +247,7 @@ __device__ inline void stage(const GDev &P, const GPair &pr, const GBig &o, cons
 
 // D_sym[a_i mu][b_j nu] as the MFMA B operand of k-step s: lane holds
 // (mu = lane & 15, nu = 4 s + (lane >> 4)).
-__device__ inline void load_dsym(const GDev &P, const GPair &pr, const double *__restrict__ D, double dreg[4][4][4]) {
+__device__ inline void load_dsym(const GDev &P, CPair &pr, const double *__restrict__ D, double dreg[4][4][4]) {
     const int lane = threadIdx.x & 63;
     const int mu = lane & 15;
 #pragma unroll
@@ -279,8 +255,8 @@ __device__ inline void load_dsym(const GDev &P, const GPair &pr, const double *_
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
-            const int na = pr.a[i] >= 0 ? P.atoms[pr.a[i]].norb : 0;
-            const int nb = pr.b[j] >= 0 ? P.atoms[pr.b[j]].norb : 0;
+            const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
+            const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int nu = 4 * s + (lane >> 4);
@@ -337,11 +313,11 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
     // split-K: wave w owns k-steps 4w..4w+3 (points 16w..16w+15) of every
@@ -353,7 +329,7 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
         for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
         stage<1>(P, pr, o, V, phiA, phiB, maskpt);
@@ -401,14 +377,14 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
         __syncthreads();
         const int ai = pr.a[i];
         if (ai >= 0) {
-            const int na = P.atoms[ai].norb;
+            const int na = cst(P.atoms)[ai].norb;
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
                 const int e = threadIdx.x + 256 * k;    // (j, q, l)
                 const int j = e >> 8, q = (e >> 6) & 3, l = e & 63;
                 const int bj = pr.b[j];
                 if (bj < 0) continue;
-                const int nb = P.atoms[bj].norb;
+                const int nb = cst(P.atoms)[bj].norb;
                 const int mu = 4 * q + (l >> 4), nu = l & 15;
                 if (mu >= na || nu >= nb) continue;
                 const double v = red[((0 * 4 + j) * 4 + q) * 64 + l] + red[((1 * 4 + j) * 4 + q) * 64 + l] +
@@ -431,7 +407,7 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
 // ---------------------------------------------------------------------------
 // rho_g (Eq. 3): canonical pairs, weight 2 off the self pair
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, 2) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiA[GINT_BCPTS * PSTR];
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
@@ -440,11 +416,11 @@ __global__ __launch_bounds__(256) void k_rho(GDev P0, const double *__restrict__
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     double *rho = rho0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
     double dreg[4][4][4];
@@ -452,7 +428,7 @@ __global__ __launch_bounds__(256) void k_rho(GDev P0, const double *__restrict__
     const double weight = pr.self ? 1.0 : 2.0;
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
         stage<0>(P, pr, o, nullptr, phiA, phiB, maskpt);
@@ -488,7 +464,7 @@ __global__ __launch_bounds__(256) void k_rho(GDev P0, const double *__restrict__
 // Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only
 // acc[0..2] F of atom a_w, acc[3..11] Z, acc[12] E
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_force(GDev P0, const double *__restrict__ V0, const double *__restrict__ D,
+__global__ __launch_bounds__(256, 2) void k_force(GDev P0, const double *__restrict__ V0, const double *__restrict__ D,
                                                double *__restrict__ F, double *__restrict__ ZE0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
@@ -497,11 +473,11 @@ __global__ __launch_bounds__(256) void k_force(GDev P0, const double *__restrict
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     double *ZE = ZE0 + 10 * pr.sys;
     const int lane = threadIdx.x & 63, w = wave_id();
@@ -511,7 +487,7 @@ __global__ __launch_bounds__(256) void k_force(GDev P0, const double *__restrict
     const int aw = pr.a[w];
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
         stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt);
@@ -520,13 +496,13 @@ __global__ __launch_bounds__(256) void k_force(GDev P0, const double *__restrict
         __syncthreads();
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const Pt r = bigcell_point(P, o, lane);
-            const GAtom at = P.atoms[aw];
+            const GAtom at = ldc(P.atoms + (aw));
             const double x = r.x - at.x - pr.shiftA[0];
             const double y = r.y - at.y - pr.shiftA[1];
             const double zz = r.z - at.z - pr.shiftA[2];
             const double r2 = x * x + y * y + zz * zz;
             double e, G[3];
-            dot_phi_grad(P.species[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
+            dot_phi_grad(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
             const double wv = P.w * V[r.g];
             const double c = 2.0 * wv;
             f[0] += c * G[0];
@@ -576,34 +552,34 @@ __global__ __launch_bounds__(256) void k_work(GDev P0, double *__restrict__ W0) 
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     double *W = W0 + pr.sys;
     const double weight = pr.self ? 1.0 : 2.0;
     double acc = 0.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) {
             const Pt r = bigcell_point(P, o, threadIdx.x);
             double na = 0, nb = 0;
             for (int k = 0; k < GINT_CL; ++k) {
                 if (pr.a[k] >= 0) {
-                    const GAtom at = P.atoms[pr.a[k]];
+                    const GAtom at = ldc(P.atoms + pr.a[k]);
                     const double x = r.x - at.x - pr.shiftA[0], y = r.y - at.y - pr.shiftA[1],
                                  z = r.z - at.z - pr.shiftA[2];
                     const double r2 = x * x + y * y + z * z;
-                    const GSpecies &sp = P.species[at.species];
+                    CSpecies &sp = cst(P.species)[at.species];
                     if (r2 < sp.rcut2 && sqrt(r2) < sp.rcut) na += at.norb;
                 }
                 if (pr.b[k] >= 0) {
-                    const GAtom at = P.atoms[pr.b[k]];
+                    const GAtom at = ldc(P.atoms + pr.b[k]);
                     const double x = r.x - at.x - pr.shiftB[0], y = r.y - at.y - pr.shiftB[1],
                                  z = r.z - at.z - pr.shiftB[2];
                     const double r2 = x * x + y * y + z * z;
-                    const GSpecies &sp = P.species[at.species];
+                    CSpecies &sp = cst(P.species)[at.species];
                     if (r2 < sp.rcut2 && sqrt(r2) < sp.rcut) nb += at.norb;
                 }
             }
@@ -633,7 +609,7 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
 __global__ __launch_bounds__(256) void k_seg_sum_partial(GDev P, const double *__restrict__ x, int nparts,
                                                          double *__restrict__ part) {
     __shared__ double red[256];
-    const GSys &S = P.sys[blockIdx.y];
+    CSys &S = cst(P.sys)[blockIdx.y];
     const long long n = (long long)S.N[0] * S.N[1] * S.N[2];
     const double *xs = x + S.g_off;
     double acc = 0.0;
@@ -659,7 +635,7 @@ __global__ __launch_bounds__(256) void k_seg_sum_final(GDev P, const double *__r
         if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[sy] = red[0] * P.sys[sy].w;
+    if (threadIdx.x == 0) out[sy] = red[0] * cst(P.sys)[sy].w;
 }
 
 // stress_s = -Z_s / Omega_s, energy_s = E_s
@@ -668,7 +644,7 @@ __global__ void k_finish_stress(GDev P, const double *__restrict__ ZE, double *_
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const int sy = t / 10, k = t % 10;
     if (sy >= P.nsys) return;
-    if (k < 9) stress[9 * sy + k] = -ZE[10 * sy + k] / P.sys[sy].volume;
+    if (k < 9) stress[9 * sy + k] = -ZE[10 * sy + k] / cst(P.sys)[sy].volume;
     else if (energy) energy[sy] = ZE[10 * sy + 9];
 }
 

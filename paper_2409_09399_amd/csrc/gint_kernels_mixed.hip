@@ -13,7 +13,7 @@
 // 16-bit parts stay in range; the constant w is applied in FP64.
 #include <hip/hip_runtime.h>
 
-#include "gint_internal.h"
+#include "gint_device.h"
 
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
@@ -55,27 +55,6 @@ struct Split16<__bf16> {
     }
 };
 
-__device__ inline int wave_idx() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
-
-// Persistent work loop: items are claimed from a device counter (reset to 0
-// before every launch); each item binds its system's geometry.
-__device__ inline int claim_item(int *counter, int *slot) {
-    __syncthreads();
-    if (threadIdx.x == 0) *slot = atomicAdd(counter, 1);
-    __syncthreads();
-    return *slot;
-}
-
-__device__ inline void bind_system(GDev &P, int s) {
-    const GSys &S = P.sys[s];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        P.N[k] = S.N[k];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) P.e[k][m] = S.e[k][m];
-    }
-    P.w = S.w;
-}
 
 __device__ inline int wrapi(int n, int N) {
     int m = n % N;
@@ -103,11 +82,25 @@ struct Herm32 {
     float h00, h10, h01, h11, d00, d10, d01, d11;
 };
 
-__device__ inline Herm32 hermite32(const GSpecies &sp, const float *tab, float r) {
-    float t = r * (float)sp.inv_dr;
+// Knot interval of radius r, found in FP64: with t = r / dr of order 10^3 an
+// FP32 t would carry an absolute error of order 1e-4 (a relative error of
+// the same order in the interpolation weights); only the offset within the
+// interval is rounded to FP32.
+struct Knot {
+    int k;
+    float t;
+};
+
+__device__ inline Knot knot_of(CSpecies &sp, double r) {
+    const double t = r * sp.inv_dr;
     int k = (int)t;
     if (k > sp.nknots - 2) k = sp.nknots - 2;
-    t -= (float)k;
+    return Knot{k, (float)(t - (double)k)};
+}
+
+__device__ inline Herm32 hermite32(CSpecies &sp, const float *tab, Knot kn) {
+    const int k = kn.k;
+    const float t = kn.t;
     const float t2 = t * t, t3 = t2 * t, dr = (float)sp.dr, idr = (float)sp.inv_dr;
     Herm32 h;
     h.row0 = tab + sp.tab_off + (size_t)k * sp.nchan * 2;
@@ -125,10 +118,9 @@ __device__ inline Herm32 hermite32(const GSpecies &sp, const float *tab, float r
 
 // phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v).
 template <class Emit>
-__device__ inline void eval32(const GSpecies &sp, const float *tab, float x, float y, float z, float r2, float scale,
+__device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
                               Emit emit) {
-    const float r = sqrtf(r2);
-    const Herm32 h = hermite32(sp, tab, r);
+    const Herm32 h = hermite32(sp, tab, kn);
     const float S1y = kC1f * y, S1z = kC1f * z, S1x = kC1f * x;
     const float S20 = kC2af * x * y, S21 = kC2af * y * z, S22 = kC2bf * (2.f * z * z - x * x - y * y),
                 S23 = kC2af * x * z, S24 = kC2cf * (x * x - y * y);
@@ -158,11 +150,9 @@ __device__ inline void eval32(const GSpecies &sp, const float *tab, float x, flo
 }
 
 // sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu, FP32.
-__device__ inline void dot_grad32(const GSpecies &sp, const float *tab, float x, float y, float z, float r2,
+__device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float inv_r,
                                   const float *psi, float &e, float G[3]) {
-    const float r = sqrtf(r2);
-    const Herm32 h = hermite32(sp, tab, r);
-    const float inv_r = r > 0.f ? 1.f / r : 0.f;
+    const Herm32 h = hermite32(sp, tab, kn);
     e = 0.f;
     G[0] = G[1] = G[2] = 0.f;
     int slot = 0;
@@ -201,26 +191,40 @@ __device__ inline void dot_grad32(const GSpecies &sp, const float *tab, float x,
 
 // Activity of one atom at one point; x is the FP32 displacement.
 struct Disp {
-    float x, y, z, r2;
+    float x, y, z;
+    Knot kn;
     bool in;
 };
 
-__device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, const double *shift) {
-    Disp d{0.f, 0.f, 0.f, 0.f, false};
+__device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, cdouble *shift) {
+    Disp d{0.f, 0.f, 0.f, Knot{0, 0.f}, false};
     if (atom < 0) return d;
-    const GAtom at = P.atoms[atom];
+    const GAtom at = ldc(P.atoms + (atom));
     const double dx = r.x - at.x - shift[0], dy = r.y - at.y - shift[1], dz = r.z - at.z - shift[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
-    const GSpecies &sp = P.species[at.species];
-    d.in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+    CSpecies &sp = cst(P.species)[at.species];
+    const double rr = sqrt(r2);
+    d.in = r2 < sp.rcut2 && rr < sp.rcut;
     d.x = (float)dx;
     d.y = (float)dy;
     d.z = (float)dz;
-    d.r2 = (float)r2;
+    if (d.in) d.kn = knot_of(sp, rr);
     return d;
 }
 
 constexpr int TSTR = 72;   // 16-bit elements per tile row (64 points + 8): conflict-free 16-byte reads
+
+// Power of two s with m s in [2^12, 2^13) (1 if m is 0 or not finite),
+// exponent clamped to +-60: operands m s stay below 2^13 and well above the
+// FP16 subnormal range, and undoing s is exact.
+__device__ inline float pow2_scale(double m) {
+    if (!(m > 0.0) || !(m < 1e300)) return 1.f;
+    int e;
+    (void)frexp(m, &e);
+    int k = 13 - e;
+    k = k < -60 ? -60 : (k > 60 ? 60 : k);
+    return ldexpf(1.f, k);
+}
 
 }  // namespace
 
@@ -236,22 +240,26 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
     __shared__ __attribute__((aligned(16))) T tB[2][4][16][TSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ int s_item;
+    // A = phi * sphi, B = V phi * sB, both below 2^13 in magnitude
+    const float sphi = (float)P0.phi_scale;
+    const float sB = pow2_scale(*cst(P0.vmax) * (8192.0 / P0.phi_scale));
+    const double unscale = 1.0 / ((double)sphi * (double)sB);
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
-    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int lane = threadIdx.x & 63, w = wave_id();
     d4v acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = (d4v){0.0, 0.0, 0.0, 0.0};
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
         {
@@ -262,8 +270,8 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
             const int a = pr.a[w], b = pr.b[w];
             const Disp da = disp_of(P, r, a, pr.shiftA);
             if (da.in) {
-                const GSpecies &sp = P.species[P.atoms[a].species];
-                eval32(sp, P.tab32, da.x, da.y, da.z, da.r2, 1.f, [&](int mu, float v) {
+                CSpecies &sp = cst(P.species)[cst(P.atoms)[a].species];
+                eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
                     T hi, lo;
                     S::split(v, hi, lo);
                     tA[0][w][mu][pt] = hi;
@@ -279,9 +287,9 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
             }
             const Disp db = disp_of(P, r, b, pr.shiftB);
             if (db.in) {
-                const GSpecies &sp = P.species[P.atoms[b].species];
-                const float vg = (float)V[r.g];
-                eval32(sp, P.tab32, db.x, db.y, db.z, db.r2, vg, [&](int mu, float v) {
+                CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
+                const float vg = (float)V[r.g] * sB;
+                eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                     T hi, lo;
                     S::split(v, hi, lo);
                     tB[0][w][mu][pt] = hi;
@@ -340,13 +348,13 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
         const int j = (w - i) & 3;
         const int ai = pr.a[i], bj = pr.b[j];
         if (ai < 0 || bj < 0) continue;
-        const int na = P.atoms[ai].norb, nb = P.atoms[bj].norb;
+        const int na = cst(P.atoms)[ai].norb, nb = cst(P.atoms)[bj].norb;
         const long long off = pr.hoff[i * 4 + j], offt = pr.hoff_t[i * 4 + j];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int mu = 4 * (lane >> 4) + q;
             if (mu >= na || nu >= nb) continue;
-            const double v = P.w * acc[i][q];
+            const double v = P.w * unscale * acc[i][q];
             if (exclusive) {
                 if (off >= 0) H[off + (long long)mu * nb + nu] = v;
                 if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
@@ -365,30 +373,45 @@ namespace {
 // k-step kk covers B atoms 2kk, 2kk+1; lane l holds mu = l & 15 and
 // nu' = 8 (l >> 4) + e, i.e. atom 2kk + (l >> 5), orbital 8 ((l >> 4) & 1) + e.
 template <class T>
-__device__ inline void load_dsym16(const GDev &P, const GPair &pr, const double *__restrict__ D,
-                                   typename Split16<T>::vec dh[4][2], typename Split16<T>::vec dl[4][2]) {
+__device__ inline float load_dsym16(const GDev &P, CPair &pr, const double *__restrict__ D, float sphi,
+                                    typename Split16<T>::vec dh[4][2], typename Split16<T>::vec dl[4][2]) {
     const int lane = threadIdx.x & 63;
     const int mu = lane & 15;
+    float val[4][2][8];
+    float m = 0.f;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int j = 2 * kk + (lane >> 5);
             const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
-            const int na = pr.a[i] >= 0 ? P.atoms[pr.a[i]].norb : 0;
-            const int nb = pr.b[j] >= 0 ? P.atoms[pr.b[j]].norb : 0;
+            const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
+            const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const int nu = 8 * ((lane >> 4) & 1) + e;
                 float v = 0.f;
                 if (o >= 0 && ot >= 0 && mu < na && nu < nb)
                     v = (float)(0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]));
+                val[i][kk][e] = v;
+                m = fmaxf(m, fabsf(v));
+            }
+        }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    const float sD = pow2_scale((double)m);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
                 T hi, lo;
-                Split16<T>::split(v, hi, lo);
+                Split16<T>::split(val[i][kk][e] * sD, hi, lo);
                 dh[i][kk][e] = hi;
                 dl[i][kk][e] = lo;
             }
-        }
+    return 1.f / (sphi * sD);   // psi = (phi sphi)(D sD) / (sphi sD), exact
 }
 
 constexpr int RSTR = 72;   // 16-bit elements per point row of the B tile (4 slots x 16 + 8)
@@ -397,9 +420,9 @@ constexpr int FSTR = 65;   // floats per point row of FP32 tiles
 // Phase 1 of rho/force: B orbitals as 16-bit hi/lo rows [h][point][slot*16+mu];
 // A orbitals in FP32 (rho) or only their activity (force).
 template <class T, bool WANT_A>
-__device__ inline void stage_rho(const GDev &P, const GPair &pr, const GBig &o, T (*tB)[GINT_BCPTS][RSTR],
+__device__ inline void stage_rho(const GDev &P, CPair &pr, const GBig &o, float sphi, T (*tB)[GINT_BCPTS][RSTR],
                                  float *pA, unsigned *maskpt) {
-    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int lane = threadIdx.x & 63, w = wave_id();
     const int pt = lane;
     const P3 r = point_of(P, o, pt);
     unsigned bits = 0;
@@ -408,8 +431,8 @@ __device__ inline void stage_rho(const GDev &P, const GPair &pr, const GBig &o, 
     if (WANT_A) {
         float *dst = pA + pt * FSTR + w * 16;
         if (da.in) {
-            const GSpecies &sp = P.species[P.atoms[a].species];
-            eval32(sp, P.tab32, da.x, da.y, da.z, da.r2, 1.f, [&](int mu, float v) { dst[mu] = v; });
+            CSpecies &sp = cst(P.species)[cst(P.atoms)[a].species];
+            eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float v) { dst[mu] = v; });
         } else {
 #pragma unroll
             for (int mu = 0; mu < 16; ++mu) dst[mu] = 0.f;
@@ -420,8 +443,8 @@ __device__ inline void stage_rho(const GDev &P, const GPair &pr, const GBig &o, 
     T *h0 = &tB[0][pt][w * 16];
     T *h1 = &tB[1][pt][w * 16];
     if (db.in) {
-        const GSpecies &sp = P.species[P.atoms[b].species];
-        eval32(sp, P.tab32, db.x, db.y, db.z, db.r2, 1.f, [&](int mu, float v) {
+        CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
+        eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
             T hi, lo;
             Split16<T>::split(v, hi, lo);
             h0[mu] = hi;
@@ -442,9 +465,9 @@ __device__ inline void stage_rho(const GDev &P, const GPair &pr, const GBig &o, 
 // the wave's 16 points (FP32 result into psi rows of FSTR floats).
 template <class T>
 __device__ inline void psi_mx(const typename Split16<T>::vec dh[4][2], const typename Split16<T>::vec dl[4][2],
-                              T (*tB)[GINT_BCPTS][RSTR], float *psi, const unsigned *maskpt) {
+                              T (*tB)[GINT_BCPTS][RSTR], float *psi, const unsigned *maskpt, float unscale) {
     typedef typename Split16<T>::vec vec;
-    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int lane = threadIdx.x & 63, w = wave_id();
     unsigned gm = maskpt[16 * w + (lane & 15)];
     gm |= __shfl_xor(gm, 1);
     gm |= __shfl_xor(gm, 2);
@@ -472,7 +495,7 @@ __device__ inline void psi_mx(const typename Split16<T>::vec dh[4][2], const typ
             c = Split16<T>::mfma(bl[kk], dh[i][kk], c);
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q * FSTR + i * 16] = c[q];
+        for (int q = 0; q < 4; ++q) dst[q * FSTR + i * 16] = c[q] * unscale;
     }
 }
 
@@ -493,23 +516,24 @@ __global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__rest
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     double *rho = rho0 + SY.g_off;
-    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int lane = threadIdx.x & 63, w = wave_id();
     vec dh[4][2], dl[4][2];
-    load_dsym16<T>(P, pr, D, dh, dl);
+    const float sphi = (float)P0.phi_scale;
+    const float unscale = load_dsym16<T>(P, pr, D, sphi, dh, dl);
     const double weight = pr.self ? 1.0 : 2.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_rho<T, true>(P, pr, o, tB, pA, maskpt);
+        stage_rho<T, true>(P, pr, o, sphi, tB, pA, maskpt);
         __syncthreads();
-        psi_mx<T>(dh, dl, tB, psi, maskpt);
+        psi_mx<T>(dh, dl, tB, psi, maskpt, unscale);
         __syncthreads();
         {
             float v = 0.f;
@@ -553,34 +577,37 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
-    const GItem it = P0.items[item_];
-    const GPair &pr = P0.pairs[it.pair];
+    const GItem it = ldc(P0.items + item_);
+    CPair &pr = cst(P0.pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
-    const GSys &SY = P0.sys[pr.sys];
+    CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     double *ZE = ZE0 + 10 * pr.sys;
-    const int lane = threadIdx.x & 63, w = wave_idx();
+    const int lane = threadIdx.x & 63, w = wave_id();
     vec dh[4][2], dl[4][2];
-    load_dsym16<T>(P, pr, D, dh, dl);
+    const float sphi = (float)P0.phi_scale;
+    const float unscale = load_dsym16<T>(P, pr, D, sphi, dh, dl);
     double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     const int aw = pr.a[w];
     for (int bc = 0; bc < it.bc_count; ++bc) {
-        const GBig o = P.bigcells[it.bc_begin + bc];
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_rho<T, false>(P, pr, o, tB, nullptr, maskpt);
+        stage_rho<T, false>(P, pr, o, sphi, tB, nullptr, maskpt);
         __syncthreads();
-        psi_mx<T>(dh, dl, tB, psi, maskpt);
+        psi_mx<T>(dh, dl, tB, psi, maskpt, unscale);
         __syncthreads();
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const P3 r = point_of(P, o, lane);
-            const GAtom at = P.atoms[aw];
+            const GAtom at = ldc(P.atoms + (aw));
             const double dx = r.x - at.x - pr.shiftA[0], dy = r.y - at.y - pr.shiftA[1],
                          dz = r.z - at.z - pr.shiftA[2];
             const float x = (float)dx, y = (float)dy, zz = (float)dz;
+            CSpecies &sp = cst(P.species)[at.species];
+            const double rr = sqrt(dx * dx + dy * dy + dz * dz);
             float e, G[3];
-            dot_grad32(P.species[at.species], P.tab32, x, y, zz, (float)(dx * dx + dy * dy + dz * dz),
+            dot_grad32(sp, P.tab32, x, y, zz, knot_of(sp, rr), rr > 0.0 ? (float)(1.0 / rr) : 0.f,
                        psi + lane * FSTR + w * 16, e, G);
             const double wv = P.w * V[r.g];
             const double c = 2.0 * wv;
@@ -638,7 +665,27 @@ static hipError_t launch_persistent(K kernel, const GDev &P, hipStream_t s, Args
     return hipGetLastError();
 }
 
-hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, double *H, hipStream_t s) {
+// max |x| into *out (non-negative doubles order like their bit patterns)
+__global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ x, long long n,
+                                                unsigned long long *__restrict__ out) {
+    double m = 0.0;
+    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) m = fmax(m, fabs(x[i]));
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
+                                 hipStream_t s) {
+    hipError_t e = gint_launch_fill(const_cast<double *>(P.vmax), 1, 0.0, s);
+    if (e != hipSuccess) return e;
+    long long blocks = (ngrid + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks > 0) {
+        hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, V, ngrid,
+                           (unsigned long long *)const_cast<double *>(P.vmax));
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     return prec == 2 ? launch_persistent(k_vlocal_mx<__bf16>, P, s, V, H)
                      : launch_persistent(k_vlocal_mx<_Float16>, P, s, V, H);
 }

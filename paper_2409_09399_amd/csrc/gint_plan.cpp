@@ -180,6 +180,21 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         if (norb > GINT_ORB) return fail(GINT_EUNSUPPORTED, "more than 16 orbitals per atom");
         g.norb = norb;
         g.tab_off = (int)hp.tab.size();
+        // bound on |phi| = |p_c(r)| |S_lm(x)| over the table: the Hermite
+        // cubic on [r_k, r_k+1] is at most |f_k| + |f_k+1| + (4/27) dr
+        // (|f'_k| + |f'_k+1|), and |S_lm(x)| <= r^l sqrt((2l+1)/(4 pi))
+        for (int c = 0; c < sp.nchan; ++c) {
+            const int l = sp.chan_l[c];
+            const double ylm = std::sqrt((2.0 * l + 1.0) / (4.0 * M_PI));
+            const double *f = sp.f + (size_t)c * sp.nknots, *fp = sp.fp + (size_t)c * sp.nknots;
+            for (int k = 0; k + 1 < sp.nknots && k * sp.dr < sp.rcut; ++k) {
+                const double pk = std::fabs(f[k]) + std::fabs(f[k + 1]) +
+                                  (4.0 / 27.0) * sp.dr * (std::fabs(fp[k]) + std::fabs(fp[k + 1]));
+                const double r1 = std::min((k + 1) * sp.dr, sp.rcut);
+                const double b = pk * std::pow(r1, l) * ylm;
+                if (std::isfinite(b) && b > hp.phi_max) hp.phi_max = b;
+            }
+        }
         for (int k = 0; k < sp.nknots; ++k)
             for (int c = 0; c < sp.nchan; ++c) {
                 const double f = sp.f[(size_t)c * sp.nknots + k], fp = sp.fp[(size_t)c * sp.nknots + k];
@@ -516,6 +531,7 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
         }
         hp.tab.insert(hp.tab.end(), one.tab.begin(), one.tab.end());
         hp.tab32.insert(hp.tab32.end(), one.tab32.begin(), one.tab32.end());
+        hp.phi_max = std::max(hp.phi_max, one.phi_max);
         for (GAtom at : one.atoms) {
             at.species += species_off;
             hp.atoms.push_back(at);

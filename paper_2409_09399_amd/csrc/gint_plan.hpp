@@ -27,6 +27,7 @@ struct HostPlan {
     double e[3][3] = {{0}};
     double omega = 0.0;
     double w = 0.0;
+    double phi_max = 0.0;            // bound on |phi| over every species (mixed-precision scaling)
     long long nnz = 0;
     long long ngrid = 0;
     int cluster_atoms = GINT_CL;

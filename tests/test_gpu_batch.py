@@ -196,7 +196,9 @@ def test_batch64_mixed(G_mod, torch_dev, batch64, prec):
         worst["rho_rel"] = max(worst["rho_rel"], rel(g["rho"], r["rho"]))
         worst["sigma_rel"] = max(worst["sigma_rel"], rel(g["sig"], r["sig"]))
         worst["E_rel"] = max(worst["E_rel"], abs(g["E"] - r["E"]) / abs(r["E"]))
-    print(f"[mixed] batch64 prec={prec} worst {worst}", flush=True)
+    hmax = max(float(np.abs(r["h"]).max()) for r in ref)
+    fmax = max(float(np.abs(r["F"]).max()) for r in ref)
+    print(f"[mixed] batch64 prec={prec} worst {worst} max|H| {hmax:.4g} max|F| {fmax:.4g}", flush=True)
     assert worst["H_abs"] <= bounds["H_abs"]
     assert worst["F_abs"] <= bounds["F_abs"]
     for k in ("rho_rel", "sigma_rel", "E_rel"):
