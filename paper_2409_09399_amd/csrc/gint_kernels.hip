@@ -131,10 +131,11 @@ __device__ inline void zero16(double *dst) {
     for (int k = 0; k < GINT_ORB; ++k) dst[k] = 0.0;
 }
 
-// sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu for one atom at x
-// (grad phi = (p'/r) x S + p grad S; the first term is 0 at r = 0).
-__device__ inline void dot_phi_grad(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
-                                    const double *psi, double &e, double G[3]) {
+// sum_mu psi_mu phi_mu and (GRAD) sum_mu psi_mu grad phi_mu for one atom at
+// x (grad phi = (p'/r) x S + p grad S; the first term is 0 at r = 0).
+template <bool GRAD>
+__device__ inline void dot_phi(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
+                               const double *psi, double &e, double G[3]) {
     const double r = sqrt(r2);
     const Herm h = hermite(sp, tab, r);
     const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
@@ -144,7 +145,7 @@ __device__ inline void dot_phi_grad(CSpecies &sp, const double *tab, double x, d
     for (int c = 0; c < sp.nchan; ++c) {
         const double f0 = h.row0[2 * c], fp0 = h.row0[2 * c + 1], f1 = h.row1[2 * c], fp1 = h.row1[2 * c + 1];
         const double p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
-        const double q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
+        const double q = GRAD ? (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r : 0.0;
         const int l = sp.chan_l[c];
         double A, Bx, By, Bz;   // A = sum_m psi_m S_m, B = sum_m psi_m grad S_m
         if (l == 0) {
@@ -169,9 +170,11 @@ __device__ inline void dot_phi_grad(CSpecies &sp, const double *tab, double x, d
             slot += 5;
         }
         e += p * A;
-        G[0] += q * A * x + p * Bx;
-        G[1] += q * A * y + p * By;
-        G[2] += q * A * z + p * Bz;
+        if (GRAD) {
+            G[0] += q * A * x + p * Bx;
+            G[1] += q * A * y + p * By;
+            G[2] += q * A * z + p * Bz;
+        }
     }
 }
 
@@ -192,7 +195,7 @@ __device__ inline unsigned or16(unsigned m) {
 // gets the activity bit only.
 template <int MODE>
 __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
-                             double *phiA, double *phiB, unsigned *maskpt) {
+                             double *phiA, double *phiB, unsigned *maskpt, unsigned *maskt = nullptr) {
     const int t = threadIdx.x;
     const int pt = t & 63, slot = wave_id();
     const Pt r = bigcell_point(P, o, pt);
@@ -242,61 +245,72 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
         }
         if (in) bits |= 1u << (4 + slot);
     }
-    if (bits) atomicOr(&maskpt[pt], bits);
+    if (bits) {
+        atomicOr(&maskpt[pt], bits);
+        if (maskt) atomicOr(&maskt[pt >> 4], bits);
+    }
 }
 
-// D_sym[a_i mu][b_j nu] as the MFMA B operand of k-step s: lane holds
-// (mu = lane & 15, nu = 4 s + (lane >> 4)).
-__device__ inline void load_dsym(const GDev &P, CPair &pr, const double *__restrict__ D, double dreg[4][4][4]) {
+// Row atom i of D_sym as MFMA B operands: dw[j][s] holds
+// D_sym[a_i mu][b_j nu] with mu = lane & 15, nu = 4 s + (lane >> 4).
+__device__ inline void load_dsym_row(const GDev &P, CPair &pr, const double *__restrict__ D, int i,
+                                     double dw[4][4]) {
     const int lane = threadIdx.x & 63;
     const int mu = lane & 15;
+    const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+        const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
+        const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
-            const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
-            const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const int nu = 4 * s + (lane >> 4);
-                double v = 0.0;
-                if (o >= 0 && ot >= 0 && mu < na && nu < nb)
-                    v = 0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]);
-                dreg[i][j][s] = v;
-            }
+        for (int s = 0; s < 4; ++s) {
+            const int nu = 4 * s + (lane >> 4);
+            double v = 0.0;
+            if (o >= 0 && ot >= 0 && mu < na && nu < nb)
+                v = 0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]);
+            dw[j][s] = v;
         }
+    }
 }
 
-// Phase 2 of rho/force: wave w computes psi[pt][a_i][mu] = sum_{b_j, nu}
-// phi_B[pt][b_j][nu] D_sym[a_i mu][b_j nu] for its 16 points and writes it
-// over its own rows of phiB (no other wave reads those rows).  All operand
-// reads are issued before the MFMAs; each B-atom operand feeds all 4 A atoms.
-__device__ inline void psi_tiles(const double dreg[4][4][4], double *phiB, const unsigned *maskpt) {
+// Phase 2 of rho/force: wave w computes psi[pt][mu] = sum_{b_j, nu}
+// phi_B[pt][b_j][nu] D_sym[a_w mu][b_j nu] for all 64 points (four 16-point
+// tiles; tiles where a_w is inactive are skipped, and B atoms inactive on a
+// tile are skipped).  Result in registers, MFMA layout: c[t] lane l register
+// q holds point 16 t + 4 q + (l >> 4), orbital l & 15.
+__device__ inline void psi_row(const double dw[4][4], const double *phiB, const unsigned *maskt, d4 c[4]) {
     const int lane = threadIdx.x & 63, w = wave_id();
-    unsigned gm = or16(maskpt[16 * w + (lane & 15)]);
-    gm = __builtin_amdgcn_readfirstlane(gm);
-    const double *base = phiB + (16 * w + (lane & 15)) * PSTR + (lane >> 4);
-    double src[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int t = 0; t < 4; ++t) {
+        c[t] = (d4){0.0, 0.0, 0.0, 0.0};
+        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        if (!(gm & (1u << w))) continue;
+        const double *base = phiB + (16 * t + (lane & 15)) * PSTR + (lane >> 4);
+        double src[4][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) src[j][s] = base[j * GINT_ORB + 4 * s];
-    __builtin_amdgcn_wave_barrier();
-    // FP64 16x16x4 result layout: lane l, register q holds row 4q + (l >> 4), column l & 15
-    double *dst = phiB + (16 * w + (lane >> 4)) * PSTR + (lane & 15);
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (!(gm & (1u << i))) continue;   // psi of an inactive A atom is never read
-        d4 c = (d4){0.0, 0.0, 0.0, 0.0};
+            for (int s = 0; s < 4; ++s) src[j][s] = base[j * GINT_ORB + 4 * s];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (!(gm & (1u << (4 + j)))) continue;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) c = mfma64(src[j][s], dreg[i][j][s], c);
+            for (int s = 0; s < 4; ++s) c[t] = mfma64(src[j][s], dw[j][s], c[t]);
         }
+    }
+}
+
+// Store psi of atom slot w over that slot's columns of phiB (after every
+// wave has finished reading phiB); only rows of tiles where a_w is active.
+__device__ inline void store_psi(const d4 c[4], double *phiB, const unsigned *maskt) {
+    const int lane = threadIdx.x & 63, w = wave_id();
 #pragma unroll
-        for (int q = 0; q < 4; ++q) dst[4 * q * PSTR + i * GINT_ORB] = c[q];
+    for (int t = 0; t < 4; ++t) {
+        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        if (!(gm & (1u << w))) continue;
+        double *dst = phiB + (16 * t + (lane >> 4)) * PSTR + w * GINT_ORB + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[4 * q * PSTR] = c[t][q];
     }
 }
 
@@ -405,12 +419,14 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
 }
 
 // ---------------------------------------------------------------------------
-// rho_g (Eq. 3): canonical pairs, weight 2 off the self pair
+// rho_g (Eq. 3): canonical pairs, weight 2 off the self pair.  Wave w owns A
+// atom slot w: psi of a_w for the 64 points by MFMA, then per point (lane)
+// phi_{a_w} . psi evaluated on the fly.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
-    __shared__ double phiA[GINT_BCPTS * PSTR];
+__global__ __launch_bounds__(256, 3) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ unsigned maskt[4];
     __shared__ double part[4][GINT_BCPTS];
     __shared__ int s_item;
     for (;;) {
@@ -423,26 +439,34 @@ __global__ __launch_bounds__(256, 2) void k_rho(GDev P0, const double *__restric
     CSys &SY = cst(P0.sys)[pr.sys];
     double *rho = rho0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
-    double dreg[4][4][4];
-    load_dsym(P, pr, D, dreg);
+    const int aw = pr.a[w];
+    double dw[4][4];
+    load_dsym_row(P, pr, D, w, dw);
     const double weight = pr.self ? 1.0 : 2.0;
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage<0>(P, pr, o, nullptr, phiA, phiB, maskpt);
+        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt, maskt);
         __syncthreads();
-        psi_tiles(dreg, phiB, maskpt);
+        d4 c[4];
+        psi_row(dw, phiB, maskt, c);
         __syncthreads();
-        // phase 3: wave w = A slot w, lane = point
+        store_psi(c, phiB, maskt);
+        // phase 3: wave w = A slot w, lane = point (reads only its own psi)
         {
-            const double *pa = phiA + lane * PSTR + w * GINT_ORB;
-            const double *ps = phiB + lane * PSTR + w * GINT_ORB;
             double v = 0.0;
-            if (maskpt[lane] & (1u << w)) {
-#pragma unroll
-                for (int mu = 0; mu < GINT_ORB; ++mu) v += pa[mu] * ps[mu];
+            if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+                const Pt r = bigcell_point(P, o, lane);
+                const GAtom at = ldc(P.atoms + aw);
+                const double x = r.x - at.x - pr.shiftA[0];
+                const double y = r.y - at.y - pr.shiftA[1];
+                const double z = r.z - at.z - pr.shiftA[2];
+                double G[3];
+                dot_phi<false>(cst(P.species)[at.species], P.tab, x, y, z, x * x + y * y + z * z,
+                               phiB + lane * PSTR + w * GINT_ORB, v, G);
             }
             part[w][lane] = v;
         }
@@ -461,13 +485,15 @@ __global__ __launch_bounds__(256, 2) void k_rho(GDev P0, const double *__restric
 }
 
 // ---------------------------------------------------------------------------
-// Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only
-// acc[0..2] F of atom a_w, acc[3..11] Z, acc[12] E
+// Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only.
+// Wave w owns A atom slot w (psi by MFMA, then grad phi . psi per point).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_force(GDev P0, const double *__restrict__ V0, const double *__restrict__ D,
-                                               double *__restrict__ F, double *__restrict__ ZE0) {
+__global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restrict__ V0,
+                                                  const double *__restrict__ D, double *__restrict__ F,
+                                                  double *__restrict__ ZE0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ unsigned maskt[4];
     __shared__ double red[4][10];
     __shared__ int s_item;
     for (;;) {
@@ -481,38 +507,41 @@ __global__ __launch_bounds__(256, 2) void k_force(GDev P0, const double *__restr
     const double *V = V0 + SY.g_off;
     double *ZE = ZE0 + 10 * pr.sys;
     const int lane = threadIdx.x & 63, w = wave_id();
-    double dreg[4][4][4];
-    load_dsym(P, pr, D, dreg);
-    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     const int aw = pr.a[w];
+    double dw[4][4];
+    load_dsym_row(P, pr, D, w, dw);
+    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt);
+        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt, maskt);
         __syncthreads();
-        psi_tiles(dreg, phiB, maskpt);
+        d4 c[4];
+        psi_row(dw, phiB, maskt, c);
         __syncthreads();
+        store_psi(c, phiB, maskt);
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const Pt r = bigcell_point(P, o, lane);
-            const GAtom at = ldc(P.atoms + (aw));
+            const GAtom at = ldc(P.atoms + aw);
             const double x = r.x - at.x - pr.shiftA[0];
             const double y = r.y - at.y - pr.shiftA[1];
             const double zz = r.z - at.z - pr.shiftA[2];
             const double r2 = x * x + y * y + zz * zz;
             double e, G[3];
-            dot_phi_grad(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
+            dot_phi<true>(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
             const double wv = P.w * V[r.g];
-            const double c = 2.0 * wv;
-            f[0] += c * G[0];
-            f[1] += c * G[1];
-            f[2] += c * G[2];
+            const double c2 = 2.0 * wv;
+            f[0] += c2 * G[0];
+            f[1] += c2 * G[1];
+            f[2] += c2 * G[2];
             const double xs[3] = {x, y, zz};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) z[3 * a + b] += c * G[a] * xs[b];
+                for (int b = 0; b < 3; ++b) z[3 * a + b] += c2 * G[a] * xs[b];
             en += wv * e;
         }
         __syncthreads();
