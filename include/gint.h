@@ -170,6 +170,14 @@ int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, vo
 int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals,
                       double *force, double *stress, double *energy, void *stream);
 
+/* rho (Eq. 3), the force and stress (Eq. 4-5) and E in one pass: the same
+ * outputs as gint_rho followed by gint_force_stress, for callers that need
+ * both (the per-point values phi_A . psi_A that E needs are the terms of rho,
+ * so rho costs little on top of the force pass).  n_elec and energy may be
+ * NULL; every other output is overwritten. */
+int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, double *rho,
+                          double *n_elec, double *force, double *stress, double *energy, void *stream);
+
 /* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
  * the unit of work of the throughput metric, counted exactly from the plan's
  * neighbour lists.  w_out: device f64[n_sys], overwritten. */

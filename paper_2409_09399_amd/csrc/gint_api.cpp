@@ -14,7 +14,8 @@
 hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s);
 hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s);
-hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, hipStream_t s);
+hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, double *rho,
+                             hipStream_t s);
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s);
 hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
                                hipStream_t s);
@@ -26,7 +27,7 @@ hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long 
                                  hipStream_t s);
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s);
 hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
-                                hipStream_t s);
+                                double *rho, hipStream_t s);
 
 namespace {
 
@@ -219,18 +220,36 @@ int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, vo
     return GINT_OK;
 }
 
+namespace {
+
+// force/stress (and rho when given) in one pass over the ordered pairs
+int force_pass(gint_plan *p, const double *v_loc, const double *d_vals, double *rho, double *n_elec,
+               double *force, double *stress, double *energy, hipStream_t s) {
+    hipError_t e = gint_launch_fill(force, 3LL * p->sizes.natom, 0.0, s);
+    if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10LL * p->n_sys, 0.0, s);
+    if (e == hipSuccess && rho) e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
+    if (e == hipSuccess)
+        e = p->precision == GINT_FP64
+                ? gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, rho, s)
+                : gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, rho, s);
+    if (e == hipSuccess) e = gint_launch_finish_stress(p->ordered, p->ZE, stress, energy, s);
+    if (e == hipSuccess && rho && n_elec) e = gint_launch_seg_sum(p->canon, rho, p->part, kParts, n_elec, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return GINT_OK;
+}
+
+}  // namespace
+
 int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, double *force, double *stress,
                       double *energy, void *stream) {
     if (!p || !v_loc || !d_vals || !force || !stress) return GINT_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    hipError_t e = gint_launch_fill(force, 3LL * p->sizes.natom, 0.0, s);
-    if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10LL * p->n_sys, 0.0, s);
-    if (e == hipSuccess)
-        e = p->precision == GINT_FP64 ? gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, s)
-                                      : gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, s);
-    if (e == hipSuccess) e = gint_launch_finish_stress(p->ordered, p->ZE, stress, energy, s);
-    if (e != hipSuccess) return hip_fail(e);
-    return GINT_OK;
+    return force_pass(p, v_loc, d_vals, nullptr, nullptr, force, stress, energy, (hipStream_t)stream);
+}
+
+int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, double *rho, double *n_elec,
+                          double *force, double *stress, double *energy, void *stream) {
+    if (!p || !v_loc || !d_vals || !rho || !force || !stress) return GINT_EINVAL;
+    return force_pass(p, v_loc, d_vals, rho, n_elec, force, stress, energy, (hipStream_t)stream);
 }
 
 // W = sum_g n_orb(g)^2, the unit of work of the throughput metric.

@@ -487,14 +487,19 @@ __global__ __launch_bounds__(256, 3) void k_rho(GDev P0, const double *__restric
 // ---------------------------------------------------------------------------
 // Pulay force and strain derivative (Eq. 4-5): ordered pairs, A side only.
 // Wave w owns A atom slot w (psi by MFMA, then grad phi . psi per point).
+// With RHO the per-point values phi_A . psi_A, which the energy needs anyway,
+// are also added into rho: over the two orders of a pair they give rho's
+// weight 2 off the self pair, so one pass yields rho, F, Z and E.
 // ---------------------------------------------------------------------------
+template <bool RHO>
 __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restrict__ V0,
                                                   const double *__restrict__ D, double *__restrict__ F,
-                                                  double *__restrict__ ZE0) {
+                                                  double *__restrict__ ZE0, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ unsigned maskt[4];
     __shared__ double red[4][10];
+    __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
@@ -506,6 +511,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     double *ZE = ZE0 + 10 * pr.sys;
+    double *rho = RHO ? rho0 + SY.g_off : nullptr;
     const int lane = threadIdx.x & 63, w = wave_id();
     const int aw = pr.a[w];
     double dw[4][4];
@@ -523,6 +529,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
         psi_row(dw, phiB, maskt, c);
         __syncthreads();
         store_psi(c, phiB, maskt);
+        double e = 0.0;
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const Pt r = bigcell_point(P, o, lane);
             const GAtom at = ldc(P.atoms + aw);
@@ -530,7 +537,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
             const double y = r.y - at.y - pr.shiftA[1];
             const double zz = r.z - at.z - pr.shiftA[2];
             const double r2 = x * x + y * y + zz * zz;
-            double e, G[3];
+            double G[3];
             dot_phi<true>(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
             const double wv = P.w * V[r.g];
             const double c2 = 2.0 * wv;
@@ -543,6 +550,17 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
 #pragma unroll
                 for (int b = 0; b < 3; ++b) z[3 * a + b] += c2 * G[a] * xs[b];
             en += wv * e;
+        }
+        if (RHO) {
+            part[w][lane] = e;
+            __syncthreads();
+            if (threadIdx.x < GINT_BCPTS) {
+                const int pt = threadIdx.x;
+                if ((maskpt[pt] & 0xFu) && (maskpt[pt] & 0xF0u)) {
+                    const Pt r = bigcell_point(P, o, pt);
+                    atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
+                }
+            }
         }
         __syncthreads();
     }
@@ -741,8 +759,10 @@ hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStrea
     GINT_PERSISTENT_LAUNCH(k_rho, P, s, D, rho);
 }
 
-hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, hipStream_t s) {
-    GINT_PERSISTENT_LAUNCH(k_force, P, s, V, D, F, ZE);
+hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, double *rho,
+                             hipStream_t s) {
+    if (rho) GINT_PERSISTENT_LAUNCH(k_force<true>, P, s, V, D, F, ZE, rho);
+    GINT_PERSISTENT_LAUNCH(k_force<false>, P, s, V, D, F, ZE, nullptr);
 }
 
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
@@ -769,6 +789,7 @@ hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *st
 void gint_prime_grids_fp64() {
     gint_resident_blocks((const void *)k_vlocal);
     gint_resident_blocks((const void *)k_rho);
-    gint_resident_blocks((const void *)k_force);
+    gint_resident_blocks((const void *)k_force<false>);
+    gint_resident_blocks((const void *)k_force<true>);
     gint_resident_blocks((const void *)k_work);
 }

@@ -564,15 +564,16 @@ __global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__rest
 // Pulay force and strain derivative (Eq. 4-5), mixed precision: ordered
 // pairs, A side; FP32 per-point terms, FP64 accumulation.
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, bool RHO>
 __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__restrict__ V0,
                                                      const double *__restrict__ D, double *__restrict__ F,
-                                                     double *__restrict__ ZE0) {
+                                                     double *__restrict__ ZE0, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) T tB[2][GINT_BCPTS][RSTR];
     __shared__ float psi[GINT_BCPTS * FSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ double red[4][10];
+    __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
@@ -584,6 +585,7 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     double *ZE = ZE0 + 10 * pr.sys;
+    double *rho = RHO ? rho0 + SY.g_off : nullptr;
     const int lane = threadIdx.x & 63, w = wave_id();
     vec dh[4][2], dl[4][2];
     const float sphi = (float)P0.phi_scale;
@@ -598,6 +600,7 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
         __syncthreads();
         psi_mx<T>(dh, dl, tB, psi, maskpt, unscale);
         __syncthreads();
+        double ev = 0.0;
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const P3 r = point_of(P, o, lane);
             const GAtom at = ldc(P.atoms + (aw));
@@ -621,6 +624,19 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
 #pragma unroll
                 for (int b = 0; b < 3; ++b) z[3 * a + b] += c * gs[a] * xs[b];
             en += wv * (double)e;
+            ev = (double)e;
+        }
+        if (RHO) {
+            part[w][lane] = ev;
+            __syncthreads();
+            if (threadIdx.x < GINT_BCPTS) {
+                const int pt = threadIdx.x;
+                const unsigned m = maskpt[pt];
+                if ((m & 0xFu) && (m & 0xF0u)) {
+                    const P3 r = point_of(P, o, pt);
+                    atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
+                }
+            }
         }
         __syncthreads();
     }
@@ -696,9 +712,12 @@ hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *
 }
 
 hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
-                                hipStream_t s) {
-    return prec == 2 ? launch_persistent(k_force_mx<__bf16>, P, s, V, D, F, ZE)
-                     : launch_persistent(k_force_mx<_Float16>, P, s, V, D, F, ZE);
+                                double *rho, hipStream_t s) {
+    if (rho)
+        return prec == 2 ? launch_persistent(k_force_mx<__bf16, true>, P, s, V, D, F, ZE, rho)
+                         : launch_persistent(k_force_mx<_Float16, true>, P, s, V, D, F, ZE, rho);
+    return prec == 2 ? launch_persistent(k_force_mx<__bf16, false>, P, s, V, D, F, ZE, (double *)nullptr)
+                     : launch_persistent(k_force_mx<_Float16, false>, P, s, V, D, F, ZE, (double *)nullptr);
 }
 
 int gint_resident_blocks(const void *kernel);
@@ -707,10 +726,12 @@ void gint_prime_grids_mx(int prec) {
     if (prec == 2) {
         gint_resident_blocks((const void *)k_vlocal_mx<__bf16>);
         gint_resident_blocks((const void *)k_rho_mx<__bf16>);
-        gint_resident_blocks((const void *)k_force_mx<__bf16>);
+        gint_resident_blocks((const void *)k_force_mx<__bf16, false>);
+        gint_resident_blocks((const void *)k_force_mx<__bf16, true>);
     } else {
         gint_resident_blocks((const void *)k_vlocal_mx<_Float16>);
         gint_resident_blocks((const void *)k_rho_mx<_Float16>);
-        gint_resident_blocks((const void *)k_force_mx<_Float16>);
+        gint_resident_blocks((const void *)k_force_mx<_Float16, false>);
+        gint_resident_blocks((const void *)k_force_mx<_Float16, true>);
     }
 }

@@ -67,7 +67,7 @@ class gint_tune_report(C.Structure):
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
-            "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
+            "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
             "gint_last_hip_error"]
 
@@ -106,6 +106,7 @@ def _load():
         getattr(lib, name).argtypes = [P, P, P, P]
     lib.gint_rho.argtypes = [P, P, P, P, P]
     lib.gint_force_stress.argtypes = [P, P, P, P, P, P, P]
+    lib.gint_rho_force_stress.argtypes = [P] * 9
     lib.gint_work_units.argtypes = [P, P, P]
     lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
     lib.gint_plan_query_system.argtypes = [P, C.c_int, C.POINTER(gint_system_sizes)]
@@ -322,3 +323,13 @@ def autotune(system, precision: int = GINT_FP64, budget_seconds: float = 2.0, st
     return ({"cluster_atoms": int(opt.cluster_atoms), "max_bigcells_per_item": int(opt.max_bigcells_per_item),
              "precision": precision},
             {"trials": trials, "best": int(rep.best), "seconds": float(rep.seconds)})
+
+
+def gint_rho_force_stress(plan: Plan, v_loc, d_vals, rho, force, stress, n_elec=None, energy=None, stream=None):
+    ne = _dev_ptr(n_elec, plan.n_sys, "n_elec") if n_elec is not None else None
+    en = _dev_ptr(energy, plan.n_sys, "energy") if energy is not None else None
+    _check(_lib.gint_rho_force_stress(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"),
+                                      _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(rho, plan.ngrid, "rho"), ne,
+                                      _dev_ptr(force, 3 * plan.natom, "force"),
+                                      _dev_ptr(stress, 9 * plan.n_sys, "stress"), en, _stream(stream)),
+           "gint_rho_force_stress")

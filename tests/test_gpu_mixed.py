@@ -106,3 +106,29 @@ def test_mixed_tbg868_sampled(torch_dev, oracle_mod, prec):
     record("tbg868_sampled", prec, errs)
     for k in errs:
         assert errs[k] <= BOUNDS[prec][k], (k, errs[k])
+
+
+@pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
+def test_mixed_three_species(torch_dev, oracle_mod, prec):
+    """Species with different channel sets (spd, sp, 2s2p1d) in a skewed cell,
+    against the full oracle, at the same bounds."""
+    from paper_2409_09399_amd import gint as G
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    rng = np.random.default_rng(7)
+    sps = [I.make_species("X", "spd", 4.1, 0.01, rng), I.make_species("Y", "sp", 3.3, 0.02, rng),
+           I.make_species("Z", "2s2p1d", 5.0, 0.01, rng)]
+    cell = np.array([[5.1, 0.0, 0.0], [1.2, 4.6, 0.0], [0.4, -0.7, 5.5]])
+    pos = rng.uniform(0, 1, size=(5, 3)) @ cell
+    grid = (20, 18, 22)
+    millers = I.random_millers_box(rng, 8, 2)
+    v = I.plane_wave_potential(grid, millers, np.full(8, 0.3), rng.uniform(0, 6.28, 8))
+    s = I.assemble(cell, pos, np.array([0, 1, 2, 1, 0]), sps, grid, v, rng, name="mixed5")
+    o = oracle_mod.Oracle(s)
+    F, Z, E, sig = o.force_stress()
+    ref = dict(h=o.vlocal(), rho=o.rho(), F=F, sig=sig, E=E)
+    errs = errors(run(G, torch, dev, s, prec), ref)
+    print("[mixed] three species", prec, errs, flush=True)
+    record("mixed5", prec, errs)
+    for k, b in BOUNDS[prec].items():
+        assert errs[k] <= b, (k, errs[k], b)

@@ -175,3 +175,45 @@ def test_tbg868_identities(tbg868, oracle_mod):
     assert gpu["W"] == oracle_mod.Oracle(s).work()
     # translation: total force of a constant potential vanishes
     assert np.isfinite(gpu["sig"]).all()
+
+
+@pytest.mark.parametrize("case", ["diamond", "tbg76", "mixed5"])
+def test_fused_rho_force(G, torch_dev, oracle_mod, case):
+    """gint_rho_force_stress (one pass over the ordered pairs) gives the same
+    rho, N_e, F, sigma and E as the separate calls, to the FP64 bar."""
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    if case == "diamond":
+        s = I.diamond8(3)
+    elif case == "tbg76":
+        s = I.tbg_system(2, grid=(40, 40, 96))
+    else:
+        rng = np.random.default_rng(7)
+        sps = [I.make_species("X", "spd", 4.1, 0.01, rng), I.make_species("Y", "sp", 3.3, 0.02, rng),
+               I.make_species("Z", "2s2p1d", 5.0, 0.01, rng)]
+        cell = np.array([[5.1, 0.0, 0.0], [1.2, 4.6, 0.0], [0.4, -0.7, 5.5]])
+        pos = rng.uniform(0, 1, size=(5, 3)) @ cell
+        grid = (20, 18, 22)
+        v = I.plane_wave_potential(grid, I.random_millers_box(rng, 8, 2), np.full(8, 0.3), rng.uniform(0, 6.28, 8))
+        s = I.assemble(cell, pos, np.array([0, 1, 2, 1, 0]), sps, grid, v, rng, name="mixed5")
+    print(f"[gpu] fused rho+force {s.name}", flush=True)
+    plan = G.Plan(s)
+    v = torch.tensor(s.v, device=dev)
+    d = torch.tensor(s.d, device=dev)
+    rho = torch.full((s.ngrid,), float("nan"), dtype=torch.float64, device=dev)
+    ne = torch.zeros(1, dtype=torch.float64, device=dev)
+    F = torch.full((s.natom * 3,), float("nan"), dtype=torch.float64, device=dev)
+    sig = torch.full((9,), float("nan"), dtype=torch.float64, device=dev)
+    E = torch.zeros(1, dtype=torch.float64, device=dev)
+    G.gint_rho_force_stress(plan, v, d, rho, F, sig, n_elec=ne, energy=E)
+    torch.cuda.synchronize()
+    o = oracle_mod.Oracle(s)
+    Fo, Zo, Eo, sigo = o.force_stress()
+    rho_o = o.rho()
+    assert rel(rho.cpu().numpy(), rho_o) <= TOL
+    assert rel(F.cpu().numpy().reshape(-1, 3), Fo) <= TOL
+    assert rel(sig.cpu().numpy().reshape(3, 3), sigo) <= TOL
+    assert abs(float(E.cpu()[0]) - Eo) <= TOL * abs(Eo)
+    ne_o = float(rho_o.sum()) * s.volume / s.ngrid
+    assert abs(float(ne.cpu()[0]) - ne_o) <= TOL * abs(ne_o)
+    plan.close()
