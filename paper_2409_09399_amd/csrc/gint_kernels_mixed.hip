@@ -369,75 +369,63 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
 
 namespace {
 
-// D_sym blocks as 16-bit hi/lo MFMA B operands for psi = phi_B D^T:
+// Row atom i of D_sym as 16-bit hi/lo MFMA B operands for psi = phi_B D^T:
 // k-step kk covers B atoms 2kk, 2kk+1; lane l holds mu = l & 15 and
 // nu' = 8 (l >> 4) + e, i.e. atom 2kk + (l >> 5), orbital 8 ((l >> 4) & 1) + e.
+// The row is scaled by a power of two (its largest entry maps below 2^13);
+// returns the factor that undoes the scales of phi and D in psi.
 template <class T>
-__device__ inline float load_dsym16(const GDev &P, CPair &pr, const double *__restrict__ D, float sphi,
-                                    typename Split16<T>::vec dh[4][2], typename Split16<T>::vec dl[4][2]) {
+__device__ inline float load_dsym16_row(const GDev &P, CPair &pr, const double *__restrict__ D, int i, float sphi,
+                                        typename Split16<T>::vec dh[2], typename Split16<T>::vec dl[2]) {
     const int lane = threadIdx.x & 63;
     const int mu = lane & 15;
-    float val[4][2][8];
+    const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
+    float val[2][8];
     float m = 0.f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int kk = 0; kk < 2; ++kk) {
+        const int j = 2 * kk + (lane >> 5);
+        const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
+        const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk) {
-            const int j = 2 * kk + (lane >> 5);
-            const long long o = pr.hoff[i * 4 + j], ot = pr.hoff_t[i * 4 + j];
-            const int na = pr.a[i] >= 0 ? cst(P.atoms)[pr.a[i]].norb : 0;
-            const int nb = pr.b[j] >= 0 ? cst(P.atoms)[pr.b[j]].norb : 0;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int nu = 8 * ((lane >> 4) & 1) + e;
-                float v = 0.f;
-                if (o >= 0 && ot >= 0 && mu < na && nu < nb)
-                    v = (float)(0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]));
-                val[i][kk][e] = v;
-                m = fmaxf(m, fabsf(v));
-            }
+        for (int e = 0; e < 8; ++e) {
+            const int nu = 8 * ((lane >> 4) & 1) + e;
+            float v = 0.f;
+            if (o >= 0 && ot >= 0 && mu < na && nu < nb)
+                v = (float)(0.5 * (D[o + (long long)mu * nb + nu] + D[ot + (long long)nu * na + mu]));
+            val[kk][e] = v;
+            m = fmaxf(m, fabsf(v));
         }
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     const float sD = pow2_scale((double)m);
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
-        for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                T hi, lo;
-                Split16<T>::split(val[i][kk][e] * sD, hi, lo);
-                dh[i][kk][e] = hi;
-                dl[i][kk][e] = lo;
-            }
+        for (int e = 0; e < 8; ++e) {
+            T hi, lo;
+            Split16<T>::split(val[kk][e] * sD, hi, lo);
+            dh[kk][e] = hi;
+            dl[kk][e] = lo;
+        }
     return 1.f / (sphi * sD);   // psi = (phi sphi)(D sD) / (sphi sD), exact
 }
 
 constexpr int RSTR = 72;   // 16-bit elements per point row of the B tile (4 slots x 16 + 8)
-constexpr int FSTR = 65;   // floats per point row of FP32 tiles
+constexpr int FSTR = 65;   // floats per point row of the FP32 psi tile
 
-// Phase 1 of rho/force: B orbitals as 16-bit hi/lo rows [h][point][slot*16+mu];
-// A orbitals in FP32 (rho) or only their activity (force).
-template <class T, bool WANT_A>
-__device__ inline void stage_rho(const GDev &P, CPair &pr, const GBig &o, float sphi, T (*tB)[GINT_BCPTS][RSTR],
-                                 float *pA, unsigned *maskpt) {
+// Phase 1 of rho/force: B orbitals (scaled by sphi) as 16-bit hi/lo rows
+// [h][point][slot*16+mu]; A atoms only mark where they are active.
+template <class T>
+__device__ inline void stage_b16(const GDev &P, CPair &pr, const GBig &o, float sphi, T (*tB)[GINT_BCPTS][RSTR],
+                                 unsigned *maskpt, unsigned *maskt) {
     const int lane = threadIdx.x & 63, w = wave_id();
     const int pt = lane;
     const P3 r = point_of(P, o, pt);
     unsigned bits = 0;
     const int a = pr.a[w], b = pr.b[w];
     const Disp da = disp_of(P, r, a, pr.shiftA);
-    if (WANT_A) {
-        float *dst = pA + pt * FSTR + w * 16;
-        if (da.in) {
-            CSpecies &sp = cst(P.species)[cst(P.atoms)[a].species];
-            eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float v) { dst[mu] = v; });
-        } else {
-#pragma unroll
-            for (int mu = 0; mu < 16; ++mu) dst[mu] = 0.f;
-        }
-    }
     if (da.in) bits |= 1u << w;
     const Disp db = disp_of(P, r, b, pr.shiftB);
     T *h0 = &tB[0][pt][w * 16];
@@ -458,61 +446,78 @@ __device__ inline void stage_rho(const GDev &P, CPair &pr, const GBig &o, float 
             h1[mu] = (T)0.f;
         }
     }
-    if (bits) atomicOr(&maskpt[pt], bits);
+    if (bits) {
+        atomicOr(&maskpt[pt], bits);
+        atomicOr(&maskt[pt >> 4], bits);
+    }
 }
 
-// Phase 2: psi[pt][a_i][mu] = sum_{b, nu} phi_B[pt][b][nu] D_sym[a_i mu][b nu] for
-// the wave's 16 points (FP32 result into psi rows of FSTR floats).
+// Phase 2: wave w computes psi[pt][mu] = sum_{b, nu} phi_B[pt][b nu]
+// D_sym[a_w mu][b nu] for the 64 points (four 16-point tiles; tiles where a_w
+// is inactive and B-atom pairs inactive on a tile are skipped).  MFMA layout:
+// c[t] lane l register q holds point 16 t + 4 (l >> 4) + q, orbital l & 15.
 template <class T>
-__device__ inline void psi_mx(const typename Split16<T>::vec dh[4][2], const typename Split16<T>::vec dl[4][2],
-                              T (*tB)[GINT_BCPTS][RSTR], float *psi, const unsigned *maskpt, float unscale) {
+__device__ inline void psi_row16(const typename Split16<T>::vec dh[2], const typename Split16<T>::vec dl[2],
+                                 T (*tB)[GINT_BCPTS][RSTR], const unsigned *maskt, f4v c[4]) {
     typedef typename Split16<T>::vec vec;
     const int lane = threadIdx.x & 63, w = wave_id();
-    unsigned gm = maskpt[16 * w + (lane & 15)];
-    gm |= __shfl_xor(gm, 1);
-    gm |= __shfl_xor(gm, 2);
-    gm |= __shfl_xor(gm, 4);
-    gm |= __shfl_xor(gm, 8);
-    gm = __builtin_amdgcn_readfirstlane(gm);
-    const int pt = 16 * w + (lane & 15);
-    const int off = 32 * 0 + 16 * (lane >> 5) + 8 * ((lane >> 4) & 1);   // within a 2-atom k-step
-    vec bh[2], bl[2];
+    const int off = 8 * (lane >> 4);
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk) {
-        bh[kk] = *(const vec *)&tB[0][pt][32 * kk + off];
-        bl[kk] = *(const vec *)&tB[1][pt][32 * kk + off];
-    }
-    float *dst = psi + (16 * w + 4 * (lane >> 4)) * FSTR + (lane & 15);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (!(gm & (1u << i))) continue;
-        f4v c = (f4v){0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 4; ++t) {
+        c[t] = (f4v){0.f, 0.f, 0.f, 0.f};
+        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        if (!(gm & (1u << w))) continue;
+        const int pt = 16 * t + (lane & 15);
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             if (!(gm & (3u << (4 + 2 * kk)))) continue;
-            c = Split16<T>::mfma(bh[kk], dh[i][kk], c);
-            c = Split16<T>::mfma(bh[kk], dl[i][kk], c);
-            c = Split16<T>::mfma(bl[kk], dh[i][kk], c);
+            const vec ah = *(const vec *)&tB[0][pt][32 * kk + off];
+            const vec al = *(const vec *)&tB[1][pt][32 * kk + off];
+            c[t] = Split16<T>::mfma(ah, dh[kk], c[t]);
+            c[t] = Split16<T>::mfma(ah, dl[kk], c[t]);
+            c[t] = Split16<T>::mfma(al, dh[kk], c[t]);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) dst[q * FSTR + i * 16] = c[q] * unscale;
     }
 }
+
+// psi of slot w into its columns of the FP32 tile (after every wave has read tB).
+__device__ inline void store_psi32(const f4v c[4], float *psi, const unsigned *maskt, float unscale) {
+    const int lane = threadIdx.x & 63, w = wave_id();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        if (!(gm & (1u << w))) continue;
+        float *dst = psi + (16 * t + 4 * (lane >> 4)) * FSTR + w * 16 + (lane & 15);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dst[q * FSTR] = c[t][q] * unscale;
+    }
+}
+
+// LDS of the rho/force kernels: the B tile, reused for psi after phase 2.
+template <class T>
+struct TileBuf {
+    static constexpr int bytes = 2 * GINT_BCPTS * RSTR * (int)sizeof(T);
+    static_assert(bytes >= GINT_BCPTS * FSTR * (int)sizeof(float), "psi must fit in the B tile");
+};
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// rho_g (Eq. 3), mixed precision: canonical pairs, weight 2 off the self pair
+// rho_g (Eq. 3), mixed precision: canonical pairs, weight 2 off the self
+// pair.  Wave w owns A atom slot w: psi by MFMA, then per point (lane)
+// phi_{a_w} . psi with phi evaluated on the fly.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, 3) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
-    __shared__ __attribute__((aligned(16))) T tB[2][GINT_BCPTS][RSTR];
-    __shared__ float pA[GINT_BCPTS * FSTR];
-    __shared__ float psi[GINT_BCPTS * FSTR];
+    __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ unsigned maskt[4];
     __shared__ float part[4][GINT_BCPTS];
     __shared__ int s_item;
+    T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
+    float *psi = reinterpret_cast<float *>(buf);
+    const float sphi = (float)P0.phi_scale;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -523,25 +528,29 @@ __global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__rest
     CSys &SY = cst(P0.sys)[pr.sys];
     double *rho = rho0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
-    vec dh[4][2], dl[4][2];
-    const float sphi = (float)P0.phi_scale;
-    const float unscale = load_dsym16<T>(P, pr, D, sphi, dh, dl);
+    const int aw = pr.a[w];
+    vec dh[2], dl[2];
+    const float unscale = load_dsym16_row<T>(P, pr, D, w, sphi, dh, dl);
     const double weight = pr.self ? 1.0 : 2.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_rho<T, true>(P, pr, o, sphi, tB, pA, maskpt);
+        stage_b16<T>(P, pr, o, sphi, tB, maskpt, maskt);
         __syncthreads();
-        psi_mx<T>(dh, dl, tB, psi, maskpt, unscale);
+        f4v c[4];
+        psi_row16<T>(dh, dl, tB, maskt, c);
         __syncthreads();
+        store_psi32(c, psi, maskt, unscale);
         {
             float v = 0.f;
-            if (maskpt[lane] & (1u << w)) {
-                const float *a = pA + lane * FSTR + w * 16;
-                const float *s = psi + lane * FSTR + w * 16;
-#pragma unroll
-                for (int mu = 0; mu < 16; ++mu) v += a[mu] * s[mu];
+            if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+                const P3 r = point_of(P, o, lane);
+                const Disp da = disp_of(P, r, aw, pr.shiftA);
+                const float *ps = psi + lane * FSTR + w * 16;
+                CSpecies &sp = cst(P.species)[cst(P.atoms)[aw].species];
+                eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float x) { v += x * ps[mu]; });
             }
             part[w][lane] = v;
         }
@@ -562,19 +571,23 @@ __global__ __launch_bounds__(256, 2) void k_rho_mx(GDev P0, const double *__rest
 
 // ---------------------------------------------------------------------------
 // Pulay force and strain derivative (Eq. 4-5), mixed precision: ordered
-// pairs, A side; FP32 per-point terms, FP64 accumulation.
+// pairs, A side; FP32 per-point terms, FP64 accumulation.  With RHO the
+// per-point values phi_A . psi_A are also added into rho (see k_force).
 // ---------------------------------------------------------------------------
 template <class T, bool RHO>
-__global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__restrict__ V0,
+__global__ __launch_bounds__(256, 3) void k_force_mx(GDev P0, const double *__restrict__ V0,
                                                      const double *__restrict__ D, double *__restrict__ F,
                                                      double *__restrict__ ZE0, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
-    __shared__ __attribute__((aligned(16))) T tB[2][GINT_BCPTS][RSTR];
-    __shared__ float psi[GINT_BCPTS * FSTR];
+    __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ unsigned maskt[4];
     __shared__ double red[4][10];
     __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
+    T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
+    float *psi = reinterpret_cast<float *>(buf);
+    const float sphi = (float)P0.phi_scale;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -587,23 +600,25 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
     double *ZE = ZE0 + 10 * pr.sys;
     double *rho = RHO ? rho0 + SY.g_off : nullptr;
     const int lane = threadIdx.x & 63, w = wave_id();
-    vec dh[4][2], dl[4][2];
-    const float sphi = (float)P0.phi_scale;
-    const float unscale = load_dsym16<T>(P, pr, D, sphi, dh, dl);
-    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     const int aw = pr.a[w];
+    vec dh[2], dl[2];
+    const float unscale = load_dsym16_row<T>(P, pr, D, w, sphi, dh, dl);
+    double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
+        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_rho<T, false>(P, pr, o, sphi, tB, nullptr, maskpt);
+        stage_b16<T>(P, pr, o, sphi, tB, maskpt, maskt);
         __syncthreads();
-        psi_mx<T>(dh, dl, tB, psi, maskpt, unscale);
+        f4v c[4];
+        psi_row16<T>(dh, dl, tB, maskt, c);
         __syncthreads();
+        store_psi32(c, psi, maskt, unscale);
         double ev = 0.0;
         if (aw >= 0 && (maskpt[lane] & (1u << w))) {
             const P3 r = point_of(P, o, lane);
-            const GAtom at = ldc(P.atoms + (aw));
+            const GAtom at = ldc(P.atoms + aw);
             const double dx = r.x - at.x - pr.shiftA[0], dy = r.y - at.y - pr.shiftA[1],
                          dz = r.z - at.z - pr.shiftA[2];
             const float x = (float)dx, y = (float)dy, zz = (float)dz;
@@ -613,16 +628,16 @@ __global__ __launch_bounds__(256, 2) void k_force_mx(GDev P0, const double *__re
             dot_grad32(sp, P.tab32, x, y, zz, knot_of(sp, rr), rr > 0.0 ? (float)(1.0 / rr) : 0.f,
                        psi + lane * FSTR + w * 16, e, G);
             const double wv = P.w * V[r.g];
-            const double c = 2.0 * wv;
+            const double c2 = 2.0 * wv;
             const double g0 = G[0], g1 = G[1], g2 = G[2];
-            f[0] += c * g0;
-            f[1] += c * g1;
-            f[2] += c * g2;
+            f[0] += c2 * g0;
+            f[1] += c2 * g1;
+            f[2] += c2 * g2;
             const double gs[3] = {g0, g1, g2}, xs[3] = {dx, dy, dz};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
-                for (int b = 0; b < 3; ++b) z[3 * a + b] += c * gs[a] * xs[b];
+                for (int b = 0; b < 3; ++b) z[3 * a + b] += c2 * gs[a] * xs[b];
             en += wv * (double)e;
             ev = (double)e;
         }
