@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
 // atom slot w: psi of a_w for the 64 points by MFMA, then per point (lane)
 // phi_{a_w} . psi evaluated on the fly.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 3) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
     __shared__ unsigned maskt[4];

@@ -508,7 +508,7 @@ struct TileBuf {
 // phi_{a_w} . psi with phi evaluated on the fly.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256, 3) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[GINT_BCPTS];
