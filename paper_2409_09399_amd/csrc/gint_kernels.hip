@@ -93,6 +93,25 @@ __device__ inline void solid9(double x, double y, double z, double S[9]) {
     S[8] = kC2c * (x * x - y * y);
 }
 
+// Table values (f, f') of up to RCH channels at knots k and k + 1, all
+// loads issued before any is used: a channel loop that loads as it goes
+// waits one memory round trip per channel.
+constexpr int RCH = 5;
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+struct Rows {
+    dbl2 a[RCH], b[RCH];    // (f_k, f'_k) and (f_k+1, f'_k+1) of channel c0 + q
+};
+
+__device__ inline void load_rows(const Herm &h, int nchan, int c0, Rows &R) {
+#pragma unroll
+    for (int q = 0; q < RCH; ++q)
+        if (c0 + q < nchan) {
+            R.a[q] = *(const dbl2 *)(h.row0 + 2 * (c0 + q));
+            R.b[q] = *(const dbl2 *)(h.row1 + 2 * (c0 + q));
+        }
+}
+
 // phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
 // (LDS); slots past the atom's orbitals are zero.
 __device__ inline void eval_phi(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
@@ -101,26 +120,32 @@ __device__ inline void eval_phi(CSpecies &sp, const double *tab, double x, doubl
     const Herm h = hermite(sp, tab, r);
     double S[9];
     solid9(x, y, z, S);
+    const int nchan = sp.nchan;
     int slot = 0;
-    for (int c = 0; c < sp.nchan; ++c) {
-        const double p = (h.h00 * h.row0[2 * c] + h.h10 * h.row0[2 * c + 1] + h.h01 * h.row1[2 * c] +
-                          h.h11 * h.row1[2 * c + 1]) * scale;
-        const int l = sp.chan_l[c];
-        if (l == 0) {
-            dst[slot] = p * S[0];
-            slot += 1;
-        } else if (l == 1) {
-            dst[slot] = p * S[1];
-            dst[slot + 1] = p * S[2];
-            dst[slot + 2] = p * S[3];
-            slot += 3;
-        } else {
-            dst[slot] = p * S[4];
-            dst[slot + 1] = p * S[5];
-            dst[slot + 2] = p * S[6];
-            dst[slot + 3] = p * S[7];
-            dst[slot + 4] = p * S[8];
-            slot += 5;
+    for (int c0 = 0; c0 < nchan; c0 += RCH) {
+        Rows R;
+        load_rows(h, nchan, c0, R);
+#pragma unroll
+        for (int q = 0; q < RCH; ++q) {
+            if (c0 + q >= nchan) break;
+            const double p = (h.h00 * R.a[q].x + h.h10 * R.a[q].y + h.h01 * R.b[q].x + h.h11 * R.b[q].y) * scale;
+            const int l = sp.chan_l[c0 + q];
+            if (l == 0) {
+                dst[slot] = p * S[0];
+                slot += 1;
+            } else if (l == 1) {
+                dst[slot] = p * S[1];
+                dst[slot + 1] = p * S[2];
+                dst[slot + 2] = p * S[3];
+                slot += 3;
+            } else {
+                dst[slot] = p * S[4];
+                dst[slot + 1] = p * S[5];
+                dst[slot + 2] = p * S[6];
+                dst[slot + 3] = p * S[7];
+                dst[slot + 4] = p * S[8];
+                slot += 5;
+            }
         }
     }
     for (; slot < GINT_ORB; ++slot) dst[slot] = 0.0;
@@ -141,39 +166,46 @@ __device__ inline void dot_phi(CSpecies &sp, const double *tab, double x, double
     const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
     e = 0.0;
     G[0] = G[1] = G[2] = 0.0;
+    const int nchan = sp.nchan;
     int slot = 0;
-    for (int c = 0; c < sp.nchan; ++c) {
-        const double f0 = h.row0[2 * c], fp0 = h.row0[2 * c + 1], f1 = h.row1[2 * c], fp1 = h.row1[2 * c + 1];
-        const double p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
-        const double q = GRAD ? (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r : 0.0;
-        const int l = sp.chan_l[c];
-        double A, Bx, By, Bz;   // A = sum_m psi_m S_m, B = sum_m psi_m grad S_m
-        if (l == 0) {
-            A = psi[slot] * kC0;
-            Bx = By = Bz = 0.0;
-            slot += 1;
-        } else if (l == 1) {
-            const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2];   // (y, z, x)
-            A = kC1 * (p0 * y + p1 * z + p2 * x);
-            Bx = kC1 * p2;
-            By = kC1 * p0;
-            Bz = kC1 * p1;
-            slot += 3;
-        } else {
-            const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2], p3 = psi[slot + 3],
-                         p4 = psi[slot + 4];
-            A = kC2a * (p0 * x * y + p1 * y * z + p3 * x * z) + kC2b * p2 * (2.0 * z * z - x * x - y * y) +
-                kC2c * p4 * (x * x - y * y);
-            Bx = kC2a * (p0 * y + p3 * z) - 2.0 * kC2b * p2 * x + 2.0 * kC2c * p4 * x;
-            By = kC2a * (p0 * x + p1 * z) - 2.0 * kC2b * p2 * y - 2.0 * kC2c * p4 * y;
-            Bz = kC2a * (p1 * y + p3 * x) + 4.0 * kC2b * p2 * z;
-            slot += 5;
-        }
-        e += p * A;
-        if (GRAD) {
-            G[0] += q * A * x + p * Bx;
-            G[1] += q * A * y + p * By;
-            G[2] += q * A * z + p * Bz;
+    for (int c0 = 0; c0 < nchan; c0 += RCH) {
+        Rows R;
+        load_rows(h, nchan, c0, R);
+#pragma unroll
+        for (int qq = 0; qq < RCH; ++qq) {
+            if (c0 + qq >= nchan) break;
+            const double f0 = R.a[qq].x, fp0 = R.a[qq].y, f1 = R.b[qq].x, fp1 = R.b[qq].y;
+            const double p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
+            const double q = GRAD ? (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r : 0.0;
+            const int l = sp.chan_l[c0 + qq];
+            double A, Bx, By, Bz;   // A = sum_m psi_m S_m, B = sum_m psi_m grad S_m
+            if (l == 0) {
+                A = psi[slot] * kC0;
+                Bx = By = Bz = 0.0;
+                slot += 1;
+            } else if (l == 1) {
+                const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2];   // (y, z, x)
+                A = kC1 * (p0 * y + p1 * z + p2 * x);
+                Bx = kC1 * p2;
+                By = kC1 * p0;
+                Bz = kC1 * p1;
+                slot += 3;
+            } else {
+                const double p0 = psi[slot], p1 = psi[slot + 1], p2 = psi[slot + 2], p3 = psi[slot + 3],
+                             p4 = psi[slot + 4];
+                A = kC2a * (p0 * x * y + p1 * y * z + p3 * x * z) + kC2b * p2 * (2.0 * z * z - x * x - y * y) +
+                    kC2c * p4 * (x * x - y * y);
+                Bx = kC2a * (p0 * y + p3 * z) - 2.0 * kC2b * p2 * x + 2.0 * kC2c * p4 * x;
+                By = kC2a * (p0 * x + p1 * z) - 2.0 * kC2b * p2 * y - 2.0 * kC2c * p4 * y;
+                Bz = kC2a * (p1 * y + p3 * x) + 4.0 * kC2b * p2 * z;
+                slot += 5;
+            }
+            e += p * A;
+            if (GRAD) {
+                G[0] += q * A * x + p * Bx;
+                G[1] += q * A * y + p * By;
+                G[2] += q * A * z + p * Bz;
+            }
         }
     }
 }

@@ -116,6 +116,25 @@ __device__ inline Herm32 hermite32(CSpecies &sp, const float *tab, Knot kn) {
     return h;
 }
 
+// Table values (f, f') of up to RCH32 channels at knots k and k + 1, all
+// loads issued before any is used (a loop that loads as it goes waits one
+// memory round trip per channel).
+constexpr int RCH32 = 5;
+typedef float flt2 __attribute__((ext_vector_type(2)));
+
+struct Rows32 {
+    flt2 a[RCH32], b[RCH32];
+};
+
+__device__ inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R) {
+#pragma unroll
+    for (int q = 0; q < RCH32; ++q)
+        if (c0 + q < nchan) {
+            R.a[q] = *(const flt2 *)(h.row0 + 2 * (c0 + q));
+            R.b[q] = *(const flt2 *)(h.row1 + 2 * (c0 + q));
+        }
+}
+
 // phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v).
 template <class Emit>
 __device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
@@ -124,26 +143,32 @@ __device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, 
     const float S1y = kC1f * y, S1z = kC1f * z, S1x = kC1f * x;
     const float S20 = kC2af * x * y, S21 = kC2af * y * z, S22 = kC2bf * (2.f * z * z - x * x - y * y),
                 S23 = kC2af * x * z, S24 = kC2cf * (x * x - y * y);
+    const int nchan = sp.nchan;
     int slot = 0;
-    for (int c = 0; c < sp.nchan; ++c) {
-        const float p = (h.h00 * h.row0[2 * c] + h.h10 * h.row0[2 * c + 1] + h.h01 * h.row1[2 * c] +
-                         h.h11 * h.row1[2 * c + 1]) * scale;
-        const int l = sp.chan_l[c];
-        if (l == 0) {
-            emit(slot, p * kC0f);
-            slot += 1;
-        } else if (l == 1) {
-            emit(slot, p * S1y);
-            emit(slot + 1, p * S1z);
-            emit(slot + 2, p * S1x);
-            slot += 3;
-        } else {
-            emit(slot, p * S20);
-            emit(slot + 1, p * S21);
-            emit(slot + 2, p * S22);
-            emit(slot + 3, p * S23);
-            emit(slot + 4, p * S24);
-            slot += 5;
+    for (int c0 = 0; c0 < nchan; c0 += RCH32) {
+        Rows32 R;
+        load_rows32(h, nchan, c0, R);
+#pragma unroll
+        for (int q = 0; q < RCH32; ++q) {
+            if (c0 + q >= nchan) break;
+            const float p = (h.h00 * R.a[q].x + h.h10 * R.a[q].y + h.h01 * R.b[q].x + h.h11 * R.b[q].y) * scale;
+            const int l = sp.chan_l[c0 + q];
+            if (l == 0) {
+                emit(slot, p * kC0f);
+                slot += 1;
+            } else if (l == 1) {
+                emit(slot, p * S1y);
+                emit(slot + 1, p * S1z);
+                emit(slot + 2, p * S1x);
+                slot += 3;
+            } else {
+                emit(slot, p * S20);
+                emit(slot + 1, p * S21);
+                emit(slot + 2, p * S22);
+                emit(slot + 3, p * S23);
+                emit(slot + 4, p * S24);
+                slot += 5;
+            }
         }
     }
     for (; slot < GINT_ORB; ++slot) emit(slot, 0.f);
@@ -155,12 +180,18 @@ __device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float
     const Herm32 h = hermite32(sp, tab, kn);
     e = 0.f;
     G[0] = G[1] = G[2] = 0.f;
+    const int nchan = sp.nchan;
     int slot = 0;
-    for (int c = 0; c < sp.nchan; ++c) {
-        const float f0 = h.row0[2 * c], fp0 = h.row0[2 * c + 1], f1 = h.row1[2 * c], fp1 = h.row1[2 * c + 1];
+    for (int c0 = 0; c0 < nchan; c0 += RCH32) {
+      Rows32 R;
+      load_rows32(h, nchan, c0, R);
+#pragma unroll
+      for (int qq = 0; qq < RCH32; ++qq) {
+        if (c0 + qq >= nchan) break;
+        const float f0 = R.a[qq].x, fp0 = R.a[qq].y, f1 = R.b[qq].x, fp1 = R.b[qq].y;
         const float p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
         const float q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
-        const int l = sp.chan_l[c];
+        const int l = sp.chan_l[c0 + qq];
         float A, Bx, By, Bz;
         if (l == 0) {
             A = psi[slot] * kC0f;
@@ -186,6 +217,7 @@ __device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float
         G[0] += q * A * x + p * Bx;
         G[1] += q * A * y + p * By;
         G[2] += q * A * z + p * Bz;
+      }
     }
 }
 
@@ -575,7 +607,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
 // per-point values phi_A . psi_A are also added into rho (see k_force).
 // ---------------------------------------------------------------------------
 template <class T, bool RHO>
-__global__ __launch_bounds__(256, 3) void k_force_mx(GDev P0, const double *__restrict__ V0,
+__global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__restrict__ V0,
                                                      const double *__restrict__ D, double *__restrict__ F,
                                                      double *__restrict__ ZE0, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
