@@ -206,8 +206,10 @@ typedef struct {
     long ng;
     double omega, w;
     int bs[3], M[3];          /* bin size (grid points), bin counts */
-    long *bin_ptr;
+    long *bin_ptr;            /* all bins built up front (NULL in the lazy form) */
     cand_t *cand;
+    cand_t **lazy;            /* lazy form: candidates of bin b, built on request */
+    int *lazy_n;
     int *norb;                /* per atom */
     long *orb_start;          /* unused placeholder for clarity */
     bhash hb;
@@ -233,10 +235,76 @@ static void grid_point(const ctx_t *c, const long n[3], double r[3])
 static void ctx_free(ctx_t *c)
 {
     free(c->bin_ptr); free(c->cand); free(c->norb);
+    if (c->lazy) {
+        const long nbin = (long)c->M[0] * c->M[1] * c->M[2];
+        for (long b = 0; b < nbin; ++b) free(c->lazy[b]);
+        free(c->lazy); free(c->lazy_n);
+    }
     bhash_free(&c->hb);
 }
 
-static int ctx_init(ctx_t *c, const oracle_system *s)
+/* Candidate atom images of bin b: every (atom, T) whose cutoff sphere can
+ * reach a point of the bin (centre distance < rcut + bin radius).  Appends
+ * to *buf (capacity *cap, grown as needed); returns the new count. */
+static long bin_candidates(const ctx_t *c, const oracle_system *s, long b, cand_t **buf, long *cap, long nc)
+{
+    const int b0 = (int)(b / ((long)c->M[1] * c->M[2])), b1 = (int)((b / c->M[2]) % c->M[1]), b2 = (int)(b % c->M[2]);
+    const long lo[3] = {(long)b0 * c->bs[0], (long)b1 * c->bs[1], (long)b2 * c->bs[2]};
+    long hi[3];
+    for (int a = 0; a < 3; ++a) {
+        hi[a] = lo[a] + c->bs[a] - 1;
+        if (hi[a] > c->N[a] - 1) hi[a] = c->N[a] - 1;
+    }
+    /* bin centre and radius (max distance to its corner points) */
+    double ctr[3], rad = 0.0;
+    {
+        double fl[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
+        for (int a = 0; a < 3; ++a)
+            ctr[a] = fl[0] / c->N[0] * c->cell[a] + fl[1] / c->N[1] * c->cell[3 + a] + fl[2] / c->N[2] * c->cell[6 + a];
+        for (int q = 0; q < 8; ++q) {
+            long n[3] = {(q & 1) ? hi[0] : lo[0], (q & 2) ? hi[1] : lo[1], (q & 4) ? hi[2] : lo[2]};
+            double r[3];
+            grid_point(c, n, r);
+            double d2 = 0;
+            for (int a = 0; a < 3; ++a) d2 += (r[a] - ctr[a]) * (r[a] - ctr[a]);
+            if (sqrt(d2) > rad) rad = sqrt(d2);
+        }
+        rad += 1e-9;
+    }
+    for (int i = 0; i < s->natom; ++i) {
+        const double reach = s->sp_rcut[s->species[i]] + rad;
+        double dx[3];
+        for (int a = 0; a < 3; ++a) dx[a] = ctr[a] - s->pos[3 * i + a];
+        double u[3];
+        for (int a = 0; a < 3; ++a) u[a] = dx[0] * c->inv[a] + dx[1] * c->inv[3 + a] + dx[2] * c->inv[6 + a];
+        int tlo[3], thi[3];
+        for (int a = 0; a < 3; ++a) {
+            tlo[a] = (int)floor(u[a] - reach / c->spacing[a]) - 1;
+            thi[a] = (int)ceil(u[a] + reach / c->spacing[a]) + 1;
+        }
+        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+            for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+                for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+                    double d2 = 0;
+                    for (int a = 0; a < 3; ++a) {
+                        double x = dx[a] - (t0 * c->cell[a] + t1 * c->cell[3 + a] + t2 * c->cell[6 + a]);
+                        d2 += x * x;
+                    }
+                    if (d2 < reach * reach) {
+                        if (nc == *cap) {
+                            *cap *= 2;
+                            *buf = (cand_t *)realloc(*buf, sizeof(cand_t) * (*cap));
+                        }
+                        (*buf)[nc].atom = i;
+                        (*buf)[nc].T[0] = t0; (*buf)[nc].T[1] = t1; (*buf)[nc].T[2] = t2;
+                        ++nc;
+                    }
+                }
+    }
+    return nc;
+}
+
+static int ctx_init(ctx_t *c, const oracle_system *s, int lazy)
 {
     memset(c, 0, sizeof(*c));
     if (s->natom < 0 || !s->cell || !s->grid) return ORACLE_EINVAL;
@@ -269,67 +337,55 @@ static int ctx_init(ctx_t *c, const oracle_system *s)
         c->M[a] = (c->N[a] + c->bs[a] - 1) / c->bs[a];
     }
     const long nbin = (long)c->M[0] * c->M[1] * c->M[2];
+    if (lazy) {
+        /* bins are built on request (ensure_bins), for callers that visit few points */
+        c->lazy = (cand_t **)calloc(nbin, sizeof(cand_t *));
+        c->lazy_n = (int *)calloc(nbin, sizeof(int));
+        return ORACLE_OK;
+    }
     c->bin_ptr = (long *)calloc(nbin + 1, sizeof(long));
     long capc = 1024, nc = 0;
     c->cand = (cand_t *)malloc(sizeof(cand_t) * capc);
     for (long b = 0; b < nbin; ++b) {
-        const int b0 = (int)(b / ((long)c->M[1] * c->M[2])), b1 = (int)((b / c->M[2]) % c->M[1]), b2 = (int)(b % c->M[2]);
-        const long lo[3] = {(long)b0 * c->bs[0], (long)b1 * c->bs[1], (long)b2 * c->bs[2]};
-        long hi[3];
-        for (int a = 0; a < 3; ++a) {
-            hi[a] = lo[a] + c->bs[a] - 1;
-            if (hi[a] > c->N[a] - 1) hi[a] = c->N[a] - 1;
-        }
-        /* bin centre and radius (max distance to its corner points) */
-        double ctr[3], rad = 0.0;
-        {
-            double fl[3] = {0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2])};
-            for (int a = 0; a < 3; ++a)
-                ctr[a] = fl[0] / c->N[0] * c->cell[a] + fl[1] / c->N[1] * c->cell[3 + a] + fl[2] / c->N[2] * c->cell[6 + a];
-            for (int q = 0; q < 8; ++q) {
-                long n[3] = {(q & 1) ? hi[0] : lo[0], (q & 2) ? hi[1] : lo[1], (q & 4) ? hi[2] : lo[2]};
-                double r[3];
-                grid_point(c, n, r);
-                double d2 = 0;
-                for (int a = 0; a < 3; ++a) d2 += (r[a] - ctr[a]) * (r[a] - ctr[a]);
-                if (sqrt(d2) > rad) rad = sqrt(d2);
-            }
-            rad += 1e-9;
-        }
-        for (int i = 0; i < s->natom; ++i) {
-            const double reach = s->sp_rcut[s->species[i]] + rad;
-            double dx[3];
-            for (int a = 0; a < 3; ++a) dx[a] = ctr[a] - s->pos[3 * i + a];
-            double u[3];
-            for (int a = 0; a < 3; ++a) u[a] = dx[0] * c->inv[a] + dx[1] * c->inv[3 + a] + dx[2] * c->inv[6 + a];
-            int tlo[3], thi[3];
-            for (int a = 0; a < 3; ++a) {
-                tlo[a] = (int)floor(u[a] - reach / c->spacing[a]) - 1;
-                thi[a] = (int)ceil(u[a] + reach / c->spacing[a]) + 1;
-            }
-            for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-                for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
-                    for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
-                        double d2 = 0;
-                        for (int a = 0; a < 3; ++a) {
-                            double x = dx[a] - (t0 * c->cell[a] + t1 * c->cell[3 + a] + t2 * c->cell[6 + a]);
-                            d2 += x * x;
-                        }
-                        if (d2 < reach * reach) {
-                            if (nc == capc) {
-                                capc *= 2;
-                                c->cand = (cand_t *)realloc(c->cand, sizeof(cand_t) * capc);
-                            }
-                            c->cand[nc].atom = i;
-                            c->cand[nc].T[0] = t0; c->cand[nc].T[1] = t1; c->cand[nc].T[2] = t2;
-                            ++nc;
-                        }
-                    }
-        }
+        nc = bin_candidates(c, s, b, &c->cand, &capc, nc);
         c->bin_ptr[b + 1] = nc;
         if (nc - c->bin_ptr[b] > c->maxcand) c->maxcand = (int)(nc - c->bin_ptr[b]);
     }
     return ORACLE_OK;
+}
+
+/* Bin of the home-cell grid point g. */
+static long bin_of(const ctx_t *c, long g)
+{
+    const long n[3] = {g / ((long)c->N[1] * c->N[2]), (g / c->N[2]) % c->N[1], g % c->N[2]};
+    return ((long)(n[0] / c->bs[0]) * c->M[1] + (n[1] / c->bs[1])) * c->M[2] + (n[2] / c->bs[2]);
+}
+
+/* Lazy form: build the candidate lists of the bins of points g[0..n). */
+static void ensure_bins(ctx_t *c, const oracle_system *s, long n, const long *g)
+{
+    const long nbin = (long)c->M[0] * c->M[1] * c->M[2];
+    unsigned char *want = (unsigned char *)calloc(nbin, 1);
+    for (long k = 0; k < n; ++k)
+        if (g[k] >= 0 && g[k] < c->ng) want[bin_of(c, g[k])] = 1;
+    long nw = 0;
+    for (long b = 0; b < nbin; ++b) nw += (want[b] && !c->lazy[b]);
+    long *list = (long *)malloc(sizeof(long) * (nw > 0 ? nw : 1));
+    nw = 0;
+    for (long b = 0; b < nbin; ++b)
+        if (want[b] && !c->lazy[b]) list[nw++] = b;
+    free(want);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long k = 0; k < nw; ++k) {
+        long cap = 64;
+        cand_t *buf = (cand_t *)malloc(sizeof(cand_t) * cap);
+        const long cnt = bin_candidates(c, s, list[k], &buf, &cap, 0);
+        c->lazy[list[k]] = buf;
+        c->lazy_n[list[k]] = (int)cnt;
+    }
+    for (long k = 0; k < nw; ++k)
+        if (c->lazy_n[list[k]] > c->maxcand) c->maxcand = c->lazy_n[list[k]];
+    free(list);
 }
 
 /* One entry of C(g): atom image and its orbital values/gradients. */
@@ -348,9 +404,11 @@ static int neighbours(const oracle_system *s, const ctx_t *c, long g, entry_t *e
     double r[3];
     grid_point(c, n, r);
     const long b = ((long)(n[0] / c->bs[0]) * c->M[1] + (n[1] / c->bs[1])) * c->M[2] + (n[2] / c->bs[2]);
+    const cand_t *cb = c->bin_ptr ? c->cand + c->bin_ptr[b] : c->lazy[b];
+    const long nb = c->bin_ptr ? c->bin_ptr[b + 1] - c->bin_ptr[b] : c->lazy_n[b];
     int cnt = 0;
-    for (long q = c->bin_ptr[b]; q < c->bin_ptr[b + 1]; ++q) {
-        const cand_t *cd = &c->cand[q];
+    for (long q = 0; q < nb; ++q) {
+        const cand_t *cd = &cb[q];
         const int i = cd->atom, sp = s->species[i];
         double x[3], d2 = 0;
         for (int a = 0; a < 3; ++a) {
@@ -401,7 +459,7 @@ static int thread_id(void)
 int oracle_vlocal(const oracle_system *s, const double *v, double *h, long g0, long g1)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 0);
     if (rc) { ctx_free(&c); return rc; }
     if ((rc = resolve_range(&c, &g0, &g1))) { ctx_free(&c); return rc; }
     long nnz = 0;
@@ -491,7 +549,7 @@ static int rho_at(const oracle_system *s, const ctx_t *c, const double *d, const
 int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, long g1)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 0);
     if (rc) { ctx_free(&c); return rc; }
     if ((rc = resolve_range(&c, &g0, &g1))) { ctx_free(&c); return rc; }
     int err = ORACLE_OK;
@@ -518,8 +576,9 @@ int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, lo
 int oracle_rho_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 1);
     if (rc) { ctx_free(&c); return rc; }
+    ensure_bins(&c, s, npts, gidx);
     int err = ORACLE_OK;
 #pragma omp parallel
     {
@@ -590,7 +649,7 @@ int oracle_force_stress(const oracle_system *s, const double *v, const double *d
                         double *force, double *zstrain, double *energy, long g0, long g1)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 0);
     if (rc) { ctx_free(&c); return rc; }
     if ((rc = resolve_range(&c, &g0, &g1))) { ctx_free(&c); return rc; }
     const int nt = nthreads_max();
@@ -655,7 +714,7 @@ static long floordiv(long a, long b) { long q = a / b; if ((a % b != 0) && ((a <
 int oracle_vlocal_blocks(const oracle_system *s, const double *v, int nsel, const int *blk, double *out)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 1);
     if (rc) { ctx_free(&c); return rc; }
     long *outoff = (long *)malloc(sizeof(long) * (nsel + 1));
     outoff[0] = 0;
@@ -708,7 +767,7 @@ int oracle_force_atoms(const oracle_system *s, const double *v, const double *d,
                        int nsel, const int *atoms, double *force, double *zstrain)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 1);
     if (rc) { ctx_free(&c); return rc; }
     int err = ORACLE_OK;
     for (int k = 0; k < nsel; ++k)
@@ -743,6 +802,7 @@ int oracle_force_atoms(const oracle_system *s, const double *v, const double *d,
         for (long g = 0; g < c.ng; ++g)
             if (seen[g]) pts[npt++] = g;
         free(seen);
+        ensure_bins(&c, s, npt, pts);
 #pragma omp parallel
         {
             const int t = thread_id();
@@ -809,9 +869,10 @@ int oracle_radial(const oracle_system *s, int sp, int chan, long n, const double
 int oracle_neighbours(const oracle_system *s, long g, int cap, int *atom, int *T, double *x)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 1);
     if (rc) { ctx_free(&c); return rc; }
     if (g < 0 || g >= c.ng) { ctx_free(&c); return ORACLE_EINVAL; }
+    ensure_bins(&c, s, 1, &g);
     entry_t *e = (entry_t *)malloc(sizeof(entry_t) * (c.maxcand + 1));
     const int n = neighbours(s, &c, g, e, 0);
     for (int k = 0; k < n && k < cap; ++k) {
@@ -826,7 +887,7 @@ int oracle_neighbours(const oracle_system *s, long g, int cap, int *atom, int *T
 int oracle_work(const oracle_system *s, long g0, long g1, double *w_out)
 {
     ctx_t c;
-    int rc = ctx_init(&c, s);
+    int rc = ctx_init(&c, s, 0);
     if (rc) { ctx_free(&c); return rc; }
     if ((rc = resolve_range(&c, &g0, &g1))) { ctx_free(&c); return rc; }
     double W = 0.0;
