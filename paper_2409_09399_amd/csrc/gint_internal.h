@@ -52,7 +52,9 @@ struct GPair {
 };
 
 struct GBig {
-    int x, y, z, w;              // origin point index of a bigcell (w unused)
+    int x, y, z;                 // origin point index of a bigcell (unwrapped)
+    int w;                       // flat index of the wrapped origin when no point of the bigcell
+                                 // wraps and the grid has < 2^31 points, else -1
 };
 
 struct GItem {

@@ -50,7 +50,10 @@ __device__ inline Pt bigcell_point(const GDev &P, const GBig &o, int pt) {
     r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
     r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
     r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
-    r.g = ((long long)wrap(n0, P.N[0]) * P.N[1] + wrap(n1, P.N[1])) * P.N[2] + wrap(n2, P.N[2]);
+    if (o.w >= 0)   // the bigcell does not wrap: w is the flat index of its origin
+        r.g = o.w + (((pt >> 4) * P.N[1] + ((pt >> 2) & 3)) * P.N[2] + (pt & 3));
+    else
+        r.g = ((long long)wrap(n0, P.N[0]) * P.N[1] + wrap(n1, P.N[1])) * P.N[2] + wrap(n2, P.N[2]);
     return r;
 }
 
@@ -490,7 +493,7 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
         // phase 3: wave w = A slot w, lane = point (reads only its own psi)
         {
             double v = 0.0;
-            if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+            if (aw >= 0 && (maskpt[lane] & (1u << w)) && (maskpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
                 const Pt r = bigcell_point(P, o, lane);
                 const GAtom at = ldc(P.atoms + aw);
                 const double x = r.x - at.x - pr.shiftA[0];
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
         __syncthreads();
         store_psi(c, phiB, maskt);
         double e = 0.0;
-        if (aw >= 0 && (maskpt[lane] & (1u << w))) {
+        if (aw >= 0 && (maskpt[lane] & (1u << w)) && (maskpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
             const Pt r = bigcell_point(P, o, lane);
             const GAtom at = ldc(P.atoms + aw);
             const double x = r.x - at.x - pr.shiftA[0];

@@ -72,7 +72,10 @@ __device__ inline P3 point_of(const GDev &P, const GBig &o, int pt) {
     r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
     r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
     r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
-    r.g = ((long long)wrapi(n0, P.N[0]) * P.N[1] + wrapi(n1, P.N[1])) * P.N[2] + wrapi(n2, P.N[2]);
+    if (o.w >= 0)   // the bigcell does not wrap: w is the flat index of its origin
+        r.g = o.w + (((pt >> 4) * P.N[1] + ((pt >> 2) & 3)) * P.N[2] + (pt & 3));
+    else
+        r.g = ((long long)wrapi(n0, P.N[0]) * P.N[1] + wrapi(n1, P.N[1])) * P.N[2] + wrapi(n2, P.N[2]);
     return r;
 }
 
@@ -448,13 +451,14 @@ constexpr int RSTR = 72;   // 16-bit elements per point row of the B tile (4 slo
 constexpr int FSTR = 65;   // floats per point row of the FP32 psi tile
 
 // Phase 1 of rho/force: B orbitals (scaled by sphi) as 16-bit hi/lo rows
-// [h][point][slot*16+mu]; A atoms only mark where they are active.
+// [h][point][slot*16+mu]; A atoms only mark where they are active.  Returns
+// the displacement of A atom a_w from this lane's point r, which the
+// per-point phase reuses.
 template <class T>
-__device__ inline void stage_b16(const GDev &P, CPair &pr, const GBig &o, float sphi, T (*tB)[GINT_BCPTS][RSTR],
+__device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sphi, T (*tB)[GINT_BCPTS][RSTR],
                                  unsigned *maskpt, unsigned *maskt) {
     const int lane = threadIdx.x & 63, w = wave_id();
     const int pt = lane;
-    const P3 r = point_of(P, o, pt);
     unsigned bits = 0;
     const int a = pr.a[w], b = pr.b[w];
     const Disp da = disp_of(P, r, a, pr.shiftA);
@@ -482,6 +486,7 @@ __device__ inline void stage_b16(const GDev &P, CPair &pr, const GBig &o, float 
         atomicOr(&maskpt[pt], bits);
         atomicOr(&maskt[pt >> 4], bits);
     }
+    return da;
 }
 
 // Phase 2: wave w computes psi[pt][mu] = sum_{b, nu} phi_B[pt][b nu]
@@ -569,7 +574,8 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_b16<T>(P, pr, o, sphi, tB, maskpt, maskt);
+        const P3 r = point_of(P, o, lane);
+        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, maskpt, maskt);
         __syncthreads();
         f4v c[4];
         psi_row16<T>(dh, dl, tB, maskt, c);
@@ -577,9 +583,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
         store_psi32(c, psi, maskt, unscale);
         {
             float v = 0.f;
-            if (aw >= 0 && (maskpt[lane] & (1u << w))) {
-                const P3 r = point_of(P, o, lane);
-                const Disp da = disp_of(P, r, aw, pr.shiftA);
+            if (da.in && (maskpt[lane] & 0xF0u)) {
                 const float *ps = psi + lane * FSTR + w * 16;
                 CSpecies &sp = cst(P.species)[cst(P.atoms)[aw].species];
                 eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float x) { v += x * ps[mu]; });
@@ -592,8 +596,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
             const unsigned m = maskpt[pt];
             if ((m & 0xFu) && (m & 0xF0u)) {
                 const double v = (double)part[0][pt] + (double)part[1][pt] + (double)part[2][pt] + (double)part[3][pt];
-                const P3 r = point_of(P, o, pt);
-                atomicAdd(rho + r.g, weight * v);
+                atomicAdd(rho + r.g, weight * v);   // threads below 64 are wave 0: r is point pt
             }
         }
         __syncthreads();
@@ -641,31 +644,28 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_b16<T>(P, pr, o, sphi, tB, maskpt, maskt);
+        const P3 r = point_of(P, o, lane);
+        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, maskpt, maskt);
         __syncthreads();
         f4v c[4];
         psi_row16<T>(dh, dl, tB, maskt, c);
         __syncthreads();
         store_psi32(c, psi, maskt, unscale);
         double ev = 0.0;
-        if (aw >= 0 && (maskpt[lane] & (1u << w))) {
-            const P3 r = point_of(P, o, lane);
-            const GAtom at = ldc(P.atoms + aw);
-            const double dx = r.x - at.x - pr.shiftA[0], dy = r.y - at.y - pr.shiftA[1],
-                         dz = r.z - at.z - pr.shiftA[2];
-            const float x = (float)dx, y = (float)dy, zz = (float)dz;
-            CSpecies &sp = cst(P.species)[at.species];
-            const double rr = sqrt(dx * dx + dy * dy + dz * dz);
+        if (da.in && (maskpt[lane] & 0xF0u)) {
+            CSpecies &sp = cst(P.species)[ldc(P.atoms + aw).species];
+            // |r - tau| from the knot: (k + t) dr, relative error ~1e-7
+            const float rr = ((float)da.kn.k + da.kn.t) * (float)sp.dr;
             float e, G[3];
-            dot_grad32(sp, P.tab32, x, y, zz, knot_of(sp, rr), rr > 0.0 ? (float)(1.0 / rr) : 0.f,
-                       psi + lane * FSTR + w * 16, e, G);
+            dot_grad32(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? 1.f / rr : 0.f, psi + lane * FSTR + w * 16,
+                       e, G);
             const double wv = P.w * V[r.g];
             const double c2 = 2.0 * wv;
             const double g0 = G[0], g1 = G[1], g2 = G[2];
             f[0] += c2 * g0;
             f[1] += c2 * g1;
             f[2] += c2 * g2;
-            const double gs[3] = {g0, g1, g2}, xs[3] = {dx, dy, dz};
+            const double gs[3] = {g0, g1, g2}, xs[3] = {da.x, da.y, da.z};
 #pragma unroll
             for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
                 const int pt = threadIdx.x;
                 const unsigned m = maskpt[pt];
                 if ((m & 0xFu) && (m & 0xF0u)) {
-                    const P3 r = point_of(P, o, pt);
+                    // threads below 64 are wave 0: r is point pt
                     atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
                 }
             }

@@ -37,6 +37,24 @@ struct Geometry {
     }
 };
 
+// Bigcell record: unwrapped origin, plus the flat index of the wrapped origin
+// when none of the bigcell's points wraps (then the kernels index V and rho
+// by adding a fixed per-point offset) and the grid has fewer than 2^31 points;
+// -1 sends the kernels to the general wrapped index.
+GBig make_bigcell(const int N[3], long long o0, long long o1, long long o2) {
+    const long long o[3] = {o0, o1, o2};
+    long long wr[3];
+    bool wraps = (long long)N[0] * N[1] * N[2] > 0x7fffffffLL;
+    for (int k = 0; k < 3; ++k) {
+        long long m = o[k] % N[k];
+        if (m < 0) m += N[k];
+        wr[k] = m;
+        if (m + GINT_BC > N[k]) wraps = true;
+    }
+    const long long flat = (wr[0] * N[1] + wr[1]) * N[2] + wr[2];
+    return GBig{(int)o0, (int)o1, (int)o2, wraps ? -1 : (int)flat};
+}
+
 bool invert3(const double *a, double *b, double *det) {
     double d = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
                a[2] * (a[3] * a[7] - a[4] * a[6]);
@@ -401,7 +419,7 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
                                             err.compare_exchange_strong(expected, GINT_EINVAL);
                                             continue;
                                         }
-                                        po.bcs.push_back({(int)(GINT_BC * b0), (int)(GINT_BC * b1), (int)(GINT_BC * b2), 0});
+                                        po.bcs.push_back(make_bigcell(G.N, GINT_BC * b0, GINT_BC * b1, GINT_BC * b2));
                                     }
                             if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
                         }
