@@ -280,9 +280,18 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
         }
         if (in) bits |= 1u << (4 + slot);
     }
-    if (bits) {
-        atomicOr(&maskpt[pt], bits);
-        if (maskt) atomicOr(&maskt[pt >> 4], bits);
+    if (bits) atomicOr(&maskpt[pt], bits);
+    if (maskt) {
+        // activity per 16-point tile, packed in one word (tile t: bit 8t + slot
+        // for A, 8t + 4 + slot for B) from the wave's ballots: one atomic per wave
+        const unsigned long long ba = __ballot((bits >> slot) & 1u), bb = __ballot(bits >> 4);
+        unsigned tw = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if ((ba >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + slot);
+            if ((bb >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + 4 + slot);
+        }
+        if (pt == 0 && tw) atomicOr(maskt, tw);
     }
 }
 
@@ -318,7 +327,7 @@ __device__ inline void psi_row(const double dw[4][4], const double *phiB, const 
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         c[t] = (d4){0.0, 0.0, 0.0, 0.0};
-        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        const unsigned gm = (__builtin_amdgcn_readfirstlane(*maskt) >> (8 * t)) & 0xFFu;
         if (!(gm & (1u << w))) continue;
         const double *base = phiB + (16 * t + (lane & 15)) * PSTR + (lane >> 4);
         double src[4][4];
@@ -341,7 +350,7 @@ __device__ inline void store_psi(const d4 c[4], double *phiB, const unsigned *ma
     const int lane = threadIdx.x & 63, w = wave_id();
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        const unsigned gm = (__builtin_amdgcn_readfirstlane(*maskt) >> (8 * t)) & 0xFFu;
         if (!(gm & (1u << w))) continue;
         double *dst = phiB + (16 * t + (lane >> 4)) * PSTR + w * GINT_ORB + (lane & 15);
 #pragma unroll
@@ -460,10 +469,15 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
-    __shared__ unsigned maskpt[GINT_BCPTS];
-    __shared__ unsigned maskt[4];
+    __shared__ unsigned maskpt[2][GINT_BCPTS];
+    __shared__ unsigned maskt[2];
     __shared__ double part[4][GINT_BCPTS];
     __shared__ int s_item;
+    // masks are double-buffered: each bigcell uses buffer cur, which is clear
+    // on entry, and clears the other one for the next bigcell
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    if (threadIdx.x < 2) maskt[threadIdx.x] = 0u;
+    int cur = 0;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -481,19 +495,21 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
-        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
+        unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
+        stage<2>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
-        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt, maskt);
-        __syncthreads();
+        // the other buffer was last read before the previous bigcell's final barrier
+        if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
+        if (threadIdx.x == GINT_BCPTS) maskt[cur ^ 1] = 0u;
+        cur ^= 1;
         d4 c[4];
-        psi_row(dw, phiB, maskt, c);
+        psi_row(dw, phiB, mt, c);
         __syncthreads();
-        store_psi(c, phiB, maskt);
+        store_psi(c, phiB, mt);
         // phase 3: wave w = A slot w, lane = point (reads only its own psi)
         {
             double v = 0.0;
-            if (aw >= 0 && (maskpt[lane] & (1u << w)) && (maskpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
+            if (aw >= 0 && (mpt[lane] & (1u << w)) && (mpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
                 const Pt r = bigcell_point(P, o, lane);
                 const GAtom at = ldc(P.atoms + aw);
                 const double x = r.x - at.x - pr.shiftA[0];
@@ -509,7 +525,7 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
         if (threadIdx.x < GINT_BCPTS) {
             const int pt = threadIdx.x;
             const double v = part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt];
-            if ((maskpt[pt] & 0xFu) && (maskpt[pt] & 0xF0u)) {
+            if ((mpt[pt] & 0xFu) && (mpt[pt] & 0xF0u)) {
                 const Pt r = bigcell_point(P, o, pt);
                 atomicAdd(rho + r.g, weight * v);
             }
@@ -531,11 +547,16 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
                                                   const double *__restrict__ D, double *__restrict__ F,
                                                   double *__restrict__ ZE0, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
-    __shared__ unsigned maskpt[GINT_BCPTS];
-    __shared__ unsigned maskt[4];
+    __shared__ unsigned maskpt[2][GINT_BCPTS];
+    __shared__ unsigned maskt[2];
     __shared__ double red[4][10];
     __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
+    // masks are double-buffered: each bigcell uses buffer cur, which is clear
+    // on entry, and clears the other one for the next bigcell
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    if (threadIdx.x < 2) maskt[threadIdx.x] = 0u;
+    int cur = 0;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -555,17 +576,19 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
-        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
+        unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
+        stage<2>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
-        stage<2>(P, pr, o, nullptr, nullptr, phiB, maskpt, maskt);
-        __syncthreads();
+        // the other buffer was last read before the previous bigcell's final barrier
+        if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
+        if (threadIdx.x == GINT_BCPTS) maskt[cur ^ 1] = 0u;
+        cur ^= 1;
         d4 c[4];
-        psi_row(dw, phiB, maskt, c);
+        psi_row(dw, phiB, mt, c);
         __syncthreads();
-        store_psi(c, phiB, maskt);
+        store_psi(c, phiB, mt);
         double e = 0.0;
-        if (aw >= 0 && (maskpt[lane] & (1u << w)) && (maskpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
+        if (aw >= 0 && (mpt[lane] & (1u << w)) && (mpt[lane] & 0xF0u)) {   // psi is 0 where no B atom reaches
             const Pt r = bigcell_point(P, o, lane);
             const GAtom at = ldc(P.atoms + aw);
             const double x = r.x - at.x - pr.shiftA[0];
@@ -591,7 +614,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
             __syncthreads();
             if (threadIdx.x < GINT_BCPTS) {
                 const int pt = threadIdx.x;
-                if ((maskpt[pt] & 0xFu) && (maskpt[pt] & 0xF0u)) {
+                if ((mpt[pt] & 0xFu) && (mpt[pt] & 0xF0u)) {
                     const Pt r = bigcell_point(P, o, pt);
                     atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
                 }

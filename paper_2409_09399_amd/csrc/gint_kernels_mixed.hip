@@ -231,6 +231,29 @@ struct Disp {
     bool in;
 };
 
+// Position (tau + lattice shift) and species of the atom in one slot of the
+// current work item, read once per item: the Vlocal bigcell loop then issues
+// no dependent atom -> species descriptor loads.  species < 0: empty slot.
+struct Slot {
+    double x, y, z;
+    int species;
+};
+
+__device__ inline Slot slot_of(const GDev &P, int atom, cdouble *shift) {
+    Slot s{0.0, 0.0, 0.0, -1};
+    if (atom >= 0) {
+        const GAtom at = ldc(P.atoms + atom);
+        s.x = at.x + shift[0];
+        s.y = at.y + shift[1];
+        s.z = at.z + shift[2];
+        s.species = at.species;
+    }
+    return s;
+}
+
+// The same from the atom index (descriptors loaded at the call; the rho and
+// force kernels use this form: holding two slots there costs more registers
+// than the loads).
 __device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, cdouble *shift) {
     Disp d{0.f, 0.f, 0.f, Knot{0, 0.f}, false};
     if (atom < 0) return d;
@@ -238,6 +261,21 @@ __device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, cdouble *sh
     const double dx = r.x - at.x - shift[0], dy = r.y - at.y - shift[1], dz = r.z - at.z - shift[2];
     const double r2 = dx * dx + dy * dy + dz * dz;
     CSpecies &sp = cst(P.species)[at.species];
+    const double rr = sqrt(r2);
+    d.in = r2 < sp.rcut2 && rr < sp.rcut;
+    d.x = (float)dx;
+    d.y = (float)dy;
+    d.z = (float)dz;
+    if (d.in) d.kn = knot_of(sp, rr);
+    return d;
+}
+
+__device__ inline Disp disp_at(const GDev &P, const P3 &r, const Slot &s) {
+    Disp d{0.f, 0.f, 0.f, Knot{0, 0.f}, false};
+    if (s.species < 0) return d;
+    const double dx = r.x - s.x, dy = r.y - s.y, dz = r.z - s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    CSpecies &sp = cst(P.species)[s.species];
     const double rr = sqrt(r2);
     d.in = r2 < sp.rcut2 && rr < sp.rcut;
     d.x = (float)dx;
@@ -289,6 +327,7 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
+    const Slot sa = slot_of(P, pr.a[w], pr.shiftA), sb = slot_of(P, pr.b[w], pr.shiftB);
     d4v acc[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) acc[i] = (d4v){0.0, 0.0, 0.0, 0.0};
@@ -302,10 +341,9 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
             const int pt = lane;
             const P3 r = point_of(P, o, pt);
             unsigned bits = 0;
-            const int a = pr.a[w], b = pr.b[w];
-            const Disp da = disp_of(P, r, a, pr.shiftA);
+            const Disp da = disp_at(P, r, sa);
             if (da.in) {
-                CSpecies &sp = cst(P.species)[cst(P.atoms)[a].species];
+                CSpecies &sp = cst(P.species)[sa.species];
                 eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
                     T hi, lo;
                     S::split(v, hi, lo);
@@ -320,9 +358,9 @@ __global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__r
                     tA[1][w][mu][pt] = (T)0.f;
                 }
             }
-            const Disp db = disp_of(P, r, b, pr.shiftB);
+            const Disp db = disp_at(P, r, sb);
             if (db.in) {
-                CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
+                CSpecies &sp = cst(P.species)[sb.species];
                 const float vg = (float)V[r.g] * sB;
                 eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                     T hi, lo;
@@ -482,10 +520,17 @@ __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sp
             h1[mu] = (T)0.f;
         }
     }
-    if (bits) {
-        atomicOr(&maskpt[pt], bits);
-        atomicOr(&maskt[pt >> 4], bits);
+    if (bits) atomicOr(&maskpt[pt], bits);
+    // activity per 16-point tile, packed in one word (tile t: bit 8t + slot for
+    // A, 8t + 4 + slot for B) from the wave's ballots: one atomic per wave
+    const unsigned long long ba = __ballot(da.in), bb = __ballot(db.in);
+    unsigned tw = 0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        if ((ba >> (16 * t)) & 0xFFFFull) tw |= 1u << (8 * t + w);
+        if ((bb >> (16 * t)) & 0xFFFFull) tw |= 1u << (8 * t + 4 + w);
     }
+    if (lane == 0 && tw) atomicOr(maskt, tw);
     return da;
 }
 
@@ -499,10 +544,11 @@ __device__ inline void psi_row16(const typename Split16<T>::vec dh[2], const typ
     typedef typename Split16<T>::vec vec;
     const int lane = threadIdx.x & 63, w = wave_id();
     const int off = 8 * (lane >> 4);
+    const unsigned all = __builtin_amdgcn_readfirstlane(*maskt);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         c[t] = (f4v){0.f, 0.f, 0.f, 0.f};
-        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        const unsigned gm = (all >> (8 * t)) & 0xFFu;
         if (!(gm & (1u << w))) continue;
         const int pt = 16 * t + (lane & 15);
 #pragma unroll
@@ -520,9 +566,10 @@ __device__ inline void psi_row16(const typename Split16<T>::vec dh[2], const typ
 // psi of slot w into its columns of the FP32 tile (after every wave has read tB).
 __device__ inline void store_psi32(const f4v c[4], float *psi, const unsigned *maskt, float unscale) {
     const int lane = threadIdx.x & 63, w = wave_id();
+    const unsigned all = __builtin_amdgcn_readfirstlane(*maskt);
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-        const unsigned gm = __builtin_amdgcn_readfirstlane(maskt[t]);
+        const unsigned gm = (all >> (8 * t)) & 0xFFu;
         if (!(gm & (1u << w))) continue;
         float *dst = psi + (16 * t + 4 * (lane >> 4)) * FSTR + w * 16 + (lane & 15);
 #pragma unroll
@@ -548,13 +595,18 @@ template <class T>
 __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
-    __shared__ unsigned maskpt[GINT_BCPTS];
-    __shared__ unsigned maskt[4];
+    __shared__ unsigned maskpt[2][GINT_BCPTS];
+    __shared__ unsigned maskt[2];
     __shared__ float part[4][GINT_BCPTS];
     __shared__ int s_item;
     T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
     float *psi = reinterpret_cast<float *>(buf);
     const float sphi = (float)P0.phi_scale;
+    // masks are double-buffered: each bigcell uses buffer cur, which is clear
+    // on entry, and clears the other one for the next bigcell
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    if (threadIdx.x < 2) maskt[threadIdx.x] = 0u;
+    int cur = 0;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -571,19 +623,21 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
     const double weight = pr.self ? 1.0 : 2.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
-        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
-        __syncthreads();
+        unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const P3 r = point_of(P, o, lane);
-        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, maskpt, maskt);
+        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, mpt, mt);
         __syncthreads();
+        // the other buffer was last read before the previous bigcell's final barrier
+        if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
+        if (threadIdx.x == GINT_BCPTS) maskt[cur ^ 1] = 0u;
+        cur ^= 1;
         f4v c[4];
-        psi_row16<T>(dh, dl, tB, maskt, c);
+        psi_row16<T>(dh, dl, tB, mt, c);
         __syncthreads();
-        store_psi32(c, psi, maskt, unscale);
+        store_psi32(c, psi, mt, unscale);
         {
             float v = 0.f;
-            if (da.in && (maskpt[lane] & 0xF0u)) {
+            if (da.in && (mpt[lane] & 0xF0u)) {
                 const float *ps = psi + lane * FSTR + w * 16;
                 CSpecies &sp = cst(P.species)[cst(P.atoms)[aw].species];
                 eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float x) { v += x * ps[mu]; });
@@ -593,7 +647,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
         __syncthreads();
         if (threadIdx.x < GINT_BCPTS) {
             const int pt = threadIdx.x;
-            const unsigned m = maskpt[pt];
+            const unsigned m = mpt[pt];
             if ((m & 0xFu) && (m & 0xF0u)) {
                 const double v = (double)part[0][pt] + (double)part[1][pt] + (double)part[2][pt] + (double)part[3][pt];
                 atomicAdd(rho + r.g, weight * v);   // threads below 64 are wave 0: r is point pt
@@ -615,14 +669,19 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
                                                      double *__restrict__ ZE0, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
-    __shared__ unsigned maskpt[GINT_BCPTS];
-    __shared__ unsigned maskt[4];
+    __shared__ unsigned maskpt[2][GINT_BCPTS];
+    __shared__ unsigned maskt[2];
     __shared__ double red[4][10];
     __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
     T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
     float *psi = reinterpret_cast<float *>(buf);
     const float sphi = (float)P0.phi_scale;
+    // masks are double-buffered: each bigcell uses buffer cur, which is clear
+    // on entry, and clears the other one for the next bigcell
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    if (threadIdx.x < 2) maskt[threadIdx.x] = 0u;
+    int cur = 0;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -641,18 +700,20 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
     double f[3] = {0, 0, 0}, z[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
-        if (threadIdx.x < 4) maskt[threadIdx.x] = 0u;
-        __syncthreads();
+        unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const P3 r = point_of(P, o, lane);
-        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, maskpt, maskt);
+        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, mpt, mt);
         __syncthreads();
+        // the other buffer was last read before the previous bigcell's final barrier
+        if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
+        if (threadIdx.x == GINT_BCPTS) maskt[cur ^ 1] = 0u;
+        cur ^= 1;
         f4v c[4];
-        psi_row16<T>(dh, dl, tB, maskt, c);
+        psi_row16<T>(dh, dl, tB, mt, c);
         __syncthreads();
-        store_psi32(c, psi, maskt, unscale);
+        store_psi32(c, psi, mt, unscale);
         double ev = 0.0;
-        if (da.in && (maskpt[lane] & 0xF0u)) {
+        if (da.in && (mpt[lane] & 0xF0u)) {
             CSpecies &sp = cst(P.species)[ldc(P.atoms + aw).species];
             // |r - tau| from the knot: (k + t) dr, relative error ~1e-7
             const float rr = ((float)da.kn.k + da.kn.t) * (float)sp.dr;
@@ -678,7 +739,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
             __syncthreads();
             if (threadIdx.x < GINT_BCPTS) {
                 const int pt = threadIdx.x;
-                const unsigned m = maskpt[pt];
+                const unsigned m = mpt[pt];
                 if ((m & 0xFu) && (m & 0xF0u)) {
                     // threads below 64 are wave 0: r is point pt
                     atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
