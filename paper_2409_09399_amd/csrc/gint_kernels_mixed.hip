@@ -138,11 +138,12 @@ __device__ inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R
         }
 }
 
-// phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v).
+// phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v),
+// from the Hermite weights h and the already requested first chunk of table
+// rows R0 (the caller can issue those loads early).
 template <class Emit>
-__device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
-                              Emit emit) {
-    const Herm32 h = hermite32(sp, tab, kn);
+__device__ inline void eval32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
+                                   float scale, Emit emit) {
     const float S1y = kC1f * y, S1z = kC1f * z, S1x = kC1f * x;
     const float S20 = kC2af * x * y, S21 = kC2af * y * z, S22 = kC2bf * (2.f * z * z - x * x - y * y),
                 S23 = kC2af * x * z, S24 = kC2cf * (x * x - y * y);
@@ -150,7 +151,10 @@ __device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, 
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH32) {
         Rows32 R;
-        load_rows32(h, nchan, c0, R);
+        if (c0 == 0)
+            R = R0;
+        else
+            load_rows32(h, nchan, c0, R);
 #pragma unroll
         for (int q = 0; q < RCH32; ++q) {
             if (c0 + q >= nchan) break;
@@ -177,17 +181,29 @@ __device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, 
     for (; slot < GINT_ORB; ++slot) emit(slot, 0.f);
 }
 
-// sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu, FP32.
-__device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float inv_r,
-                                  const float *psi, float &e, float G[3]) {
+template <class Emit>
+__device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
+                              Emit emit) {
     const Herm32 h = hermite32(sp, tab, kn);
+    Rows32 R0;
+    load_rows32(h, sp.nchan, 0, R0);
+    eval32_rows(sp, h, R0, x, y, z, scale, emit);
+}
+
+// sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu, FP32, from the Hermite
+// weights and the first chunk of table rows (as eval32_rows).
+__device__ inline void dot_grad32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
+                                       float inv_r, const float *psi, float &e, float G[3]) {
     e = 0.f;
     G[0] = G[1] = G[2] = 0.f;
     const int nchan = sp.nchan;
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH32) {
       Rows32 R;
-      load_rows32(h, nchan, c0, R);
+      if (c0 == 0)
+          R = R0;
+      else
+          load_rows32(h, nchan, c0, R);
 #pragma unroll
       for (int qq = 0; qq < RCH32; ++qq) {
         if (c0 + qq >= nchan) break;
@@ -222,6 +238,14 @@ __device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float
         G[2] += q * A * z + p * Bz;
       }
     }
+}
+
+__device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float inv_r,
+                                  const float *psi, float &e, float G[3]) {
+    const Herm32 h = hermite32(sp, tab, kn);
+    Rows32 R0;
+    load_rows32(h, sp.nchan, 0, R0);
+    dot_grad32_rows(sp, h, R0, x, y, z, inv_r, psi, e, G);
 }
 
 // Activity of one atom at one point; x is the FP32 displacement.
