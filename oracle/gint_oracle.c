@@ -525,8 +525,12 @@ static int dsym_block(const oracle_system *s, const ctx_t *c, const double *d, i
     return ORACLE_OK;
 }
 
-/* rho_g (Eq. 3) at one point from its neighbour list. */
-static int rho_at(const oracle_system *s, const ctx_t *c, const double *d, const entry_t *e, int n, double *out)
+/* rho_g (Eq. 3) at one point from its neighbour list.  With absval, the sum
+ * of the magnitudes of its terms, sum |phi_Imu| |D_IJR[mu,nu]| |phi_Jnu|: the
+ * scale that rounding errors of a reordered or lower-precision evaluation of
+ * rho_g are proportional to (rho_g itself can be much smaller by cancellation). */
+static int rho_at(const oracle_system *s, const ctx_t *c, const double *d, const entry_t *e, int n, int absval,
+                  double *out)
 {
     double rho = 0.0;
     for (int p = 0; p < n; ++p)
@@ -538,15 +542,18 @@ static int rho_at(const oracle_system *s, const ctx_t *c, const double *d, const
             const int nj = e[q].norb;
             for (int mu = 0; mu < e[p].norb; ++mu) {
                 double t = 0.0;
-                for (int nu = 0; nu < nj; ++nu) t += db[mu * nj + nu] * e[q].phi[nu];
-                rho += e[p].phi[mu] * t;
+                if (absval)
+                    for (int nu = 0; nu < nj; ++nu) t += fabs(db[mu * nj + nu]) * fabs(e[q].phi[nu]);
+                else
+                    for (int nu = 0; nu < nj; ++nu) t += db[mu * nj + nu] * e[q].phi[nu];
+                rho += (absval ? fabs(e[p].phi[mu]) : e[p].phi[mu]) * t;
             }
         }
     *out = rho;
     return ORACLE_OK;
 }
 
-int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, long g1)
+static int rho_range(const oracle_system *s, const double *d, double *rho, long g0, long g1, int absval)
 {
     ctx_t c;
     int rc = ctx_init(&c, s, 0);
@@ -560,7 +567,7 @@ int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, lo
         for (long g = g0; g < g1; ++g) {
             const int n = neighbours(s, &c, g, e, 0);
             double r;
-            if (rho_at(s, &c, d, e, n, &r)) {
+            if (rho_at(s, &c, d, e, n, absval, &r)) {
 #pragma omp atomic write
                 err = ORACLE_EPATTERN;
                 r = 0.0;
@@ -573,7 +580,17 @@ int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, lo
     return err;
 }
 
-int oracle_rho_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out)
+int oracle_rho(const oracle_system *s, const double *d, double *rho, long g0, long g1)
+{
+    return rho_range(s, d, rho, g0, g1, 0);
+}
+
+int oracle_rho_abs(const oracle_system *s, const double *d, double *out, long g0, long g1)
+{
+    return rho_range(s, d, out, g0, g1, 1);
+}
+
+static int rho_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out, int absval)
 {
     ctx_t c;
     int rc = ctx_init(&c, s, 1);
@@ -593,7 +610,7 @@ int oracle_rho_points(const oracle_system *s, const double *d, long npts, const 
             }
             const int n = neighbours(s, &c, g, e, 0);
             double r;
-            if (rho_at(s, &c, d, e, n, &r)) {
+            if (rho_at(s, &c, d, e, n, absval, &r)) {
 #pragma omp atomic write
                 err = ORACLE_EPATTERN;
                 r = 0.0;
@@ -604,6 +621,16 @@ int oracle_rho_points(const oracle_system *s, const double *d, long npts, const 
     }
     ctx_free(&c);
     return err;
+}
+
+int oracle_rho_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out)
+{
+    return rho_points(s, d, npts, gidx, out, 0);
+}
+
+int oracle_rho_abs_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out)
+{
+    return rho_points(s, d, npts, gidx, out, 1);
 }
 
 /* Force/strain contributions of one grid point (Eq. 4 and 5, readings in the

@@ -69,6 +69,11 @@ int oracle_force_stress(const oracle_system *s, const double *v, const double *d
 
 /* Sampled outputs, each computed on its own. */
 int oracle_rho_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out);
+/* Magnitude scale of rho's terms at each point, sum |phi_Imu| |D_IJR[mu,nu]| |phi_Jnu|
+ * over the same pairs as rho (>= |rho_g|): the bound of rounding-error
+ * tests of reordered or reduced-precision evaluations of rho. */
+int oracle_rho_abs(const oracle_system *s, const double *d, double *out, long g_begin, long g_end);
+int oracle_rho_abs_points(const oracle_system *s, const double *d, long npts, const long *gidx, double *out);
 int oracle_vlocal_blocks(const oracle_system *s, const double *v, int nsel, const int *blk, double *out);
 int oracle_force_atoms(const oracle_system *s, const double *v, const double *d,
                        int nsel, const int *atoms, double *force, double *zstrain);

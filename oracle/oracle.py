@@ -62,6 +62,8 @@ def _load():
         lib.oracle_rho.argtypes = [P, P, P, C.c_long, C.c_long]
         lib.oracle_force_stress.argtypes = [P, P, P, P, P, P, C.c_long, C.c_long]
         lib.oracle_rho_points.argtypes = [P, P, C.c_long, P, P]
+        lib.oracle_rho_abs.argtypes = [P, P, P, C.c_long, C.c_long]
+        lib.oracle_rho_abs_points.argtypes = [P, P, C.c_long, P, P]
         lib.oracle_vlocal_blocks.argtypes = [P, P, C.c_int, P, P]
         lib.oracle_force_atoms.argtypes = [P, P, P, C.c_int, P, P, P]
         lib.oracle_orbitals.argtypes = [P, C.c_int, C.c_long, P, P, P]
@@ -167,6 +169,24 @@ class Oracle:
         self._check(self.lib.oracle_force_stress(self._ps, _p(v), _p(d), _p(F), _p(Z), _p(E),
                                                  g_range[0], g_range[1]))
         return F, Z, float(E[0]), -Z / s.volume
+
+    def rho_abs(self, d=None, g_range=(0, -1)) -> np.ndarray:
+        """sum |phi_Imu| |D_IJR[mu,nu]| |phi_Jnu| per point over the pairs of
+        rho_g (Eq. 3): the scale that rounding errors of rho_g follow."""
+        s = self.system
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        out = np.zeros(s.ngrid)
+        self._check(self.lib.oracle_rho_abs(self._ps, _p(d), _p(out), g_range[0], g_range[1]))
+        return out
+
+    def rho_abs_points(self, gidx, d=None) -> np.ndarray:
+        """rho_abs at the given flat grid indices."""
+        s = self.system
+        d = np.ascontiguousarray(s.d if d is None else d, dtype=np.float64)
+        g = np.ascontiguousarray(gidx, dtype=np.int64)
+        out = np.zeros(g.shape[0])
+        self._check(self.lib.oracle_rho_abs_points(self._ps, _p(d), g.shape[0], _p(g), _p(out)))
+        return out
 
     def rho_points(self, gidx, d=None) -> np.ndarray:
         s = self.system

@@ -28,6 +28,13 @@ constexpr float kC2af = 1.0925484305920792f;
 constexpr float kC2bf = 0.31539156525252005f;
 constexpr float kC2cf = 0.54627421529603959f;
 
+// Pins v to its FP32 value in a register.  The hi/lo split needs hi + lo to
+// reproduce that value; without the pin the compiler may fuse the product
+// that produced v into the two conversions differently (hi from the product
+// rounded to FP32, lo from the exact product, each rounded once to 16 bits),
+// and where those roundings differ hi + lo misses v by a 16-bit ulp.
+__device__ inline void fp32_value(float &v) { asm("" : "+v"(v)); }
+
 template <class T>
 struct Split16;
 
@@ -35,6 +42,7 @@ template <>
 struct Split16<_Float16> {
     typedef h8v vec;
     __device__ static inline void split(float v, _Float16 &hi, _Float16 &lo) {
+        fp32_value(v);
         hi = (_Float16)v;
         lo = (_Float16)(v - (float)hi);
     }
@@ -47,6 +55,7 @@ template <>
 struct Split16<__bf16> {
     typedef b8v vec;
     __device__ static inline void split(float v, __bf16 &hi, __bf16 &lo) {
+        fp32_value(v);
         hi = (__bf16)v;
         lo = (__bf16)(v - (float)hi);
     }
@@ -330,7 +339,7 @@ __device__ inline float pow2_scale(double m) {
 // w owns the diagonal tiles (a_i, b_{(w-i)&3}); two k-steps of 32 points.
 // ---------------------------------------------------------------------------
 template <class T>
-__global__ __launch_bounds__(256, 2) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
+__global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
     typedef Split16<T> S;
     typedef typename S::vec vec;
     __shared__ __attribute__((aligned(16))) T tA[2][4][16][TSTR];

@@ -187,16 +187,18 @@ def test_batch64_mixed(G_mod, torch_dev, batch64, prec):
     (itself within 1e-11 of the oracle).  These dense crystals have
     |H| up to ~6 Ha and |F| up to ~17 Ha/Bohr, and a two-piece FP16 split
     carries about 22 bits per operand, so the bounds here are relative to the
-    largest entry (FP16x3: H 5e-7, F 5e-6, rho/sigma/E 1e-5; BF16x3 100x
-    looser); the absolute errors are printed.  The absolute targets
-    (H 1e-6 Ha, F 1e-5 Ha/Bohr) are asserted on the diamond and bilayer
-    cases in test_gpu_mixed.py."""
+    largest entry (FP16x3: H 5e-7, F 5e-6, rho and sigma 1e-5; BF16x3 100x
+    looser); the absolute errors are printed.  E = <D, H> = sum_g w V rho is
+    a sum whose terms cancel (random V and D), so its error is bounded
+    against the magnitude of those terms, <|D|, |H|>, at the same 1e-5.  The
+    absolute targets (H 1e-6 Ha, F 1e-5 Ha/Bohr) are asserted on the diamond
+    and bilayer cases in test_gpu_mixed.py."""
     torch, dev = torch_dev
     systems, ref = batch64
     got = run_batch(G_mod, torch, dev, systems, precision=prec)
     bounds = {1: dict(H=5e-7, F=5e-6, rel=1e-5), 2: dict(H=5e-5, F=5e-4, rel=1e-3)}[prec]
-    worst = dict(H_abs=0.0, F_abs=0.0, H_rel=0.0, F_rel=0.0, rho_rel=0.0, sigma_rel=0.0, E_rel=0.0)
-    for g, r in zip(got, ref):
+    worst = dict(H_abs=0.0, F_abs=0.0, H_rel=0.0, F_rel=0.0, rho_rel=0.0, sigma_rel=0.0, E_rel=0.0, E_scaled=0.0)
+    for s, g, r in zip(systems, got, ref):
         worst["H_abs"] = max(worst["H_abs"], float(np.abs(g["h"] - r["h"]).max()))
         worst["F_abs"] = max(worst["F_abs"], float(np.abs(g["F"] - r["F"]).max()))
         worst["H_rel"] = max(worst["H_rel"], rel(g["h"], r["h"]))
@@ -204,13 +206,12 @@ def test_batch64_mixed(G_mod, torch_dev, batch64, prec):
         worst["rho_rel"] = max(worst["rho_rel"], rel(g["rho"], r["rho"]))
         worst["sigma_rel"] = max(worst["sigma_rel"], rel(g["sig"], r["sig"]))
         worst["E_rel"] = max(worst["E_rel"], abs(g["E"] - r["E"]) / abs(r["E"]))
+        e_scale = float(np.dot(np.abs(s.d), np.abs(r["h"])))
+        worst["E_scaled"] = max(worst["E_scaled"], abs(g["E"] - r["E"]) / e_scale)
     hmax = max(float(np.abs(r["h"]).max()) for r in ref)
     fmax = max(float(np.abs(r["F"]).max()) for r in ref)
     print(f"[mixed] batch64 prec={prec} worst {worst} max|H| {hmax:.4g} max|F| {fmax:.4g}", flush=True)
     assert worst["H_rel"] <= bounds["H"]
     assert worst["F_rel"] <= bounds["F"]
-    for k in ("sigma_rel", "E_rel"):
+    for k in ("sigma_rel", "E_scaled", "rho_rel"):
         assert worst[k] <= bounds["rel"], k
-    # rho (relative to each system's largest |rho|) carries the cancellation
-    # between the many overlapping orbitals of these cells: bounded 50x looser
-    assert worst["rho_rel"] <= 50 * bounds["rel"]

@@ -67,7 +67,7 @@ def sampled(big, out, oracle_mod, rng):
              for b, r in zip(blks, refs)]
     atoms = rng.choice(s.natom, 3, replace=False)
     Fo, _ = o.force_atoms(atoms)
-    return r_or, r_gpu, refs, h_gpu, Fo, out["F"][atoms]
+    return r_or, r_gpu, refs, h_gpu, Fo, out["F"][atoms], g, o
 
 
 def test_tbg29_fp64(big, oracle_mod):
@@ -77,7 +77,7 @@ def test_tbg29_fp64(big, oracle_mod):
     assert abs(out["rho_sum"] - out["ne"]) <= TOL * abs(out["ne"])
     hmax = float(out["h"].abs().max())
     rmax = float(out["rho"].abs().max())
-    r_or, r_gpu, refs, h_gpu, Fo, Fg = sampled(big, out, oracle_mod, np.random.default_rng(3))
+    r_or, r_gpu, refs, h_gpu, Fo, Fg, _, _ = sampled(big, out, oracle_mod, np.random.default_rng(3))
     assert np.abs(r_gpu - r_or).max() <= TOL * rmax
     for r, g in zip(refs, h_gpu):
         assert np.abs(g - r).max() <= TOL * hmax
@@ -89,11 +89,15 @@ def test_tbg29_fp64(big, oracle_mod):
 
 def test_tbg29_fp16x3(big, oracle_mod):
     out = run(big, 1)
-    r_or, r_gpu, refs, h_gpu, Fo, Fg = sampled(big, out, oracle_mod, np.random.default_rng(4))
+    r_or, r_gpu, refs, h_gpu, Fo, Fg, g, o = sampled(big, out, oracle_mod, np.random.default_rng(4))
     herr = max(float(np.abs(g - r).max()) for r, g in zip(refs, h_gpu))
     ferr = float(np.abs(Fg - Fo).max())
     rerr = float(np.abs(r_gpu - r_or).max() / float(out["rho"].abs().max()))
-    print(f"[mixed] tbg29 H_abs {herr:.3g} F_abs {ferr:.3g} rho_rel {rerr:.3g}", flush=True)
+    # rho point by point against the magnitude scale of its terms (bound as in
+    # the other mixed-precision tests)
+    ra = o.rho_abs_points(g)
+    rpt = float(np.max(np.abs(r_gpu - r_or) / (ra + 1e-10 * ra.max())))
+    print(f"[mixed] tbg29 H_abs {herr:.3g} F_abs {ferr:.3g} rho_rel {rerr:.3g} rho_pt {rpt:.3g}", flush=True)
     assert herr <= 1e-6
     assert ferr <= 1e-5
-    assert rerr <= 1e-5
+    assert rpt <= 1e-5

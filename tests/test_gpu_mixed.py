@@ -3,10 +3,20 @@
 GINT_MIXED_FP16X3: FP32 orbitals, FP16 hi+lo split operands with three FP16
 MFMA products and FP32 accumulation per bigcell, FP64 across bigcells.
 Targets: |H - H_oracle| <= 1e-6 Ha and |F - F_oracle| <= 1e-5 Ha/Bohr; the
-rho and stress errors are stated (asserted against bounds derived from the
-FP32 evaluation, relative 1e-5 of the max-norm).
-GINT_MIXED_BF16X3 (about 16 significant bits per operand) is checked against
-bounds 100x looser.
+rho and stress errors are stated.  rho is bounded point by point against the
+magnitude scale of its terms, rho_abs(g) = sum |phi||D||phi| from the oracle:
+the split operands carry about 22 bits (2^-22 per product, three products),
+phi is evaluated and psi and the per-point dot products are accumulated in
+FP32 (at most 64 + 16 terms of 2^-24), which bounds |d rho(g)| by about
+5.5e-6 rho_abs(g).  The 16-bit operands are scaled so that the largest |phi|
+maps into [2^12, 2^13); values below FP16's normal range (2^-14) keep an
+absolute step of 2^-24, an absolute floor of 2^-37 max|phi| per value, which
+in the far tails of the orbitals dominates.  The test asserts
+|d rho(g)| <= 1e-5 (rho_abs(g) + 1e-10 max rho_abs).  rho itself can be much
+smaller than rho_abs by cancellation, so the max-norm relative error is only
+recorded.  Stress and energy: relative 1e-5.
+GINT_MIXED_BF16X3 (about 16 significant bits per operand: 3 x 2^-16 per
+product) is checked against bounds 10x (rho) and 100x (the rest) looser.
 """
 import json
 import os
@@ -43,18 +53,28 @@ def run(G, torch, dev, s, precision):
     return out
 
 
+def rho_scaled(got, ref, ref_abs):
+    """max_g |got - ref| / (rho_abs(g) + 1e-10 max rho_abs): the error
+    relative to the magnitude of rho's terms at each point, with the absolute
+    floor of the scaled 16-bit operands."""
+    err = np.abs(np.asarray(got) - np.asarray(ref))
+    ra = np.asarray(ref_abs)
+    return float(np.max(err / (ra + 1e-10 * ra.max() + 1e-300), initial=0.0))
+
+
 def errors(gpu, ref):
     e = {}
     e["H_abs"] = float(np.abs(gpu["h"] - ref["h"]).max())
     e["rho_rel"] = float(np.abs(gpu["rho"] - ref["rho"]).max() / np.abs(ref["rho"]).max())
+    e["rho_pt"] = rho_scaled(gpu["rho"], ref["rho"], ref["rho_abs"])
     e["F_abs"] = float(np.abs(gpu["F"] - ref["F"]).max())
     e["sigma_rel"] = float(np.abs(gpu["sig"] - ref["sig"]).max() / np.abs(ref["sig"]).max())
     e["E_rel"] = abs(gpu["E"] - ref["E"]) / abs(ref["E"])
     return e
 
 
-BOUNDS = {1: dict(H_abs=1e-6, F_abs=1e-5, rho_rel=1e-5, sigma_rel=1e-5, E_rel=1e-5),
-          2: dict(H_abs=1e-4, F_abs=1e-3, rho_rel=1e-3, sigma_rel=1e-3, E_rel=1e-3)}
+BOUNDS = {1: dict(H_abs=1e-6, F_abs=1e-5, rho_pt=1e-5, sigma_rel=1e-5, E_rel=1e-5),
+          2: dict(H_abs=1e-4, F_abs=1e-3, rho_pt=1e-4, sigma_rel=1e-3, E_rel=1e-3)}
 
 
 def record(name, prec, errs):
@@ -72,7 +92,7 @@ def test_mixed_diamond(torch_dev, oracle_mod, prec):
     s = I.diamond8(0)
     o = oracle_mod.Oracle(s)
     F, Z, E, sig = o.force_stress()
-    ref = dict(h=o.vlocal(), rho=o.rho(), F=F, sig=sig, E=E)
+    ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
     errs = errors(run(G, torch, dev, s, prec), ref)
     print("[mixed] diamond", prec, errs, flush=True)
     record("diamond8", prec, errs)
@@ -101,10 +121,11 @@ def test_mixed_tbg868_sampled(torch_dev, oracle_mod, prec):
     atoms = rng.choice(s.natom, 3, replace=False)
     Fo, _ = o.force_atoms(atoms)
     errs = {"H_abs": herr, "rho_rel": float(np.abs(gpu["rho"][g] - r_or).max() / np.abs(gpu["rho"]).max()),
+            "rho_pt": rho_scaled(gpu["rho"][g], r_or, o.rho_abs_points(g)),
             "F_abs": float(np.abs(gpu["F"][atoms] - Fo).max())}
     print("[mixed] tbg868", prec, errs, flush=True)
     record("tbg868_sampled", prec, errs)
-    for k in errs:
+    for k in ("H_abs", "rho_pt", "F_abs"):
         assert errs[k] <= BOUNDS[prec][k], (k, errs[k])
 
 
@@ -126,7 +147,7 @@ def test_mixed_three_species(torch_dev, oracle_mod, prec):
     s = I.assemble(cell, pos, np.array([0, 1, 2, 1, 0]), sps, grid, v, rng, name="mixed5")
     o = oracle_mod.Oracle(s)
     F, Z, E, sig = o.force_stress()
-    ref = dict(h=o.vlocal(), rho=o.rho(), F=F, sig=sig, E=E)
+    ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
     errs = errors(run(G, torch, dev, s, prec), ref)
     print("[mixed] three species", prec, errs, flush=True)
     record("mixed5", prec, errs)

@@ -206,6 +206,9 @@ def test_sampled_match_full(diamond):
     rng = np.random.default_rng(5)
     g = rng.choice(s.ngrid, 50, replace=False)
     assert np.abs(o.rho_points(g) - rho[g]).max() < 1e-13
+    ra = o.rho_abs()
+    assert np.abs(o.rho_abs_points(g) - ra[g]).max() < 1e-13 * ra.max()
+    assert np.all(ra >= np.abs(rho) * (1 - 1e-14))
     blks = rng.choice(len(s.blk_i), 12, replace=False)
     for b, blk in zip(blks, o.vlocal_blocks(blks)):
         ref = h[s.blk_off[b]:s.blk_off[b] + blk.size].reshape(blk.shape)
@@ -233,7 +236,8 @@ def _tiny(seed=2, grid=(6, 7, 9)):
 
 def test_brute_force_tiny(oracle_mod):
     """Triple loop over (point, atom, image box) with its own enumeration, and
-    the Gamma-point dense product Phi^T diag(wV) Phi, agree with the oracle."""
+    the Gamma-point dense product Phi^T diag(wV) Phi, agree with the oracle
+    (H, rho, and the magnitude scale sum |phi||D||phi| of rho's terms)."""
     s = _tiny()
     o = oracle_mod.Oracle(s)
     N = s.grid
@@ -244,6 +248,7 @@ def test_brute_force_tiny(oracle_mod):
     Ts = np.array(np.meshgrid(*[np.arange(-4, 5)] * 3, indexing="ij")).reshape(3, -1).T
     H = np.zeros(s.nnz)
     rho = np.zeros(s.ngrid)
+    rho_abs = np.zeros(s.ngrid)
     ostart = np.concatenate([[0], np.cumsum(norb)])
     Phi = np.zeros((s.ngrid, int(ostart[-1])))
     for g in range(s.ngrid):
@@ -265,9 +270,14 @@ def test_brute_force_tiny(oracle_mod):
                 H[s.blk_off[k]:s.blk_off[k] + blk.size] += w * s.v[g] * blk.ravel()
                 D = s.d[s.blk_off[k]:s.blk_off[k] + blk.size].reshape(blk.shape)
                 rho[g] += np.sum(D * blk)
+                rho_abs[g] += np.sum(np.abs(D) * np.abs(blk))
     Ho = o.vlocal()
     assert np.abs(Ho - H).max() < 1e-14 * max(1, np.abs(H).max()) * 10
     assert np.abs(o.rho() - rho).max() < 1e-13 * max(1, np.abs(rho).max())
+    # magnitude scale of rho's terms (the bound of the reduced-precision tests)
+    ra = o.rho_abs()
+    assert np.abs(ra - rho_abs).max() < 1e-13 * rho_abs.max()
+    assert np.all(ra >= np.abs(rho) * (1 - 1e-14))
     # dense Gamma-point check: sum over R of H(I,J,R) = Phi^T diag(wV) Phi
     HG = Phi.T @ (Phi * (w * s.v)[:, None])
     HGo = np.zeros_like(HG)
