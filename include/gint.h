@@ -178,6 +178,16 @@ int gint_force_stress(gint_plan *p, const double *v_loc, const double *d_vals,
 int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_vals, double *rho,
                           double *n_elec, double *force, double *stress, double *energy, void *stream);
 
+/* Symmetry check of D (a debug aid; the kernels assume D_JI(-R) = D_IJR^T
+ * and use D_sym, see the conventions above).  max_asym: device f64[n_sys],
+ * overwritten with max over the blocks of each system of
+ * |D_IJR[mu,nu] - D_JI(-R)[nu,mu]| (0 for an exactly symmetric D; NaN if a
+ * difference is NaN).  d_vals as for gint_rho.  The first call uploads the
+ * plan's block table (one allocation and a synchronous copy, so it is not
+ * for stream capture); later calls only enqueue two kernels on `stream`.
+ * The plan's device must be current (else GINT_EINVAL). */
+int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, void *stream);
+
 /* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
  * the unit of work of the throughput metric, counted exactly from the plan's
  * neighbour lists.  w_out: device f64[n_sys], overwritten. */

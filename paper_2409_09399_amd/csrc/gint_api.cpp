@@ -17,6 +17,7 @@ hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStrea
 hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, double *rho,
                              hipStream_t s);
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s);
+hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double *D, double *out, hipStream_t s);
 hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
                                hipStream_t s);
 hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
@@ -52,6 +53,8 @@ struct gint_plan {
     double *ZE = nullptr;      // [n_sys][10]: Z (9) and E
     double *part = nullptr;    // [n_sys][kParts]
     std::vector<GSys> sys_host;
+    std::vector<GBlk> blocks_host;   // pattern blocks, uploaded by the first symmetry check
+    DevBuf blocks;
     gint_sizes sizes{};
 };
 
@@ -82,7 +85,7 @@ int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
 
 void release(gint_plan *p) {
     DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->tab32, &p->pairs, &p->bigcells, &p->items_canon,
-                      &p->items_ordered, &p->sys, &p->ws};
+                      &p->items_ordered, &p->sys, &p->ws, &p->blocks};
     for (DevBuf *b : bufs)
         if (b->p) {
             (void)hipFree(b->p);
@@ -135,6 +138,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     }
     p->n_sys = n_sys;
     p->sys_host = hp.sys;
+    p->blocks_host = std::move(hp.blocks);
     // resident-block counts of the persistent kernels, queried once here so
     // that no launch (eager or captured) needs a device query
     gint_prime_grids_fp64();   // k_work serves every precision form
@@ -253,6 +257,29 @@ int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_val
 }
 
 // W = sum_g n_orb(g)^2, the unit of work of the throughput metric.
+int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, void *stream) {
+    if (!p || !d_vals || !max_asym) return GINT_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    int cur = 0;
+    hipError_t ge = hipGetDevice(&cur);
+    if (ge != hipSuccess) return hip_fail(ge);
+    if (cur != p->device) return GINT_EINVAL;
+    if (!p->blocks.p && !p->blocks_host.empty()) {
+        size_t total = 0;
+        const int rc = upload(p->blocks, p->blocks_host, total);
+        if (rc != GINT_OK) {
+            if (p->blocks.p) (void)hipFree(p->blocks.p);
+            p->blocks.p = nullptr;
+            return rc;
+        }
+    }
+    hipError_t e = gint_launch_fill(max_asym, p->n_sys, 0.0, s);
+    if (e == hipSuccess)
+        e = gint_launch_dsym_check((const GBlk *)p->blocks.p, (long long)p->blocks_host.size(), d_vals, max_asym, s);
+    if (e != hipSuccess) return hip_fail(e);
+    return GINT_OK;
+}
+
 int gint_work_units(gint_plan *p, double *w_out, void *stream) {
     if (!p || !w_out) return GINT_EINVAL;
     hipStream_t s = (hipStream_t)stream;

@@ -57,6 +57,15 @@ struct GBig {
                                  // wraps and the grid has < 2^31 points, else -1
 };
 
+// One (I, J, R) block of the sparse pattern with its transpose (J, I, -R),
+// for the symmetry check of D.
+struct GBlk {
+    long long off, off_t;        // element offsets of the block and of its transpose
+    int ni, nj;                  // orbitals of I and J (the block is ni x nj, row-major)
+    int sys;                     // system of a batched plan
+    int pad;
+};
+
 struct GItem {
     int pair;
     int bc_begin;

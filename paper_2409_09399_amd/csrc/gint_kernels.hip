@@ -709,6 +709,26 @@ __global__ void k_fill(double *__restrict__ p, long long n, double v) {
         p[i] = v;
 }
 
+// Largest |D_IJR[mu,nu] - D_JI(-R)[nu,mu]| per system: the symmetry the
+// kernels assume when they use D_sym (one block per thread; the maximum of
+// non-negative doubles is taken on their bit patterns, which order the same
+// way; a NaN difference reports as NaN).
+__global__ __launch_bounds__(256) void k_dsym_check(const GBlk *__restrict__ blk, long long nblk,
+                                                    const double *__restrict__ D,
+                                                    unsigned long long *__restrict__ out) {
+    for (long long b = blockIdx.x * (long long)blockDim.x + threadIdx.x; b < nblk;
+         b += (long long)gridDim.x * blockDim.x) {
+        const GBlk k = blk[b];
+        double m = 0.0;
+        for (int mu = 0; mu < k.ni; ++mu)
+            for (int nu = 0; nu < k.nj; ++nu) {
+                const double d = fabs(D[k.off + (long long)mu * k.nj + nu] - D[k.off_t + (long long)nu * k.ni + mu]);
+                m = (d > m || d != d) ? d : m;
+            }
+        if (m != 0.0) atomicMax(out + k.sys, (unsigned long long)__double_as_longlong(m));
+    }
+}
+
 // Per-system sums of w_s * x over each system's grid range (two passes,
 // deterministic): part[s * nparts + b] then out[s].
 __global__ __launch_bounds__(256) void k_seg_sum_partial(GDev P, const double *__restrict__ x, int nparts,
@@ -825,6 +845,14 @@ hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, do
 
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
     GINT_PERSISTENT_LAUNCH(k_work, P, s, W);
+}
+
+hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double *D, double *out, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
+    const long long nb = (nblk + 255) / 256;
+    hipLaunchKernelGGL(k_dsym_check, dim3((unsigned)(nb < 4096 ? nb : 4096)), dim3(256), 0, s, blk, nblk, D,
+                       reinterpret_cast<unsigned long long *>(out));
+    return hipGetLastError();
 }
 
 hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,

@@ -270,10 +270,12 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
     std::sort(spans.begin(), spans.end());
     for (size_t k = 1; k < spans.size(); ++k)
         if (spans[k].first < spans[k - 1].second) return fail(GINT_EINVAL, "overlapping blocks");
+    hp.blocks.resize(sys->nblk);
     for (int b = 0; b < sys->nblk; ++b) {
         const int *r = sys->blk_r + 3 * b;
-        if (bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]) < 0)
-            return fail(GINT_EPATTERN, "pattern is not transpose-closed");
+        const long long ot = bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]);
+        if (ot < 0) return fail(GINT_EPATTERN, "pattern is not transpose-closed");
+        hp.blocks[b] = GBlk{sys->blk_off[b], ot, norb[sys->blk_i[b]], norb[sys->blk_j[b]], 0, 0};
     }
     hp.nnz = nnz;
 
@@ -543,6 +545,12 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             hp.cluster_atoms = one.cluster_atoms;
         }
         hp.sys.push_back(S);
+        for (GBlk b : one.blocks) {
+            b.off += nnz_off;
+            b.off_t += nnz_off;
+            b.sys = i;
+            hp.blocks.push_back(b);
+        }
         for (GSpecies sp : one.species) {
             sp.tab_off += (int)tab_off;
             hp.species.push_back(sp);

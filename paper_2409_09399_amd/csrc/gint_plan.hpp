@@ -19,6 +19,7 @@ struct HostPlan {
     std::vector<GItem> items_canon;  // canonical pairs, longest first
     std::vector<GItem> items_ordered;// canonical + swapped, longest first
     std::vector<GSys> sys;           // one per system
+    std::vector<GBlk> blocks;        // pattern blocks with their transposes (symmetry check)
     int ncanon = 0;
     int ncluster = 0;
     int natom = 0;

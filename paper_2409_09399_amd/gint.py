@@ -67,6 +67,7 @@ class gint_tune_report(C.Structure):
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
+            "gint_check_symmetry",
             "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
             "gint_last_hip_error"]
@@ -108,6 +109,7 @@ def _load():
     lib.gint_force_stress.argtypes = [P, P, P, P, P, P, P]
     lib.gint_rho_force_stress.argtypes = [P] * 9
     lib.gint_work_units.argtypes = [P, P, P]
+    lib.gint_check_symmetry.argtypes = [P, P, P, P]
     lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
     lib.gint_plan_query_system.argtypes = [P, C.c_int, C.POINTER(gint_system_sizes)]
     lib.gint_plan_destroy.argtypes = [P]
@@ -271,6 +273,13 @@ def gint_force_stress(plan: Plan, v_loc, d_vals, force, stress, energy=None, str
 
 def gint_work_units(plan: Plan, w_out, stream=None):
     _check(_lib.gint_work_units(plan._p, _dev_ptr(w_out, plan.n_sys, "w_out"), _stream(stream)), "gint_work_units")
+
+
+def gint_check_symmetry(plan: Plan, d_vals, max_asym, stream=None):
+    """max |D_IJR[mu,nu] - D_JI(-R)[nu,mu]| per system into max_asym (device, n_sys)."""
+    _check(_lib.gint_check_symmetry(plan._p, _dev_ptr(d_vals, plan.nnz, "d_vals"),
+                                    _dev_ptr(max_asym, plan.n_sys, "max_asym"), _stream(stream)),
+           "gint_check_symmetry")
 
 
 class Graph:
