@@ -361,9 +361,44 @@ __device__ inline void store_psi(const d4 c[4], double *phiB, const unsigned *ma
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// H_IJR (Eq. 2)
+// H_IJR (Eq. 2), FP64.  Eight waves share the two 64-point tiles: wave w
+// evaluates one orbital set (A for w < 4, B scaled by w V_g for w >= 4, slot
+// w & 3) and, in the contraction, owns row atom a_i (i = w & 3) over the 32
+// points of half h = w >> 2, accumulating the four (a_i, b_j) tiles of those
+// points.  The two halves are added through LDS when the item ends and each
+// block is written once (plain stores when the item covers the whole pair,
+// atomics otherwise), with its transpose (b_j, a_i, -R).  With the LDS of the
+// tiles the limit, eight waves per workgroup double the waves per CU of a
+// four-wave layout.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
+constexpr int kVlocalThreads = 512;
+
+__device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
+                                    double *phiA, double *phiB, unsigned *maskpt) {
+    const int pt = threadIdx.x & 63, w = wave_id();
+    const int slot = w & 3;
+    const bool sideB = w >= 4;
+    const Pt r = bigcell_point(P, o, pt);
+    const int a = sideB ? pr.b[slot] : pr.a[slot];
+    cdouble *sh = sideB ? pr.shiftB : pr.shiftA;
+    double *dst = (sideB ? phiB : phiA) + pt * PSTR + slot * GINT_ORB;
+    bool in = false;
+    if (a >= 0) {
+        const GAtom at = ldc(P.atoms + a);
+        const double x = r.x - at.x - sh[0], y = r.y - at.y - sh[1], z = r.z - at.z - sh[2];
+        const double r2 = x * x + y * y + z * z;
+        CSpecies &sp = cst(P.species)[at.species];
+        in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+        if (in) eval_phi(sp, P.tab, x, y, z, r2, sideB ? P.w * V[r.g] : 1.0, dst);
+        else zero16(dst);
+    } else {
+        zero16(dst);
+    }
+    if (in) atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
+}
+
+__global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const double *__restrict__ V0,
+                                                              double *__restrict__ H) {
     __shared__ double phiA[GINT_BCPTS * PSTR];
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[GINT_BCPTS];
@@ -378,76 +413,66 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
-    // split-K: wave w owns k-steps 4w..4w+3 (points 16w..16w+15) of every
-    // bigcell and accumulates all 16 (a_i, b_j) tiles
-    d4 acc[4][4];
+    const int i = w & 3, half = w >> 2;
+    d4 acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
-        stage<1>(P, pr, o, V, phiA, phiB, maskpt);
+        stage_vlocal(P, pr, o, V, phiA, phiB, maskpt);
         __syncthreads();
-        // k-step t of this wave = points 16w + 4t .. +3; its activity mask is the
-        // OR over those 4 points, read into scalar registers once
-        const unsigned mp = maskpt[16 * w + (lane & 15)];
+        // k-step t of this wave = points 32 half + 4t .. +3; its activity mask is
+        // the OR over those 4 points, read into scalar registers once
+        const unsigned mp = maskpt[32 * half + (lane & 31)];
         unsigned mk = mp | __shfl_xor(mp, 1);
         mk |= __shfl_xor(mk, 2);
-        unsigned km[4];
+        unsigned km[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) km[t] = __builtin_amdgcn_readlane(mk, 4 * t);
-        // all operands of the wave's 4 k-steps in one batch of LDS reads
-        double a[4][4], b[4][4];
-        const int row0 = (16 * w + (lane >> 4)) * PSTR + (lane & 15);
+        for (int t = 0; t < 8; ++t) km[t] = __builtin_amdgcn_readlane(mk, 4 * t);
+        const int row0 = (32 * half + (lane >> 4)) * PSTR + (lane & 15);
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 8; ++t) {
+            if (!(km[t] & (1u << i))) continue;
+            const double a = phiA[row0 + 4 * t * PSTR + i * GINT_ORB];
+            double b[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[t][i] = phiA[row0 + 4 * t * PSTR + i * GINT_ORB];
-                b[t][i] = phiB[row0 + 4 * t * PSTR + i * GINT_ORB];
-            }
+            for (int j = 0; j < 4; ++j) b[j] = phiB[row0 + 4 * t * PSTR + j * GINT_ORB];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (!(km[t] & (1u << i))) continue;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (km[t] & (1u << (4 + j))) acc[i][j] = mfma64(a[t][i], b[t][j], acc[i][j]);
-            }
+            for (int j = 0; j < 4; ++j)
+                if (km[t] & (1u << (4 + j))) acc[j] = mfma64(a, b[j], acc[j]);
+        }
         __syncthreads();
     }
-    // reduce the 4 waves' partial tiles through LDS, one row atom at a time,
-    // then write each (a_i, b_j) block once (plain stores when the item covers
-    // the whole pair, atomics otherwise), plus its transpose (b_j, a_i, -R)
-    double *red = phiA;    // [wave][j][q][lane] = 4*4*4*64 doubles
-    const bool exclusive = it.pad != 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    // the second half's partial tiles go through LDS ([wave][j][q][lane], 4096
+    // doubles in phiA); the first half adds them and writes its row's blocks
+    double *red = phiA;
+    if (half == 1) {
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) red[((w * 4 + j) * 4 + q) * 64 + lane] = acc[i][j][q];
-        __syncthreads();
-        const int ai = pr.a[i];
-        if (ai >= 0) {
-            const int na = cst(P.atoms)[ai].norb;
+            for (int q = 0; q < 4; ++q) red[((i * 4 + j) * 4 + q) * 64 + lane] = acc[j][q];
+    }
+    __syncthreads();
+    const int ai = pr.a[i];
+    if (half == 0 && ai >= 0) {
+        const bool exclusive = it.pad != 0;
+        const int na = cst(P.atoms)[ai].norb;
+        const int nu = lane & 15;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int e = threadIdx.x + 256 * k;    // (j, q, l)
-                const int j = e >> 8, q = (e >> 6) & 3, l = e & 63;
-                const int bj = pr.b[j];
-                if (bj < 0) continue;
-                const int nb = cst(P.atoms)[bj].norb;
-                const int mu = 4 * q + (l >> 4), nu = l & 15;
+        for (int j = 0; j < 4; ++j) {
+            const int bj = pr.b[j];
+            if (bj < 0) continue;
+            const int nb = cst(P.atoms)[bj].norb;
+            const long long off = pr.hoff[i * 4 + j], offt = pr.hoff_t[i * 4 + j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // 16x16x4 FP64 result layout: lane l, register q holds row 4q + (l >> 4), column l & 15
+                const int mu = 4 * q + (lane >> 4);
                 if (mu >= na || nu >= nb) continue;
-                const double v = red[((0 * 4 + j) * 4 + q) * 64 + l] + red[((1 * 4 + j) * 4 + q) * 64 + l] +
-                                 red[((2 * 4 + j) * 4 + q) * 64 + l] + red[((3 * 4 + j) * 4 + q) * 64 + l];
-                const long long off = pr.hoff[i * 4 + j], offt = pr.hoff_t[i * 4 + j];
+                const double v = acc[j][q] + red[((i * 4 + j) * 4 + q) * 64 + lane];
                 if (exclusive) {
                     if (off >= 0) H[off + (long long)mu * nb + nu] = v;
                     if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
@@ -457,7 +482,6 @@ __global__ __launch_bounds__(256, 2) void k_vlocal(GDev P0, const double *__rest
                 }
             }
         }
-        __syncthreads();
     }
     }
 }
@@ -787,7 +811,7 @@ std::mutex g_grid_mu;
 std::vector<std::pair<GridKey, int>> g_grid_cache;
 }  // namespace
 
-int gint_resident_blocks(const void *kernel) {
+int gint_resident_blocks(const void *kernel, int threads) {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = -1;
     {
@@ -798,15 +822,16 @@ int gint_resident_blocks(const void *kernel) {
     int cus = 0, per_cu = 0;
     if (dev < 0 || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu <= 0) per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 1;
     const int slots = cus * per_cu;
     std::lock_guard<std::mutex> lk(g_grid_mu);
     g_grid_cache.push_back({GridKey{kernel, dev}, slots});
     return slots;
 }
 
-int gint_persistent_grid(const void *kernel, int nitems) {
-    const int slots = gint_resident_blocks(kernel);
+int gint_persistent_grid(const void *kernel, int nitems, int threads) {
+    const int slots = gint_resident_blocks(kernel, threads);
     return nitems < slots ? nitems : slots;
 }
 
@@ -819,18 +844,19 @@ hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s) {
 }
 
 // Reset the work counter, then one persistent launch over all items.
-#define GINT_PERSISTENT_LAUNCH(KERNEL, P, s, ...)                                                    \
+#define GINT_PERSISTENT_LAUNCH_T(KERNEL, THREADS, P, s, ...)                                         \
     do {                                                                                            \
         if ((P).nitems <= 0) return hipSuccess;                                                     \
         hipError_t e_ = gint_launch_fill((double *)(P).counter, 1, 0.0, s);                         \
         if (e_ != hipSuccess) return e_;                                                            \
-        const int grid_ = gint_persistent_grid((const void *)KERNEL, (P).nitems);                   \
-        hipLaunchKernelGGL(KERNEL, dim3(grid_), dim3(256), 0, s, P, __VA_ARGS__);                    \
+        const int grid_ = gint_persistent_grid((const void *)KERNEL, (P).nitems, THREADS);          \
+        hipLaunchKernelGGL(KERNEL, dim3(grid_), dim3(THREADS), 0, s, P, __VA_ARGS__);               \
         return hipGetLastError();                                                                   \
     } while (0)
+#define GINT_PERSISTENT_LAUNCH(KERNEL, P, s, ...) GINT_PERSISTENT_LAUNCH_T(KERNEL, 256, P, s, __VA_ARGS__)
 
 hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s) {
-    GINT_PERSISTENT_LAUNCH(k_vlocal, P, s, V, H);
+    GINT_PERSISTENT_LAUNCH_T(k_vlocal, kVlocalThreads, P, s, V, H);
 }
 
 hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s) {
@@ -873,9 +899,9 @@ hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *st
 
 // Fill the resident-block cache for every kernel of a precision form.
 void gint_prime_grids_fp64() {
-    gint_resident_blocks((const void *)k_vlocal);
-    gint_resident_blocks((const void *)k_rho);
-    gint_resident_blocks((const void *)k_force<false>);
-    gint_resident_blocks((const void *)k_force<true>);
-    gint_resident_blocks((const void *)k_work);
+    gint_resident_blocks((const void *)k_vlocal, kVlocalThreads);
+    gint_resident_blocks((const void *)k_rho, 256);
+    gint_resident_blocks((const void *)k_force<false>, 256);
+    gint_resident_blocks((const void *)k_force<true>, 256);
+    gint_resident_blocks((const void *)k_work, 256);
 }

@@ -809,7 +809,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-int gint_persistent_grid(const void *kernel, int nitems);
+int gint_persistent_grid(const void *kernel, int nitems, int threads);
 hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 
 template <class K, class... Args>
@@ -817,7 +817,7 @@ static hipError_t launch_persistent(K kernel, const GDev &P, hipStream_t s, Args
     if (P.nitems <= 0) return hipSuccess;
     hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
     if (e != hipSuccess) return e;
-    const int grid = gint_persistent_grid((const void *)kernel, P.nitems);
+    const int grid = gint_persistent_grid((const void *)kernel, P.nitems, 256);
     hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, s, P, args...);
     return hipGetLastError();
 }
@@ -861,18 +861,18 @@ hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const 
                      : launch_persistent(k_force_mx<_Float16, false>, P, s, V, D, F, ZE, (double *)nullptr);
 }
 
-int gint_resident_blocks(const void *kernel);
+int gint_resident_blocks(const void *kernel, int threads);
 
 void gint_prime_grids_mx(int prec) {
     if (prec == 2) {
-        gint_resident_blocks((const void *)k_vlocal_mx<__bf16>);
-        gint_resident_blocks((const void *)k_rho_mx<__bf16>);
-        gint_resident_blocks((const void *)k_force_mx<__bf16, false>);
-        gint_resident_blocks((const void *)k_force_mx<__bf16, true>);
+        gint_resident_blocks((const void *)k_vlocal_mx<__bf16>, 256);
+        gint_resident_blocks((const void *)k_rho_mx<__bf16>, 256);
+        gint_resident_blocks((const void *)k_force_mx<__bf16, false>, 256);
+        gint_resident_blocks((const void *)k_force_mx<__bf16, true>, 256);
     } else {
-        gint_resident_blocks((const void *)k_vlocal_mx<_Float16>);
-        gint_resident_blocks((const void *)k_rho_mx<_Float16>);
-        gint_resident_blocks((const void *)k_force_mx<_Float16, false>);
-        gint_resident_blocks((const void *)k_force_mx<_Float16, true>);
+        gint_resident_blocks((const void *)k_vlocal_mx<_Float16>, 256);
+        gint_resident_blocks((const void *)k_rho_mx<_Float16>, 256);
+        gint_resident_blocks((const void *)k_force_mx<_Float16, false>, 256);
+        gint_resident_blocks((const void *)k_force_mx<_Float16, true>, 256);
     }
 }
