@@ -379,6 +379,8 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
     const int slot = w & 3;
     const bool sideB = w >= 4;
     const Pt r = bigcell_point(P, o, pt);
+    // B waves request V first, so its latency overlaps the displacement work
+    const double vpt = sideB ? V[r.g] : 0.0;
     const int a = sideB ? pr.b[slot] : pr.a[slot];
     cdouble *sh = sideB ? pr.shiftB : pr.shiftA;
     double *dst = (sideB ? phiB : phiA) + pt * PSTR + slot * GINT_ORB;
@@ -389,7 +391,7 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
         const double r2 = x * x + y * y + z * z;
         CSpecies &sp = cst(P.species)[at.species];
         in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
-        if (in) eval_phi(sp, P.tab, x, y, z, r2, sideB ? P.w * V[r.g] : 1.0, dst);
+        if (in) eval_phi(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
         else zero16(dst);
     } else {
         zero16(dst);
@@ -601,6 +603,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
+        const double vpt = V[bigcell_point(P, o, lane).g];   // requested early: its latency overlaps the stage
         stage<2>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
@@ -621,7 +624,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
             const double r2 = x * x + y * y + zz * zz;
             double G[3];
             dot_phi<true>(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
-            const double wv = P.w * V[r.g];
+            const double wv = P.w * vpt;
             const double c2 = 2.0 * wv;
             f[0] += c2 * G[0];
             f[1] += c2 * G[1];

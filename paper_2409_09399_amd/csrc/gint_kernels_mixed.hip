@@ -373,6 +373,9 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             // phase 1: A atom (slot w) and B atom (slot w) at point lane
             const int pt = lane;
             const P3 r = point_of(P, o, pt);
+            // V at this point, requested before A is evaluated so its latency
+            // overlaps that work (every point of a bigcell is a valid index)
+            const double vpt = V[r.g];
             unsigned bits = 0;
             const Disp da = disp_at(P, r, sa);
             if (da.in) {
@@ -394,7 +397,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             const Disp db = disp_at(P, r, sb);
             if (db.in) {
                 CSpecies &sp = cst(P.species)[sb.species];
-                const float vg = (float)V[r.g] * sB;
+                const float vg = (float)vpt * sB;
                 eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                     T hi, lo;
                     S::split(v, hi, lo);
@@ -735,6 +738,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const P3 r = point_of(P, o, lane);
+        const double vpt = V[r.g];   // requested early: its latency overlaps the stage
         const Disp da = stage_b16<T>(P, pr, r, sphi, tB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
@@ -753,7 +757,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
             float e, G[3];
             dot_grad32(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? 1.f / rr : 0.f, psi + lane * FSTR + w * 16,
                        e, G);
-            const double wv = P.w * V[r.g];
+            const double wv = P.w * vpt;
             const double c2 = 2.0 * wv;
             const double g0 = G[0], g1 = G[1], g2 = G[2];
             f[0] += c2 * g0;
