@@ -709,9 +709,12 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
     __shared__ unsigned maskt[2];
     __shared__ double red[4][10];
     __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
+    // psi has LDS of its own here (each wave writes and reads only its own
+    // columns), so no barrier separates the psi products from the stores; at
+    // four workgroups per CU (the register limit) the extra LDS costs no occupancy
+    __shared__ float psi[GINT_BCPTS * FSTR];
     __shared__ int s_item;
     T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
-    float *psi = reinterpret_cast<float *>(buf);
     const float sphi = (float)P0.phi_scale;
     // masks are double-buffered: each bigcell uses buffer cur, which is clear
     // on entry, and clears the other one for the next bigcell
@@ -747,7 +750,6 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
         cur ^= 1;
         f4v c[4];
         psi_row16<T>(dh, dl, tB, mt, c);
-        __syncthreads();
         store_psi32(c, psi, mt, unscale);
         double ev = 0.0;
         if (da.in && (mpt[lane] & 0xF0u)) {
