@@ -171,6 +171,9 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         k = k < -60 ? -60 : (k > 60 ? 60 : k);
         d.phi_scale = std::ldexp(1.0, k);
     }
+    d.shape_all = hp.species.empty() ? GINT_SHAPE_ANY : hp.species[0].shape;
+    for (const GSpecies &g : hp.species)
+        if (g.shape != d.shape_all) d.shape_all = GINT_SHAPE_ANY;
     d.vmax = (const double *)p->ws.p + 1;
     p->canon = d;
     p->canon.items = (const GItem *)p->items_canon.p;

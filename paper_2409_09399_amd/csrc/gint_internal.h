@@ -29,8 +29,14 @@ struct GSpecies {
     int nchan;
     int norb;
     int tab_off;                 // offset (doubles) of [knot][chan][f, f'] in the table array
+    int shape;                   // channel layout the kernels have a fixed path for (GINT_SHAPE_*)
     int chan_l[GINT_MAXCHAN];
 };
+
+// Channel layouts (l of each channel, in order) with fixed evaluation paths:
+// the double-zeta-polarised sets of second-row elements (2s2p1d) and of
+// hydrogen (2s1p).  Any other layout takes the general path.
+enum { GINT_SHAPE_ANY = 0, GINT_SHAPE_2S2P1D = 1, GINT_SHAPE_2S1P = 2 };
 
 struct GAtom {
     double x, y, z;
@@ -110,4 +116,6 @@ struct GDev {
     // max_g |V_g| of the current call (reduced on the device)
     double phi_scale;
     const double *vmax;
+    int shape_all;               // GINT_SHAPE_* shared by every species of the plan, else GINT_SHAPE_ANY
+    int pad_;
 };

@@ -15,6 +15,8 @@
 
 #include "gint_device.h"
 
+#include <type_traits>
+
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
@@ -110,7 +112,7 @@ __device__ inline Knot knot_of(CSpecies &sp, double r) {
     return Knot{k, (float)(t - (double)k)};
 }
 
-__device__ inline Herm32 hermite32(CSpecies &sp, const float *tab, Knot kn) {
+__device__ __attribute__((always_inline)) inline Herm32 hermite32(CSpecies &sp, const float *tab, Knot kn) {
     const int k = kn.k;
     const float t = kn.t;
     const float t2 = t * t, t3 = t2 * t, dr = (float)sp.dr, idr = (float)sp.inv_dr;
@@ -138,7 +140,7 @@ struct Rows32 {
     flt2 a[RCH32], b[RCH32];
 };
 
-__device__ inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R) {
+__device__ __attribute__((always_inline)) inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R) {
 #pragma unroll
     for (int q = 0; q < RCH32; ++q)
         if (c0 + q < nchan) {
@@ -147,16 +149,60 @@ __device__ inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R
         }
 }
 
+// Channel layout of a species: with SHAPE a fixed layout (GINT_SHAPE_*) the
+// channel count and each channel's l are compile-time constants, so the
+// evaluation below unrolls completely (orbital slots and LDS offsets become
+// constants and no per-channel branches remain); SHAPE 0 reads them from the
+// species record.
+template <int SHAPE>
+struct ChanShape {
+    __device__ static int nchan(CSpecies &sp) { return sp.nchan; }
+    __device__ static int l(CSpecies &sp, int c) { return sp.chan_l[c]; }
+};
+template <>
+struct ChanShape<GINT_SHAPE_2S2P1D> {
+    __device__ static constexpr int nchan(CSpecies &) { return 5; }
+    __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : (c < 4 ? 1 : 2); }
+};
+template <>
+struct ChanShape<GINT_SHAPE_2S1P> {
+    __device__ static constexpr int nchan(CSpecies &) { return 3; }
+    __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : 1; }
+};
+
+// f(std::integral_constant<int, SHAPE>) for the species' layout (a
+// wave-uniform branch on the species record).
+template <class F>
+__device__ __attribute__((always_inline)) inline void by_shape(CSpecies &sp, F &&f) {
+    const int shape = sp.shape;
+    if (shape == GINT_SHAPE_2S2P1D)
+        f(std::integral_constant<int, GINT_SHAPE_2S2P1D>{});
+    else if (shape == GINT_SHAPE_2S1P)
+        f(std::integral_constant<int, GINT_SHAPE_2S1P>{});
+    else
+        f(std::integral_constant<int, GINT_SHAPE_ANY>{});
+}
+
+// As by_shape, for a kernel compiled for plans whose species all have layout
+// KS (then no branch remains), or for any mix (KS = GINT_SHAPE_ANY).
+template <int KS, class F>
+__device__ __attribute__((always_inline)) inline void with_shape(CSpecies &sp, F &&f) {
+    if constexpr (KS != GINT_SHAPE_ANY)
+        f(std::integral_constant<int, KS>{});
+    else
+        by_shape(sp, f);
+}
+
 // phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v),
 // from the Hermite weights h and the already requested first chunk of table
 // rows R0 (the caller can issue those loads early).
-template <class Emit>
-__device__ inline void eval32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
+template <int SHAPE, class Emit>
+__device__ __attribute__((always_inline)) inline void eval32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
                                    float scale, Emit emit) {
     const float S1y = kC1f * y, S1z = kC1f * z, S1x = kC1f * x;
     const float S20 = kC2af * x * y, S21 = kC2af * y * z, S22 = kC2bf * (2.f * z * z - x * x - y * y),
                 S23 = kC2af * x * z, S24 = kC2cf * (x * x - y * y);
-    const int nchan = sp.nchan;
+    const int nchan = ChanShape<SHAPE>::nchan(sp);
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH32) {
         Rows32 R;
@@ -168,7 +214,7 @@ __device__ inline void eval32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &
         for (int q = 0; q < RCH32; ++q) {
             if (c0 + q >= nchan) break;
             const float p = (h.h00 * R.a[q].x + h.h10 * R.a[q].y + h.h01 * R.b[q].x + h.h11 * R.b[q].y) * scale;
-            const int l = sp.chan_l[c0 + q];
+            const int l = ChanShape<SHAPE>::l(sp, c0 + q);
             if (l == 0) {
                 emit(slot, p * kC0f);
                 slot += 1;
@@ -190,22 +236,23 @@ __device__ inline void eval32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &
     for (; slot < GINT_ORB; ++slot) emit(slot, 0.f);
 }
 
-template <class Emit>
-__device__ inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
+template <int SHAPE, class Emit>
+__device__ __attribute__((always_inline)) inline void eval32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float scale,
                               Emit emit) {
     const Herm32 h = hermite32(sp, tab, kn);
     Rows32 R0;
-    load_rows32(h, sp.nchan, 0, R0);
-    eval32_rows(sp, h, R0, x, y, z, scale, emit);
+    load_rows32(h, ChanShape<SHAPE>::nchan(sp), 0, R0);
+    eval32_rows<SHAPE>(sp, h, R0, x, y, z, scale, emit);
 }
 
 // sum_mu psi_mu phi_mu and sum_mu psi_mu grad phi_mu, FP32, from the Hermite
 // weights and the first chunk of table rows (as eval32_rows).
-__device__ inline void dot_grad32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
+template <int SHAPE>
+__device__ __attribute__((always_inline)) inline void dot_grad32_rows(CSpecies &sp, const Herm32 &h, const Rows32 &R0, float x, float y, float z,
                                        float inv_r, const float *psi, float &e, float G[3]) {
     e = 0.f;
     G[0] = G[1] = G[2] = 0.f;
-    const int nchan = sp.nchan;
+    const int nchan = ChanShape<SHAPE>::nchan(sp);
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH32) {
       Rows32 R;
@@ -219,7 +266,7 @@ __device__ inline void dot_grad32_rows(CSpecies &sp, const Herm32 &h, const Rows
         const float f0 = R.a[qq].x, fp0 = R.a[qq].y, f1 = R.b[qq].x, fp1 = R.b[qq].y;
         const float p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
         const float q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
-        const int l = sp.chan_l[c0 + qq];
+        const int l = ChanShape<SHAPE>::l(sp, c0 + qq);
         float A, Bx, By, Bz;
         if (l == 0) {
             A = psi[slot] * kC0f;
@@ -249,12 +296,13 @@ __device__ inline void dot_grad32_rows(CSpecies &sp, const Herm32 &h, const Rows
     }
 }
 
-__device__ inline void dot_grad32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float inv_r,
+template <int SHAPE>
+__device__ __attribute__((always_inline)) inline void dot_grad32(CSpecies &sp, const float *tab, float x, float y, float z, Knot kn, float inv_r,
                                   const float *psi, float &e, float G[3]) {
     const Herm32 h = hermite32(sp, tab, kn);
     Rows32 R0;
-    load_rows32(h, sp.nchan, 0, R0);
-    dot_grad32_rows(sp, h, R0, x, y, z, inv_r, psi, e, G);
+    load_rows32(h, ChanShape<SHAPE>::nchan(sp), 0, R0);
+    dot_grad32_rows<SHAPE>(sp, h, R0, x, y, z, inv_r, psi, e, G);
 }
 
 // Activity of one atom at one point; x is the FP32 displacement.
@@ -338,7 +386,7 @@ __device__ inline float pow2_scale(double m) {
 // H_IJR (Eq. 2), mixed precision.  Tiles [hi/lo][slot][orbital][point]; wave
 // w owns the diagonal tiles (a_i, b_{(w-i)&3}); two k-steps of 32 points.
 // ---------------------------------------------------------------------------
-template <class T>
+template <class T, int KS>
 __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
     typedef Split16<T> S;
     typedef typename S::vec vec;
@@ -380,11 +428,13 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             const Disp da = disp_at(P, r, sa);
             if (da.in) {
                 CSpecies &sp = cst(P.species)[sa.species];
-                eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
-                    T hi, lo;
-                    S::split(v, hi, lo);
-                    tA[0][w][mu][pt] = hi;
-                    tA[1][w][mu][pt] = lo;
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
+                        T hi, lo;
+                        S::split(v, hi, lo);
+                        tA[0][w][mu][pt] = hi;
+                        tA[1][w][mu][pt] = lo;
+                    });
                 });
                 bits |= 1u << w;
             } else {
@@ -398,11 +448,13 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             if (db.in) {
                 CSpecies &sp = cst(P.species)[sb.species];
                 const float vg = (float)vpt * sB;
-                eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
-                    T hi, lo;
-                    S::split(v, hi, lo);
-                    tB[0][w][mu][pt] = hi;
-                    tB[1][w][mu][pt] = lo;
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
+                        T hi, lo;
+                        S::split(v, hi, lo);
+                        tB[0][w][mu][pt] = hi;
+                        tB[1][w][mu][pt] = lo;
+                    });
                 });
                 bits |= 1u << (4 + w);
             } else {
@@ -528,7 +580,7 @@ constexpr int FSTR = 65;   // floats per point row of the FP32 psi tile
 // [h][point][slot*16+mu]; A atoms only mark where they are active.  Returns
 // the displacement of A atom a_w from this lane's point r, which the
 // per-point phase reuses.
-template <class T>
+template <class T, int KS>
 __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sphi, T (*tB)[GINT_BCPTS][RSTR],
                                  unsigned *maskpt, unsigned *maskt) {
     const int lane = threadIdx.x & 63, w = wave_id();
@@ -542,11 +594,13 @@ __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sp
     T *h1 = &tB[1][pt][w * 16];
     if (db.in) {
         CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
-        eval32(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
-            T hi, lo;
-            Split16<T>::split(v, hi, lo);
-            h0[mu] = hi;
-            h1[mu] = lo;
+        with_shape<KS>(sp, [&](auto shp) {
+            eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
+                T hi, lo;
+                Split16<T>::split(v, hi, lo);
+                h0[mu] = hi;
+                h1[mu] = lo;
+            });
         });
         bits |= 1u << (4 + w);
     } else {
@@ -627,8 +681,8 @@ struct TileBuf {
 // pair.  Wave w owns A atom slot w: psi by MFMA, then per point (lane)
 // phi_{a_w} . psi with phi evaluated on the fly.
 // ---------------------------------------------------------------------------
-template <class T>
-__global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+template <class T, int KS>
+__global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 5) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
@@ -661,7 +715,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const P3 r = point_of(P, o, lane);
-        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, mpt, mt);
+        const Disp da = stage_b16<T, KS>(P, pr, r, sphi, tB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
@@ -676,7 +730,10 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
             if (da.in && (mpt[lane] & 0xF0u)) {
                 const float *ps = psi + lane * FSTR + w * 16;
                 CSpecies &sp = cst(P.species)[cst(P.atoms)[aw].species];
-                eval32(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float x) { v += x * ps[mu]; });
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f,
+                                                 [&](int mu, float x) { v += x * ps[mu]; });
+                });
             }
             part[w][lane] = v;
         }
@@ -699,7 +756,7 @@ __global__ __launch_bounds__(256, 5) void k_rho_mx(GDev P0, const double *__rest
 // pairs, A side; FP32 per-point terms, FP64 accumulation.  With RHO the
 // per-point values phi_A . psi_A are also added into rho (see k_force).
 // ---------------------------------------------------------------------------
-template <class T, bool RHO>
+template <class T, bool RHO, int KS>
 __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__restrict__ V0,
                                                      const double *__restrict__ D, double *__restrict__ F,
                                                      double *__restrict__ ZE0, double *__restrict__ rho0) {
@@ -742,7 +799,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const P3 r = point_of(P, o, lane);
         const double vpt = V[r.g];   // requested early: its latency overlaps the stage
-        const Disp da = stage_b16<T>(P, pr, r, sphi, tB, mpt, mt);
+        const Disp da = stage_b16<T, KS>(P, pr, r, sphi, tB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
@@ -757,8 +814,10 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
             // |r - tau| from the knot: (k + t) dr, relative error ~1e-7
             const float rr = ((float)da.kn.k + da.kn.t) * (float)sp.dr;
             float e, G[3];
-            dot_grad32(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? 1.f / rr : 0.f, psi + lane * FSTR + w * 16,
-                       e, G);
+            with_shape<KS>(sp, [&](auto shp) {
+                dot_grad32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? 1.f / rr : 0.f,
+                                                 psi + lane * FSTR + w * 16, e, G);
+            });
             const double wv = P.w * vpt;
             const double c2 = 2.0 * wv;
             const double g0 = G[0], g1 = G[1], g2 = G[2];
@@ -818,15 +877,6 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
 int gint_persistent_grid(const void *kernel, int nitems, int threads);
 hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 
-template <class K, class... Args>
-static hipError_t launch_persistent(K kernel, const GDev &P, hipStream_t s, Args... args) {
-    if (P.nitems <= 0) return hipSuccess;
-    hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
-    if (e != hipSuccess) return e;
-    const int grid = gint_persistent_grid((const void *)kernel, P.nitems, 256);
-    hipLaunchKernelGGL(kernel, dim3(grid), dim3(256), 0, s, P, args...);
-    return hipGetLastError();
-}
 
 // max |x| into *out (non-negative doubles order like their bit patterns)
 __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ x, long long n,
@@ -835,6 +885,44 @@ __global__ __launch_bounds__(256) void k_absmax(const double *__restrict__ x, lo
     for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) m = fmax(m, fabs(x[i]));
     for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0 && m > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(m));
+}
+
+// Kernel instances per (16-bit type, plan-wide species layout): plans whose
+// species are all 2s2p1d run the instance with that layout fixed, others the
+// one that branches per species.
+struct KVlocal {
+    template <class T, int KS>
+    static const void *get() { return (const void *)k_vlocal_mx<T, KS>; }
+};
+struct KRho {
+    template <class T, int KS>
+    static const void *get() { return (const void *)k_rho_mx<T, KS>; }
+};
+template <bool RHO>
+struct KForce {
+    template <class T, int KS>
+    static const void *get() { return (const void *)k_force_mx<T, RHO, KS>; }
+};
+
+template <class K>
+const void *kernel_for(int prec, int shape_all) {
+    const bool fixed = shape_all == GINT_SHAPE_2S2P1D;
+    if (prec == 2)
+        return fixed ? K::template get<__bf16, GINT_SHAPE_2S2P1D>() : K::template get<__bf16, GINT_SHAPE_ANY>();
+    return fixed ? K::template get<_Float16, GINT_SHAPE_2S2P1D>() : K::template get<_Float16, GINT_SHAPE_ANY>();
+}
+
+template <class K, class... Args>
+hipError_t launch_form(const GDev &P, int prec, hipStream_t s, Args... args) {
+    const void *k = kernel_for<K>(prec, P.shape_all);
+    if (P.nitems <= 0) return hipSuccess;
+    hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
+    if (e != hipSuccess) return e;
+    const int grid = gint_persistent_grid(k, P.nitems, 256);
+    void *argv[] = {const_cast<GDev *>(&P), &args...};
+    e = hipLaunchKernel(k, dim3(grid), dim3(256), argv, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
 }
 
 hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
@@ -849,36 +937,26 @@ hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long 
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    return prec == 2 ? launch_persistent(k_vlocal_mx<__bf16>, P, s, V, H)
-                     : launch_persistent(k_vlocal_mx<_Float16>, P, s, V, H);
+    return launch_form<KVlocal>(P, prec, s, V, H);
 }
 
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s) {
-    return prec == 2 ? launch_persistent(k_rho_mx<__bf16>, P, s, D, rho)
-                     : launch_persistent(k_rho_mx<_Float16>, P, s, D, rho);
+    return launch_form<KRho>(P, prec, s, D, rho);
 }
 
 hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
                                 double *rho, hipStream_t s) {
-    if (rho)
-        return prec == 2 ? launch_persistent(k_force_mx<__bf16, true>, P, s, V, D, F, ZE, rho)
-                         : launch_persistent(k_force_mx<_Float16, true>, P, s, V, D, F, ZE, rho);
-    return prec == 2 ? launch_persistent(k_force_mx<__bf16, false>, P, s, V, D, F, ZE, (double *)nullptr)
-                     : launch_persistent(k_force_mx<_Float16, false>, P, s, V, D, F, ZE, (double *)nullptr);
+    if (rho) return launch_form<KForce<true>>(P, prec, s, V, D, F, ZE, rho);
+    return launch_form<KForce<false>>(P, prec, s, V, D, F, ZE, (double *)nullptr);
 }
 
 int gint_resident_blocks(const void *kernel, int threads);
 
 void gint_prime_grids_mx(int prec) {
-    if (prec == 2) {
-        gint_resident_blocks((const void *)k_vlocal_mx<__bf16>, 256);
-        gint_resident_blocks((const void *)k_rho_mx<__bf16>, 256);
-        gint_resident_blocks((const void *)k_force_mx<__bf16, false>, 256);
-        gint_resident_blocks((const void *)k_force_mx<__bf16, true>, 256);
-    } else {
-        gint_resident_blocks((const void *)k_vlocal_mx<_Float16>, 256);
-        gint_resident_blocks((const void *)k_rho_mx<_Float16>, 256);
-        gint_resident_blocks((const void *)k_force_mx<_Float16, false>, 256);
-        gint_resident_blocks((const void *)k_force_mx<_Float16, true>, 256);
+    for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
+        gint_resident_blocks(kernel_for<KVlocal>(prec, shape), 256);
+        gint_resident_blocks(kernel_for<KRho>(prec, shape), 256);
+        gint_resident_blocks(kernel_for<KForce<false>>(prec, shape), 256);
+        gint_resident_blocks(kernel_for<KForce<true>>(prec, shape), 256);
     }
 }

@@ -197,6 +197,15 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         }
         if (norb > GINT_ORB) return fail(GINT_EUNSUPPORTED, "more than 16 orbitals per atom");
         g.norb = norb;
+        {
+            const int *l = sp.chan_l;
+            if (sp.nchan == 5 && l[0] == 0 && l[1] == 0 && l[2] == 1 && l[3] == 1 && l[4] == 2)
+                g.shape = GINT_SHAPE_2S2P1D;
+            else if (sp.nchan == 3 && l[0] == 0 && l[1] == 0 && l[2] == 1)
+                g.shape = GINT_SHAPE_2S1P;
+            else
+                g.shape = GINT_SHAPE_ANY;
+        }
         g.tab_off = (int)hp.tab.size();
         // bound on |phi| = |p_c(r)| |S_lm(x)| over the table: the Hermite
         // cubic on [r_k, r_k+1] is at most |f_k| + |f_k+1| + (4/27) dr
