@@ -64,15 +64,17 @@ struct Herm {
     double d00, d10, d01, d11;     // derivative weights (per unit r)
 };
 
-__device__ inline Herm hermite(CSpecies &sp, const double *tab, double r) {
+template <int SHAPE>
+__device__ __attribute__((always_inline)) inline Herm hermite(CSpecies &sp, const double *tab, double r) {
+    const int nchan = ChanShape<SHAPE>::nchan(sp);
     double t = r * sp.inv_dr;
     int k = (int)t;
     if (k > sp.nknots - 2) k = sp.nknots - 2;
     t -= (double)k;
     const double t2 = t * t, t3 = t2 * t;
     Herm h;
-    h.row0 = tab + sp.tab_off + (size_t)k * sp.nchan * 2;
-    h.row1 = h.row0 + sp.nchan * 2;
+    h.row0 = tab + sp.tab_off + (size_t)k * nchan * 2;
+    h.row1 = h.row0 + nchan * 2;
     h.h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
     h.h10 = (t3 - 2.0 * t2 + t) * sp.dr;
     h.h01 = 3.0 * t2 - 2.0 * t3;
@@ -106,7 +108,7 @@ struct Rows {
     dbl2 a[RCH], b[RCH];    // (f_k, f'_k) and (f_k+1, f'_k+1) of channel c0 + q
 };
 
-__device__ inline void load_rows(const Herm &h, int nchan, int c0, Rows &R) {
+__device__ __attribute__((always_inline)) inline void load_rows(const Herm &h, int nchan, int c0, Rows &R) {
 #pragma unroll
     for (int q = 0; q < RCH; ++q)
         if (c0 + q < nchan) {
@@ -117,13 +119,14 @@ __device__ inline void load_rows(const Herm &h, int nchan, int c0, Rows &R) {
 
 // phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
 // (LDS); slots past the atom's orbitals are zero.
-__device__ inline void eval_phi(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
-                                double scale, double *dst) {
+template <int SHAPE>
+__device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, const double *tab, double x, double y,
+                                                               double z, double r2, double scale, double *dst) {
     const double r = sqrt(r2);
-    const Herm h = hermite(sp, tab, r);
+    const Herm h = hermite<SHAPE>(sp, tab, r);
     double S[9];
     solid9(x, y, z, S);
-    const int nchan = sp.nchan;
+    const int nchan = ChanShape<SHAPE>::nchan(sp);
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH) {
         Rows R;
@@ -132,7 +135,7 @@ __device__ inline void eval_phi(CSpecies &sp, const double *tab, double x, doubl
         for (int q = 0; q < RCH; ++q) {
             if (c0 + q >= nchan) break;
             const double p = (h.h00 * R.a[q].x + h.h10 * R.a[q].y + h.h01 * R.b[q].x + h.h11 * R.b[q].y) * scale;
-            const int l = sp.chan_l[c0 + q];
+            const int l = ChanShape<SHAPE>::l(sp, c0 + q);
             if (l == 0) {
                 dst[slot] = p * S[0];
                 slot += 1;
@@ -161,15 +164,16 @@ __device__ inline void zero16(double *dst) {
 
 // sum_mu psi_mu phi_mu and (GRAD) sum_mu psi_mu grad phi_mu for one atom at
 // x (grad phi = (p'/r) x S + p grad S; the first term is 0 at r = 0).
-template <bool GRAD>
-__device__ inline void dot_phi(CSpecies &sp, const double *tab, double x, double y, double z, double r2,
-                               const double *psi, double &e, double G[3]) {
+template <bool GRAD, int SHAPE>
+__device__ __attribute__((always_inline)) inline void dot_phi(CSpecies &sp, const double *tab, double x, double y,
+                                                              double z, double r2, const double *psi, double &e,
+                                                              double G[3]) {
     const double r = sqrt(r2);
-    const Herm h = hermite(sp, tab, r);
+    const Herm h = hermite<SHAPE>(sp, tab, r);
     const double inv_r = r > 0.0 ? 1.0 / r : 0.0;
     e = 0.0;
     G[0] = G[1] = G[2] = 0.0;
-    const int nchan = sp.nchan;
+    const int nchan = ChanShape<SHAPE>::nchan(sp);
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH) {
         Rows R;
@@ -180,7 +184,7 @@ __device__ inline void dot_phi(CSpecies &sp, const double *tab, double x, double
             const double f0 = R.a[qq].x, fp0 = R.a[qq].y, f1 = R.b[qq].x, fp1 = R.b[qq].y;
             const double p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
             const double q = GRAD ? (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r : 0.0;
-            const int l = sp.chan_l[c0 + qq];
+            const int l = ChanShape<SHAPE>::l(sp, c0 + qq);
             double A, Bx, By, Bz;   // A = sum_m psi_m S_m, B = sum_m psi_m grad S_m
             if (l == 0) {
                 A = psi[slot] * kC0;
@@ -228,7 +232,7 @@ __device__ inline unsigned or16(unsigned m) {
 // Phase 1: orbitals of the A atom (slot t>>6) and B atom at point t&63.
 // mode 0: A and B unscaled; mode 1: B scaled by w V_g; mode 2: B only, A
 // gets the activity bit only.
-template <int MODE>
+template <int MODE, int KS>
 __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
                              double *phiA, double *phiB, unsigned *maskpt, unsigned *maskt = nullptr) {
     const int t = threadIdx.x;
@@ -249,8 +253,12 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
             CSpecies &sp = cst(P.species)[at.species];
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
             if (MODE != 2) {
-                if (in) eval_phi(sp, P.tab, x, y, z, r2, 1.0, dst);
-                else zero16(dst);
+                if (in)
+                    with_shape<KS>(sp, [&](auto shp) {
+                        eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, 1.0, dst);
+                    });
+                else
+                    zero16(dst);
             }
         } else if (MODE != 2) {
             zero16(dst);
@@ -271,7 +279,9 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
             if (in) {
                 const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
-                eval_phi(sp, P.tab, x, y, z, r2, scale, dst);
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, scale, dst);
+                });
             } else {
                 zero16(dst);
             }
@@ -373,6 +383,7 @@ __device__ inline void store_psi(const d4 c[4], double *phiB, const unsigned *ma
 // ---------------------------------------------------------------------------
 constexpr int kVlocalThreads = 512;
 
+template <int KS>
 __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
                                     double *phiA, double *phiB, unsigned *maskpt) {
     const int pt = threadIdx.x & 63, w = wave_id();
@@ -391,14 +402,19 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
         const double r2 = x * x + y * y + z * z;
         CSpecies &sp = cst(P.species)[at.species];
         in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
-        if (in) eval_phi(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
-        else zero16(dst);
+        if (in)
+            with_shape<KS>(sp, [&](auto shp) {
+                eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
+            });
+        else
+            zero16(dst);
     } else {
         zero16(dst);
     }
     if (in) atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
 }
 
+template <int KS>
 __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const double *__restrict__ V0,
                                                               double *__restrict__ H) {
     __shared__ double phiA[GINT_BCPTS * PSTR];
@@ -424,7 +440,7 @@ __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const dou
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_vlocal(P, pr, o, V, phiA, phiB, maskpt);
+        stage_vlocal<KS>(P, pr, o, V, phiA, phiB, maskpt);
         __syncthreads();
         // k-step t of this wave = points 32 half + 4t .. +3; its activity mask is
         // the OR over those 4 points, read into scalar registers once
@@ -493,6 +509,7 @@ __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const dou
 // atom slot w: psi of a_w for the 64 points by MFMA, then per point (lane)
 // phi_{a_w} . psi evaluated on the fly.
 // ---------------------------------------------------------------------------
+template <int KS>
 __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
@@ -522,7 +539,7 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
-        stage<2>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
+        stage<2, KS>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
@@ -542,8 +559,11 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
                 const double y = r.y - at.y - pr.shiftA[1];
                 const double z = r.z - at.z - pr.shiftA[2];
                 double G[3];
-                dot_phi<false>(cst(P.species)[at.species], P.tab, x, y, z, x * x + y * y + z * z,
-                               phiB + lane * PSTR + w * GINT_ORB, v, G);
+                CSpecies &spa = cst(P.species)[at.species];
+                with_shape<KS>(spa, [&](auto shp) {
+                    dot_phi<false, decltype(shp)::value>(spa, P.tab, x, y, z, x * x + y * y + z * z,
+                                                         phiB + lane * PSTR + w * GINT_ORB, v, G);
+                });
             }
             part[w][lane] = v;
         }
@@ -568,7 +588,7 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
 // are also added into rho: over the two orders of a pair they give rho's
 // weight 2 off the self pair, so one pass yields rho, F, Z and E.
 // ---------------------------------------------------------------------------
-template <bool RHO>
+template <bool RHO, int KS>
 __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restrict__ V0,
                                                   const double *__restrict__ D, double *__restrict__ F,
                                                   double *__restrict__ ZE0, double *__restrict__ rho0) {
@@ -604,7 +624,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const double vpt = V[bigcell_point(P, o, lane).g];   // requested early: its latency overlaps the stage
-        stage<2>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
+        stage<2, KS>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
@@ -623,7 +643,10 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
             const double zz = r.z - at.z - pr.shiftA[2];
             const double r2 = x * x + y * y + zz * zz;
             double G[3];
-            dot_phi<true>(cst(P.species)[at.species], P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
+            CSpecies &spa = cst(P.species)[at.species];
+            with_shape<KS>(spa, [&](auto shp) {
+                dot_phi<true, decltype(shp)::value>(spa, P.tab, x, y, zz, r2, phiB + lane * PSTR + w * GINT_ORB, e, G);
+            });
             const double wv = P.w * vpt;
             const double c2 = 2.0 * wv;
             f[0] += c2 * G[0];
@@ -859,17 +882,32 @@ hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s) {
 #define GINT_PERSISTENT_LAUNCH(KERNEL, P, s, ...) GINT_PERSISTENT_LAUNCH_T(KERNEL, 256, P, s, __VA_ARGS__)
 
 hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s) {
-    GINT_PERSISTENT_LAUNCH_T(k_vlocal, kVlocalThreads, P, s, V, H);
+    if (P.shape_all == GINT_SHAPE_2S2P1D) {
+        auto k = k_vlocal<GINT_SHAPE_2S2P1D>;
+        GINT_PERSISTENT_LAUNCH_T(k, kVlocalThreads, P, s, V, H);
+    }
+    auto k = k_vlocal<GINT_SHAPE_ANY>;
+    GINT_PERSISTENT_LAUNCH_T(k, kVlocalThreads, P, s, V, H);
 }
 
 hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s) {
-    GINT_PERSISTENT_LAUNCH(k_rho, P, s, D, rho);
+    if (P.shape_all == GINT_SHAPE_2S2P1D) {
+        auto k = k_rho<GINT_SHAPE_2S2P1D>;
+        GINT_PERSISTENT_LAUNCH(k, P, s, D, rho);
+    }
+    auto k = k_rho<GINT_SHAPE_ANY>;
+    GINT_PERSISTENT_LAUNCH(k, P, s, D, rho);
 }
 
 hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, double *rho,
                              hipStream_t s) {
-    if (rho) GINT_PERSISTENT_LAUNCH(k_force<true>, P, s, V, D, F, ZE, rho);
-    GINT_PERSISTENT_LAUNCH(k_force<false>, P, s, V, D, F, ZE, nullptr);
+    const bool fixed = P.shape_all == GINT_SHAPE_2S2P1D;
+    if (rho) {
+        auto k = fixed ? k_force<true, GINT_SHAPE_2S2P1D> : k_force<true, GINT_SHAPE_ANY>;
+        GINT_PERSISTENT_LAUNCH(k, P, s, V, D, F, ZE, rho);
+    }
+    auto k = fixed ? k_force<false, GINT_SHAPE_2S2P1D> : k_force<false, GINT_SHAPE_ANY>;
+    GINT_PERSISTENT_LAUNCH(k, P, s, V, D, F, ZE, (double *)nullptr);
 }
 
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
@@ -902,9 +940,13 @@ hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *st
 
 // Fill the resident-block cache for every kernel of a precision form.
 void gint_prime_grids_fp64() {
-    gint_resident_blocks((const void *)k_vlocal, kVlocalThreads);
-    gint_resident_blocks((const void *)k_rho, 256);
-    gint_resident_blocks((const void *)k_force<false>, 256);
-    gint_resident_blocks((const void *)k_force<true>, 256);
+    gint_resident_blocks((const void *)k_vlocal<GINT_SHAPE_ANY>, kVlocalThreads);
+    gint_resident_blocks((const void *)k_vlocal<GINT_SHAPE_2S2P1D>, kVlocalThreads);
+    gint_resident_blocks((const void *)k_rho<GINT_SHAPE_ANY>, 256);
+    gint_resident_blocks((const void *)k_rho<GINT_SHAPE_2S2P1D>, 256);
+    gint_resident_blocks((const void *)k_force<false, GINT_SHAPE_ANY>, 256);
+    gint_resident_blocks((const void *)k_force<false, GINT_SHAPE_2S2P1D>, 256);
+    gint_resident_blocks((const void *)k_force<true, GINT_SHAPE_ANY>, 256);
+    gint_resident_blocks((const void *)k_force<true, GINT_SHAPE_2S2P1D>, 256);
     gint_resident_blocks((const void *)k_work, 256);
 }

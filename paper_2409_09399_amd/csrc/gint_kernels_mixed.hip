@@ -15,8 +15,6 @@
 
 #include "gint_device.h"
 
-#include <type_traits>
-
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
@@ -147,50 +145,6 @@ __device__ __attribute__((always_inline)) inline void load_rows32(const Herm32 &
             R.a[q] = *(const flt2 *)(h.row0 + 2 * (c0 + q));
             R.b[q] = *(const flt2 *)(h.row1 + 2 * (c0 + q));
         }
-}
-
-// Channel layout of a species: with SHAPE a fixed layout (GINT_SHAPE_*) the
-// channel count and each channel's l are compile-time constants, so the
-// evaluation below unrolls completely (orbital slots and LDS offsets become
-// constants and no per-channel branches remain); SHAPE 0 reads them from the
-// species record.
-template <int SHAPE>
-struct ChanShape {
-    __device__ static int nchan(CSpecies &sp) { return sp.nchan; }
-    __device__ static int l(CSpecies &sp, int c) { return sp.chan_l[c]; }
-};
-template <>
-struct ChanShape<GINT_SHAPE_2S2P1D> {
-    __device__ static constexpr int nchan(CSpecies &) { return 5; }
-    __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : (c < 4 ? 1 : 2); }
-};
-template <>
-struct ChanShape<GINT_SHAPE_2S1P> {
-    __device__ static constexpr int nchan(CSpecies &) { return 3; }
-    __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : 1; }
-};
-
-// f(std::integral_constant<int, SHAPE>) for the species' layout (a
-// wave-uniform branch on the species record).
-template <class F>
-__device__ __attribute__((always_inline)) inline void by_shape(CSpecies &sp, F &&f) {
-    const int shape = sp.shape;
-    if (shape == GINT_SHAPE_2S2P1D)
-        f(std::integral_constant<int, GINT_SHAPE_2S2P1D>{});
-    else if (shape == GINT_SHAPE_2S1P)
-        f(std::integral_constant<int, GINT_SHAPE_2S1P>{});
-    else
-        f(std::integral_constant<int, GINT_SHAPE_ANY>{});
-}
-
-// As by_shape, for a kernel compiled for plans whose species all have layout
-// KS (then no branch remains), or for any mix (KS = GINT_SHAPE_ANY).
-template <int KS, class F>
-__device__ __attribute__((always_inline)) inline void with_shape(CSpecies &sp, F &&f) {
-    if constexpr (KS != GINT_SHAPE_ANY)
-        f(std::integral_constant<int, KS>{});
-    else
-        by_shape(sp, f);
 }
 
 // phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v),
