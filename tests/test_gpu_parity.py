@@ -217,3 +217,25 @@ def test_fused_rho_force(G, torch_dev, oracle_mod, case):
     ne_o = float(rho_o.sum()) * s.volume / s.ngrid
     assert abs(float(ne.cpu()[0]) - ne_o) <= TOL * abs(ne_o)
     plan.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp16x3"])
+def test_layout_instances_agree(G, torch_dev, prec):
+    """A plan whose species all have the 2s2p1d channel layout runs kernels
+    with that layout built in; adding an unused species of another layout
+    (spd) sends the same atoms through the kernels that pick the layout per
+    species.  Both give the same H, rho, F, sigma and E (FP64: to round-off
+    of the summation order; FP16x3: to its split precision)."""
+    import dataclasses
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.diamond8(4)
+    extra = I.make_species("X", "spd", 4.0, 0.01, np.random.default_rng(0))
+    s2 = dataclasses.replace(s, species_list=list(s.species_list) + [extra], name=s.name + "+unused_spd")
+    a = run_all(G, torch, dev, s, precision=prec)
+    b = run_all(G, torch, dev, s2, precision=prec)
+    tol = 1e-13 if prec == 0 else 1e-6
+    for k in ("h", "rho", "F", "sig"):
+        assert rel(b[k], a[k]) <= tol, (k, rel(b[k], a[k]))
+    assert abs(b["E"] - a["E"]) <= tol * abs(a["E"])
+    assert b["W"] == a["W"]
