@@ -514,7 +514,6 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
     __shared__ double phiB[GINT_BCPTS * PSTR];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
     __shared__ unsigned maskt[2];
-    __shared__ double part[4][GINT_BCPTS];
     __shared__ int s_item;
     // masks are double-buffered: each bigcell uses buffer cur, which is clear
     // on entry, and clears the other one for the next bigcell
@@ -564,15 +563,8 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
                     dot_phi<false, decltype(shp)::value>(spa, P.tab, x, y, z, x * x + y * y + z * z,
                                                          phiB + lane * PSTR + w * GINT_ORB, v, G);
                 });
-            }
-            part[w][lane] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < GINT_BCPTS) {
-            const int pt = threadIdx.x;
-            const double v = part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt];
-            if ((mpt[pt] & 0xFu) && (mpt[pt] & 0xF0u)) {
-                const Pt r = bigcell_point(P, o, pt);
+                // each wave adds its atom's term: no LDS sum over the waves and
+                // no barrier for it, at the price of more atomics
                 atomicAdd(rho + r.g, weight * v);
             }
         }
@@ -596,7 +588,6 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
     __shared__ unsigned maskpt[2][GINT_BCPTS];
     __shared__ unsigned maskt[2];
     __shared__ double red[4][10];
-    __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     __shared__ int s_item;
     // masks are double-buffered: each bigcell uses buffer cur, which is clear
     // on entry, and clears the other one for the next bigcell
@@ -623,7 +614,8 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
-        const double vpt = V[bigcell_point(P, o, lane).g];   // requested early: its latency overlaps the stage
+        const long long gl = bigcell_point(P, o, lane).g;
+        const double vpt = V[gl];   // requested early: its latency overlaps the stage
         stage<2, KS>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
@@ -659,17 +651,9 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
                 for (int b = 0; b < 3; ++b) z[3 * a + b] += c2 * G[a] * xs[b];
             en += wv * e;
         }
-        if (RHO) {
-            part[w][lane] = e;
-            __syncthreads();
-            if (threadIdx.x < GINT_BCPTS) {
-                const int pt = threadIdx.x;
-                if ((mpt[pt] & 0xFu) && (mpt[pt] & 0xF0u)) {
-                    const Pt r = bigcell_point(P, o, pt);
-                    atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
-                }
-            }
-        }
+        // each wave adds its atom's rho term (over the two orders of a pair this
+        // gives rho's weight 2 off the self pair)
+        if (RHO && e != 0.0) atomicAdd(rho + gl, e);
         __syncthreads();
     }
     // reduce over the wave

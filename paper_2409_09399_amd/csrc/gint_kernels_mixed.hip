@@ -641,7 +641,6 @@ __global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 5) void k_rho_mx(GD
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
     __shared__ unsigned maskt[2];
-    __shared__ float part[4][GINT_BCPTS];
     __shared__ int s_item;
     T(*tB)[GINT_BCPTS][RSTR] = reinterpret_cast<T(*)[GINT_BCPTS][RSTR]>(buf);
     float *psi = reinterpret_cast<float *>(buf);
@@ -688,16 +687,9 @@ __global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 5) void k_rho_mx(GD
                     eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f,
                                                  [&](int mu, float x) { v += x * ps[mu]; });
                 });
-            }
-            part[w][lane] = v;
-        }
-        __syncthreads();
-        if (threadIdx.x < GINT_BCPTS) {
-            const int pt = threadIdx.x;
-            const unsigned m = mpt[pt];
-            if ((m & 0xFu) && (m & 0xF0u)) {
-                const double v = (double)part[0][pt] + (double)part[1][pt] + (double)part[2][pt] + (double)part[3][pt];
-                atomicAdd(rho + r.g, weight * v);   // threads below 64 are wave 0: r is point pt
+                // each wave adds its atom's term: no LDS sum over the waves and
+                // no barrier for it, at the price of more (FP64) atomics
+                atomicAdd(rho + r.g, weight * (double)v);
             }
         }
         __syncthreads();
@@ -719,7 +711,6 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
     __shared__ unsigned maskpt[2][GINT_BCPTS];
     __shared__ unsigned maskt[2];
     __shared__ double red[4][10];
-    __shared__ double part[RHO ? 4 : 1][GINT_BCPTS];
     // psi has LDS of its own here (each wave writes and reads only its own
     // columns), so no barrier separates the psi products from the stores; at
     // four workgroups per CU (the register limit) the extra LDS costs no occupancy
@@ -786,18 +777,9 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
             en += wv * (double)e;
             ev = (double)e;
         }
-        if (RHO) {
-            part[w][lane] = ev;
-            __syncthreads();
-            if (threadIdx.x < GINT_BCPTS) {
-                const int pt = threadIdx.x;
-                const unsigned m = mpt[pt];
-                if ((m & 0xFu) && (m & 0xF0u)) {
-                    // threads below 64 are wave 0: r is point pt
-                    atomicAdd(rho + r.g, part[0][pt] + part[1][pt] + part[2][pt] + part[3][pt]);
-                }
-            }
-        }
+        // each wave adds its atom's rho term (over the two orders of a pair this
+        // gives rho's weight 2 off the self pair)
+        if (RHO && ev != 0.0) atomicAdd(rho + r.g, ev);
         __syncthreads();
     }
     for (int off = 32; off > 0; off >>= 1) {
