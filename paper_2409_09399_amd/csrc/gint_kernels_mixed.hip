@@ -546,7 +546,34 @@ __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sp
     const Disp db = disp_of(P, r, b, pr.shiftB);
     T *h0 = &tB[0][pt][w * 16];
     T *h1 = &tB[1][pt][w * 16];
-    if (db.in) {
+    typedef typename Split16<T>::vec vec;
+    if constexpr (KS != GINT_SHAPE_ANY) {
+        // fixed layout: the orbital indices are compile-time constants, so the
+        // 16 hi and 16 lo values are gathered in registers and written with
+        // 16-byte stores (with 144-byte point rows each 16 lanes of such a
+        // store hit distinct banks; 2-byte stores conflict 4-way)
+        vec hv[2], lv[2];
+        if (db.in) {
+            CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
+            eval32<KS>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
+                T hi, lo;
+                Split16<T>::split(v, hi, lo);
+                hv[mu >> 3][mu & 7] = hi;
+                lv[mu >> 3][mu & 7] = lo;
+            });
+            bits |= 1u << (4 + w);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                hv[k] = (vec)(T)0.f;
+                lv[k] = (vec)(T)0.f;
+            }
+        }
+        *(vec *)h0 = hv[0];
+        *(vec *)(h0 + 8) = hv[1];
+        *(vec *)h1 = lv[0];
+        *(vec *)(h1 + 8) = lv[1];
+    } else if (db.in) {
         CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
         with_shape<KS>(sp, [&](auto shp) {
             eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
