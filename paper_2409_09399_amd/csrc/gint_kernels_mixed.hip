@@ -19,6 +19,7 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 typedef double d4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef unsigned u4v __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -38,13 +39,39 @@ __device__ inline void fp32_value(float &v) { asm("" : "+v"(v)); }
 template <class T>
 struct Split16;
 
+// FP16: lo comes from one mixed-precision FMA, -hi * 1 + v with hi read as
+// FP16, rounded once to FP16.  v - hi is exact in FP32 (hi is v rounded to
+// 11 bits, so the difference needs at most 12), hence this gives the same
+// bits as converting hi back, subtracting and rounding, in one instruction
+// instead of three.
 template <>
 struct Split16<_Float16> {
     typedef h8v vec;
+    static constexpr bool pairs = true;
     __device__ static inline void split(float v, _Float16 &hi, _Float16 &lo) {
         fp32_value(v);
         hi = (_Float16)v;
         lo = (_Float16)(v - (float)hi);
+    }
+    // the same with the one-instruction lo (used where the kernel instance has
+    // a fixed channel layout; in the per-species instances the inline asm
+    // costs register spills)
+    __device__ static inline void split_mix(float v, _Float16 &hi, _Float16 &lo) {
+        fp32_value(v);
+        hi = (_Float16)v;
+        unsigned l;
+        asm("v_fma_mixlo_f16 %0, -%1, %3, %2 op_sel_hi:[1,0,0]" : "=v"(l) : "v"(hi), "v"(v), "s"(1.0f));
+        lo = __builtin_bit_cast(_Float16, (unsigned short)l);
+    }
+    // two values as packed pairs (the first in the low half): one packed
+    // conversion for hi and the lo halves written in place
+    __device__ static inline void split2(float v0, float v1, unsigned &hi, unsigned &lo) {
+        fp32_value(v0);
+        fp32_value(v1);
+        asm("v_cvt_pk_f16_f32 %0, %1, %2" : "=v"(hi) : "v"(v0), "v"(v1));
+        asm("v_fma_mixlo_f16 %0, -%1, %4, %2 op_sel_hi:[1,0,0]\n\t"
+            "v_fma_mixhi_f16 %0, -%1, %4, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+            : "=&v"(lo) : "v"(hi), "v"(v0), "v"(v1), "s"(1.0f));
     }
     __device__ static inline f4v mfma(vec a, vec b, f4v c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
@@ -54,11 +81,13 @@ struct Split16<_Float16> {
 template <>
 struct Split16<__bf16> {
     typedef b8v vec;
+    static constexpr bool pairs = false;
     __device__ static inline void split(float v, __bf16 &hi, __bf16 &lo) {
         fp32_value(v);
         hi = (__bf16)v;
         lo = (__bf16)(v - (float)hi);
     }
+    __device__ static inline void split_mix(float v, __bf16 &hi, __bf16 &lo) { split(v, hi, lo); }
     __device__ static inline f4v mfma(vec a, vec b, f4v c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
     }
@@ -346,12 +375,16 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
     typedef typename S::vec vec;
     __shared__ __attribute__((aligned(16))) T tA[2][4][16][TSTR];
     __shared__ __attribute__((aligned(16))) T tB[2][4][16][TSTR];
-    __shared__ unsigned maskpt[GINT_BCPTS];
+    __shared__ unsigned maskpt2[2][GINT_BCPTS];
     __shared__ int s_item;
     // A = phi * sphi, B = V phi * sB, both below 2^13 in magnitude
     const float sphi = (float)P0.phi_scale;
     const float sB = pow2_scale(*cst(P0.vmax) * (8192.0 / P0.phi_scale));
     const double unscale = 1.0 / ((double)sphi * (double)sB);
+    // the activity mask is double-buffered: each bigcell uses buffer cur,
+    // clear on entry, and clears the other one for the next bigcell
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt2[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    int cur = 0;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -369,8 +402,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
-        __syncthreads();
+        unsigned *maskpt = maskpt2[cur];
         {
             // phase 1: A atom (slot w) and B atom (slot w) at point lane
             const int pt = lane;
@@ -385,7 +417,10 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
                         T hi, lo;
-                        S::split(v, hi, lo);
+                        if constexpr (KS != GINT_SHAPE_ANY)
+                            S::split_mix(v, hi, lo);
+                        else
+                            S::split(v, hi, lo);
                         tA[0][w][mu][pt] = hi;
                         tA[1][w][mu][pt] = lo;
                     });
@@ -405,7 +440,10 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                         T hi, lo;
-                        S::split(v, hi, lo);
+                        if constexpr (KS != GINT_SHAPE_ANY)
+                            S::split_mix(v, hi, lo);
+                        else
+                            S::split(v, hi, lo);
                         tB[0][w][mu][pt] = hi;
                         tB[1][w][mu][pt] = lo;
                     });
@@ -421,6 +459,9 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             if (bits) atomicOr(&maskpt[pt], bits);
         }
         __syncthreads();
+        // the other buffer was last read before the previous bigcell's final barrier
+        if (threadIdx.x < GINT_BCPTS) maskpt2[cur ^ 1][threadIdx.x] = 0u;
+        cur ^= 1;
         // phase 2: activity of the two 32-point k-steps
         const unsigned mp = maskpt[lane];
         unsigned km[2] = {0u, 0u};
@@ -546,33 +587,49 @@ __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sp
     const Disp db = disp_of(P, r, b, pr.shiftB);
     T *h0 = &tB[0][pt][w * 16];
     T *h1 = &tB[1][pt][w * 16];
-    typedef typename Split16<T>::vec vec;
     if constexpr (KS != GINT_SHAPE_ANY) {
         // fixed layout: the orbital indices are compile-time constants, so the
         // 16 hi and 16 lo values are gathered in registers and written with
         // 16-byte stores (with 144-byte point rows each 16 lanes of such a
         // store hit distinct banks; 2-byte stores conflict 4-way)
-        vec hv[2], lv[2];
+        // (orbitals are emitted in increasing order, so a pair completes at
+        // each odd index)
+        u4v hv[2], lv[2];
         if (db.in) {
             CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
+            float pend = 0.f;
             eval32<KS>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
-                T hi, lo;
-                Split16<T>::split(v, hi, lo);
-                hv[mu >> 3][mu & 7] = hi;
-                lv[mu >> 3][mu & 7] = lo;
+                if constexpr (Split16<T>::pairs) {
+                    if (mu & 1) {
+                        unsigned h2, l2;
+                        Split16<T>::split2(pend, v, h2, l2);
+                        hv[mu >> 3][(mu & 7) >> 1] = h2;
+                        lv[mu >> 3][(mu & 7) >> 1] = l2;
+                    } else {
+                        pend = v;
+                    }
+                } else {
+                    T hi, lo;
+                    Split16<T>::split(v, hi, lo);
+                    const unsigned sh = 16 * (mu & 1);
+                    const unsigned hb = __builtin_bit_cast(unsigned short, hi), lb = __builtin_bit_cast(unsigned short, lo);
+                    const int k = mu >> 3, e = (mu & 7) >> 1;
+                    hv[k][e] = (mu & 1) ? (hv[k][e] | (hb << sh)) : hb;
+                    lv[k][e] = (mu & 1) ? (lv[k][e] | (lb << sh)) : lb;
+                }
             });
             bits |= 1u << (4 + w);
         } else {
 #pragma unroll
             for (int k = 0; k < 2; ++k) {
-                hv[k] = (vec)(T)0.f;
-                lv[k] = (vec)(T)0.f;
+                hv[k] = (u4v){0u, 0u, 0u, 0u};
+                lv[k] = (u4v){0u, 0u, 0u, 0u};
             }
         }
-        *(vec *)h0 = hv[0];
-        *(vec *)(h0 + 8) = hv[1];
-        *(vec *)h1 = lv[0];
-        *(vec *)(h1 + 8) = lv[1];
+        *(u4v *)h0 = hv[0];
+        *(u4v *)(h0 + 8) = hv[1];
+        *(u4v *)h1 = lv[0];
+        *(u4v *)(h1 + 8) = lv[1];
     } else if (db.in) {
         CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
         with_shape<KS>(sp, [&](auto shp) {
@@ -787,7 +844,7 @@ __global__ __launch_bounds__(256, 4) void k_force_mx(GDev P0, const double *__re
             const float rr = ((float)da.kn.k + da.kn.t) * (float)sp.dr;
             float e, G[3];
             with_shape<KS>(sp, [&](auto shp) {
-                dot_grad32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? 1.f / rr : 0.f,
+                dot_grad32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, rr > 0.f ? __builtin_amdgcn_rcpf(rr) : 0.f,
                                                  psi + lane * FSTR + w * 16, e, G);
             });
             const double wv = P.w * vpt;
