@@ -117,9 +117,10 @@ __device__ inline P3 point_of(const GDev &P, const GBig &o, int pt) {
     return r;
 }
 
-// Cubic Hermite on the FP32 table: knot rows k, k+1 ([chan][f, f']) and weights.
+// Cubic Hermite on the FP32 table: the interval record of knot k
+// ([chan][f_k, f'_k, f_k+1, f'_k+1], 16 bytes a channel) and the weights.
 struct Herm32 {
-    const float *row0, *row1;
+    const float *rec;
     float h00, h10, h01, h11, d00, d10, d01, d11;
 };
 
@@ -144,8 +145,7 @@ __device__ __attribute__((always_inline)) inline Herm32 hermite32(CSpecies &sp, 
     const float t = kn.t;
     const float t2 = t * t, t3 = t2 * t, dr = (float)sp.dr, idr = (float)sp.inv_dr;
     Herm32 h;
-    h.row0 = tab + sp.tab_off + (size_t)k * sp.nchan * 2;
-    h.row1 = h.row0 + sp.nchan * 2;
+    h.rec = tab + 2 * (size_t)sp.tab_off + (size_t)k * sp.nchan * 4;
     h.h00 = 2.f * t3 - 3.f * t2 + 1.f;
     h.h10 = (t3 - 2.f * t2 + t) * dr;
     h.h01 = 3.f * t2 - 2.f * t3;
@@ -162,6 +162,7 @@ __device__ __attribute__((always_inline)) inline Herm32 hermite32(CSpecies &sp, 
 // memory round trip per channel).
 constexpr int RCH32 = 5;
 typedef float flt2 __attribute__((ext_vector_type(2)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
 struct Rows32 {
     flt2 a[RCH32], b[RCH32];
@@ -171,8 +172,9 @@ __device__ __attribute__((always_inline)) inline void load_rows32(const Herm32 &
 #pragma unroll
     for (int q = 0; q < RCH32; ++q)
         if (c0 + q < nchan) {
-            R.a[q] = *(const flt2 *)(h.row0 + 2 * (c0 + q));
-            R.b[q] = *(const flt2 *)(h.row1 + 2 * (c0 + q));
+            const flt4 v = *(const flt4 *)(h.rec + 4 * (c0 + q));
+            R.a[q] = v.xy;
+            R.b[q] = v.zw;
         }
 }
 

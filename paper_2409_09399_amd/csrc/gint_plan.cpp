@@ -232,7 +232,27 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         hp.species.push_back(g);
     }
     if (hp.tab.size() > (size_t)0x7fffffff) return fail(GINT_EINVAL, "radial tables too large");
-    hp.tab32.assign(hp.tab.begin(), hp.tab.end());
+    // FP32 tables by knot interval: [interval k][chan][f_k, f'_k, f_k+1, f'_k+1],
+    // 16-byte records, so one evaluation reads each channel with one 16-byte
+    // load.  Twice the length of the FP64 table, so species s starts at
+    // 2 tab_off (also after the batch merge); the record of the last knot
+    // (never an interval start) repeats that knot.
+    hp.tab32.assign(2 * hp.tab.size(), 0.f);
+    for (const GSpecies &g : hp.species) {
+        const size_t C = (size_t)g.nchan, K = (size_t)g.nknots;
+        const double *t = hp.tab.data() + g.tab_off;
+        float *o = hp.tab32.data() + 2 * (size_t)g.tab_off;
+        for (size_t k = 0; k < K; ++k) {
+            const size_t k1 = k + 1 < K ? k + 1 : k;
+            for (size_t c = 0; c < C; ++c) {
+                float *r = o + (k * C + c) * 4;
+                r[0] = (float)t[(k * C + c) * 2];
+                r[1] = (float)t[(k * C + c) * 2 + 1];
+                r[2] = (float)t[(k1 * C + c) * 2];
+                r[3] = (float)t[(k1 * C + c) * 2 + 1];
+            }
+        }
+    }
 
     // ---- atoms
     const int natom = sys->natom;
