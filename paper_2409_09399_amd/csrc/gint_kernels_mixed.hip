@@ -351,6 +351,13 @@ __device__ inline Disp disp_at(const GDev &P, const P3 &r, const Slot &s) {
     return d;
 }
 
+// Whether any lane of this lane's 32-lane half has the flag set (the
+// ballot is taken by every lane, so call it where the whole wave is).
+__device__ inline bool half_active(bool flag) {
+    const unsigned long long b = __ballot(flag);
+    return ((b >> (threadIdx.x & 32)) & 0xffffffffull) != 0ull;
+}
+
 constexpr int TSTR = 72;   // 16-bit elements per tile row (64 points + 8): conflict-free 16-byte reads
 
 // Power of two s with m s in [2^12, 2^13) (1 if m is 0 or not finite),
@@ -414,6 +421,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
             const double vpt = V[r.g];
             unsigned bits = 0;
             const Disp da = disp_at(P, r, sa);
+            const bool zA = half_active(da.in);
             if (da.in) {
                 CSpecies &sp = cst(P.species)[sa.species];
                 with_shape<KS>(sp, [&](auto shp) {
@@ -428,7 +436,10 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                     });
                 });
                 bits |= 1u << w;
-            } else {
+            } else if (zA) {
+                // zeros only where the half is read: a 32-point k-step of
+                // slot w's tile enters the products only if A_w is active
+                // somewhere in it
 #pragma unroll
                 for (int mu = 0; mu < 16; ++mu) {
                     tA[0][w][mu][pt] = (T)0.f;
@@ -436,6 +447,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 }
             }
             const Disp db = disp_at(P, r, sb);
+            const bool zB = half_active(db.in);
             if (db.in) {
                 CSpecies &sp = cst(P.species)[sb.species];
                 const float vg = (float)vpt * sB;
@@ -451,7 +463,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                     });
                 });
                 bits |= 1u << (4 + w);
-            } else {
+            } else if (zB) {
 #pragma unroll
                 for (int mu = 0; mu < 16; ++mu) {
                     tB[0][w][mu][pt] = (T)0.f;
