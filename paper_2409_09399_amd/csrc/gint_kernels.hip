@@ -396,22 +396,31 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
     cdouble *sh = sideB ? pr.shiftB : pr.shiftA;
     double *dst = (sideB ? phiB : phiA) + pt * PSTR + slot * GINT_ORB;
     bool in = false;
+    double x = 0.0, y = 0.0, z = 0.0, r2 = 0.0;
+    int species = 0;
     if (a >= 0) {
         const GAtom at = ldc(P.atoms + a);
-        const double x = r.x - at.x - sh[0], y = r.y - at.y - sh[1], z = r.z - at.z - sh[2];
-        const double r2 = x * x + y * y + z * z;
-        CSpecies &sp = cst(P.species)[at.species];
+        x = r.x - at.x - sh[0];
+        y = r.y - at.y - sh[1];
+        z = r.z - at.z - sh[2];
+        r2 = x * x + y * y + z * z;
+        species = at.species;
+        CSpecies &sp = cst(P.species)[species];
         in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
-        if (in)
-            with_shape<KS>(sp, [&](auto shp) {
-                eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
-            });
-        else
-            zero16(dst);
-    } else {
+    }
+    // zeros only where they are read: a 4-point k-step of this slot enters
+    // the products only if the slot is active at one of its points (ballot
+    // taken by the whole wave)
+    const unsigned long long act = __ballot(in);
+    if (in) {
+        CSpecies &sp = cst(P.species)[species];
+        with_shape<KS>(sp, [&](auto shp) {
+            eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
+        });
+        atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
+    } else if ((act >> (pt & ~3)) & 0xFull) {
         zero16(dst);
     }
-    if (in) atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
 }
 
 template <int KS>
