@@ -76,11 +76,13 @@ template <>
 struct ChanShape<GINT_SHAPE_2S2P1D> {
     __device__ static constexpr int nchan(CSpecies &) { return 5; }
     __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : (c < 4 ? 1 : 2); }
+    static constexpr int norb = 13;
 };
 template <>
 struct ChanShape<GINT_SHAPE_2S1P> {
     __device__ static constexpr int nchan(CSpecies &) { return 3; }
     __device__ static constexpr int l(CSpecies &, int c) { return c < 2 ? 0 : 1; }
+    static constexpr int norb = 5;
 };
 
 // f(std::integral_constant<int, SHAPE>) for the species' layout (a

@@ -119,7 +119,7 @@ __device__ __attribute__((always_inline)) inline void load_rows(const Herm &h, i
 
 // phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
 // (LDS); slots past the atom's orbitals are zero.
-template <int SHAPE>
+template <int SHAPE, bool PAD = true>
 __device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, const double *tab, double x, double y,
                                                                double z, double r2, double scale, double *dst) {
     const double r = sqrt(r2);
@@ -154,7 +154,10 @@ __device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, con
             }
         }
     }
-    for (; slot < GINT_ORB; ++slot) dst[slot] = 0.0;
+    // PAD = false leaves the padding slots as they are (where they reach only
+    // outputs beyond the orbital count)
+    if constexpr (PAD)
+        for (; slot < GINT_ORB; ++slot) dst[slot] = 0.0;
 }
 
 __device__ inline void zero16(double *dst) {
@@ -414,12 +417,19 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
     const unsigned long long act = __ballot(in);
     if (in) {
         CSpecies &sp = cst(P.species)[species];
+        // with a fixed layout the padding rows are not stored: they reach only
+        // output rows or columns beyond the orbital count, which are never written
         with_shape<KS>(sp, [&](auto shp) {
-            eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
+            eval_phi<decltype(shp)::value, KS == GINT_SHAPE_ANY>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
         });
         atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
     } else if ((act >> (pt & ~3)) & 0xFull) {
-        zero16(dst);
+        if constexpr (KS == GINT_SHAPE_ANY) {
+            zero16(dst);
+        } else {
+#pragma unroll
+            for (int k = 0; k < ChanShape<KS>::norb; ++k) dst[k] = 0.0;
+        }
     }
 }
 

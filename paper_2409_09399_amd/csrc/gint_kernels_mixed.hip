@@ -351,6 +351,16 @@ __device__ inline Disp disp_at(const GDev &P, const P3 &r, const Slot &s) {
     return d;
 }
 
+// Orbital rows of a Vlocal tile that reach stored outputs: the orbital
+// count of a fixed channel layout, else all 16.
+template <int KS>
+__device__ constexpr int rows_used() {
+    if constexpr (KS == GINT_SHAPE_ANY)
+        return 16;
+    else
+        return ChanShape<KS>::norb;
+}
+
 // Whether any lane of this lane's 32-lane half has the flag set (the
 // ballot is taken by every lane, so call it where the whole wave is).
 __device__ inline bool half_active(bool flag) {
@@ -427,10 +437,14 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
                         T hi, lo;
-                        if constexpr (KS != GINT_SHAPE_ANY)
+                        if constexpr (KS != GINT_SHAPE_ANY) {
+                            // padding rows reach only output rows or columns
+                            // beyond the orbital count, which are never stored
+                            if (mu >= ChanShape<KS>::norb) return;
                             S::split_mix(v, hi, lo);
-                        else
+                        } else {
                             S::split(v, hi, lo);
+                        }
                         tA[0][w][mu][pt] = hi;
                         tA[1][w][mu][pt] = lo;
                     });
@@ -441,7 +455,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 // slot w's tile enters the products only if A_w is active
                 // somewhere in it
 #pragma unroll
-                for (int mu = 0; mu < 16; ++mu) {
+                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
                     tA[0][w][mu][pt] = (T)0.f;
                     tA[1][w][mu][pt] = (T)0.f;
                 }
@@ -454,10 +468,14 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                         T hi, lo;
-                        if constexpr (KS != GINT_SHAPE_ANY)
+                        if constexpr (KS != GINT_SHAPE_ANY) {
+                            // padding rows reach only output rows or columns
+                            // beyond the orbital count, which are never stored
+                            if (mu >= ChanShape<KS>::norb) return;
                             S::split_mix(v, hi, lo);
-                        else
+                        } else {
                             S::split(v, hi, lo);
+                        }
                         tB[0][w][mu][pt] = hi;
                         tB[1][w][mu][pt] = lo;
                     });
@@ -465,7 +483,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 bits |= 1u << (4 + w);
             } else if (zB) {
 #pragma unroll
-                for (int mu = 0; mu < 16; ++mu) {
+                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
                     tB[0][w][mu][pt] = (T)0.f;
                     tB[1][w][mu][pt] = (T)0.f;
                 }
