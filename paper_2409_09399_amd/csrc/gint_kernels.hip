@@ -272,26 +272,32 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
         const int b = pr.b[slot];
         double *dst = phiB + pt * PSTR + slot * GINT_ORB;
         bool in = false;
+        double x = 0.0, y = 0.0, z = 0.0, r2 = 0.0;
+        int species = 0;
         if (b >= 0) {
             const GAtom at = ldc(P.atoms + (b));
-            const double x = r.x - at.x - pr.shiftB[0];
-            const double y = r.y - at.y - pr.shiftB[1];
-            const double z = r.z - at.z - pr.shiftB[2];
-            const double r2 = x * x + y * y + z * z;
-            CSpecies &sp = cst(P.species)[at.species];
+            x = r.x - at.x - pr.shiftB[0];
+            y = r.y - at.y - pr.shiftB[1];
+            z = r.z - at.z - pr.shiftB[2];
+            r2 = x * x + y * y + z * z;
+            species = at.species;
+            CSpecies &sp = cst(P.species)[species];
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
-            if (in) {
-                const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
-                with_shape<KS>(sp, [&](auto shp) {
-                    eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, scale, dst);
-                });
-            } else {
-                zero16(dst);
-            }
-        } else {
+        }
+        // with the per-tile masks the psi products skip a B atom on 16-point
+        // tiles where it is inactive, so zeros go only into tiles where it is
+        // active somewhere (ballot taken by the whole wave)
+        const unsigned long long act = __ballot(in);
+        if (in) {
+            CSpecies &sp = cst(P.species)[species];
+            const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
+            with_shape<KS>(sp, [&](auto shp) {
+                eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, scale, dst);
+            });
+            bits |= 1u << (4 + slot);
+        } else if (!maskt || ((act >> (pt & ~15)) & 0xFFFFull)) {
             zero16(dst);
         }
-        if (in) bits |= 1u << (4 + slot);
     }
     if (bits) atomicOr(&maskpt[pt], bits);
     if (maskt) {
