@@ -437,10 +437,11 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
                         T hi, lo;
-                        if constexpr (KS != GINT_SHAPE_ANY) {
+                        constexpr int SH = decltype(shp)::value;
+                        if constexpr (SH != GINT_SHAPE_ANY) {
                             // padding rows reach only output rows or columns
                             // beyond the orbital count, which are never stored
-                            if (mu >= ChanShape<KS>::norb) return;
+                            if (mu >= ChanShape<SH>::norb) return;
                             S::split_mix(v, hi, lo);
                         } else {
                             S::split(v, hi, lo);
@@ -468,10 +469,11 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
                         T hi, lo;
-                        if constexpr (KS != GINT_SHAPE_ANY) {
+                        constexpr int SH = decltype(shp)::value;
+                        if constexpr (SH != GINT_SHAPE_ANY) {
                             // padding rows reach only output rows or columns
                             // beyond the orbital count, which are never stored
-                            if (mu >= ChanShape<KS>::norb) return;
+                            if (mu >= ChanShape<SH>::norb) return;
                             S::split_mix(v, hi, lo);
                         } else {
                             S::split(v, hi, lo);
@@ -603,6 +605,43 @@ __device__ inline float load_dsym16_row(const GDev &P, CPair &pr, const double *
 constexpr int RSTR = 72;   // 16-bit elements per point row of the B tile (4 slots x 16 + 8)
 constexpr int FSTR = 65;   // floats per point row of the FP32 psi tile
 
+// One (point, slot) row of the B tile for a fixed channel layout: the
+// orbital indices are compile-time constants, so the 16 hi and 16 lo values
+// are gathered in registers (orbitals arrive in increasing order, so a pair
+// completes at each odd index) and written with 16-byte stores.  With
+// 144-byte point rows each 16 lanes of such a store hit distinct banks;
+// 2-byte stores conflict 4-way.
+template <class T, int SH>
+__device__ __attribute__((always_inline)) inline void stage_b16_rows(CSpecies &sp, const float *tab, const Disp &d,
+                                                                     float sphi, T *h0, T *h1) {
+    u4v hv[2], lv[2];
+    float pend = 0.f;
+    eval32<SH>(sp, tab, d.x, d.y, d.z, d.kn, sphi, [&](int mu, float v) {
+        if constexpr (Split16<T>::pairs) {
+            if (mu & 1) {
+                unsigned h2, l2;
+                Split16<T>::split2(pend, v, h2, l2);
+                hv[mu >> 3][(mu & 7) >> 1] = h2;
+                lv[mu >> 3][(mu & 7) >> 1] = l2;
+            } else {
+                pend = v;
+            }
+        } else {
+            T hi, lo;
+            Split16<T>::split(v, hi, lo);
+            const unsigned sh = 16 * (mu & 1);
+            const unsigned hb = __builtin_bit_cast(unsigned short, hi), lb = __builtin_bit_cast(unsigned short, lo);
+            const int k = mu >> 3, e = (mu & 7) >> 1;
+            hv[k][e] = (mu & 1) ? (hv[k][e] | (hb << sh)) : hb;
+            lv[k][e] = (mu & 1) ? (lv[k][e] | (lb << sh)) : lb;
+        }
+    });
+    *(u4v *)h0 = hv[0];
+    *(u4v *)(h0 + 8) = hv[1];
+    *(u4v *)h1 = lv[0];
+    *(u4v *)(h1 + 8) = lv[1];
+}
+
 // Phase 1 of rho/force: B orbitals (scaled by sphi) as 16-bit hi/lo rows
 // [h][point][slot*16+mu]; A atoms only mark where they are active.  Returns
 // the displacement of A atom a_w from this lane's point r, which the
@@ -619,66 +658,28 @@ __device__ inline Disp stage_b16(const GDev &P, CPair &pr, const P3 &r, float sp
     const Disp db = disp_of(P, r, b, pr.shiftB);
     T *h0 = &tB[0][pt][w * 16];
     T *h1 = &tB[1][pt][w * 16];
-    if constexpr (KS != GINT_SHAPE_ANY) {
-        // fixed layout: the orbital indices are compile-time constants, so the
-        // 16 hi and 16 lo values are gathered in registers and written with
-        // 16-byte stores (with 144-byte point rows each 16 lanes of such a
-        // store hit distinct banks; 2-byte stores conflict 4-way)
-        // (orbitals are emitted in increasing order, so a pair completes at
-        // each odd index)
-        u4v hv[2], lv[2];
-        if (db.in) {
-            CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
-            float pend = 0.f;
-            eval32<KS>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
-                if constexpr (Split16<T>::pairs) {
-                    if (mu & 1) {
-                        unsigned h2, l2;
-                        Split16<T>::split2(pend, v, h2, l2);
-                        hv[mu >> 3][(mu & 7) >> 1] = h2;
-                        lv[mu >> 3][(mu & 7) >> 1] = l2;
-                    } else {
-                        pend = v;
-                    }
-                } else {
-                    T hi, lo;
-                    Split16<T>::split(v, hi, lo);
-                    const unsigned sh = 16 * (mu & 1);
-                    const unsigned hb = __builtin_bit_cast(unsigned short, hi), lb = __builtin_bit_cast(unsigned short, lo);
-                    const int k = mu >> 3, e = (mu & 7) >> 1;
-                    hv[k][e] = (mu & 1) ? (hv[k][e] | (hb << sh)) : hb;
-                    lv[k][e] = (mu & 1) ? (lv[k][e] | (lb << sh)) : lb;
-                }
-            });
-            bits |= 1u << (4 + w);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 2; ++k) {
-                hv[k] = (u4v){0u, 0u, 0u, 0u};
-                lv[k] = (u4v){0u, 0u, 0u, 0u};
-            }
-        }
-        *(u4v *)h0 = hv[0];
-        *(u4v *)(h0 + 8) = hv[1];
-        *(u4v *)h1 = lv[0];
-        *(u4v *)(h1 + 8) = lv[1];
-    } else if (db.in) {
+    if (db.in) {
         CSpecies &sp = cst(P.species)[cst(P.atoms)[b].species];
         with_shape<KS>(sp, [&](auto shp) {
-            eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
-                T hi, lo;
-                Split16<T>::split(v, hi, lo);
-                h0[mu] = hi;
-                h1[mu] = lo;
-            });
+            constexpr int SH = decltype(shp)::value;
+            if constexpr (SH != GINT_SHAPE_ANY) {
+                stage_b16_rows<T, SH>(sp, P.tab32, db, sphi, h0, h1);
+            } else {
+                eval32<SH>(sp, P.tab32, db.x, db.y, db.z, db.kn, sphi, [&](int mu, float v) {
+                    T hi, lo;
+                    Split16<T>::split(v, hi, lo);
+                    h0[mu] = hi;
+                    h1[mu] = lo;
+                });
+            }
         });
         bits |= 1u << (4 + w);
     } else {
-#pragma unroll
-        for (int mu = 0; mu < 16; ++mu) {
-            h0[mu] = (T)0.f;
-            h1[mu] = (T)0.f;
-        }
+        const u4v z = {0u, 0u, 0u, 0u};
+        *(u4v *)h0 = z;
+        *(u4v *)(h0 + 8) = z;
+        *(u4v *)h1 = z;
+        *(u4v *)(h1 + 8) = z;
     }
     if (bits) atomicOr(&maskpt[pt], bits);
     // activity per 16-point tile, packed in one word (tile t: bit 8t + slot for
