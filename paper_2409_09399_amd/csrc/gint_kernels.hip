@@ -232,39 +232,27 @@ __device__ inline unsigned or16(unsigned m) {
     return m;
 }
 
-// Phase 1: orbitals of the A atom (slot t>>6) and B atom at point t&63.
-// mode 0: A and B unscaled; mode 1: B scaled by w V_g; mode 2: B only, A
-// gets the activity bit only.
-template <int MODE, int KS>
-__device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
-                             double *phiA, double *phiB, unsigned *maskpt, unsigned *maskt = nullptr) {
+// Phase 1 of rho/force: orbitals of the B atom of slot w at point lane into
+// phiB; the A atom of slot w only marks where it is active (the per-point
+// phase evaluates it).
+template <int KS>
+__device__ inline void stage_b(const GDev &P, CPair &pr, const GBig &o, double *phiB, unsigned *maskpt,
+                               unsigned *maskt) {
     const int t = threadIdx.x;
     const int pt = t & 63, slot = wave_id();
     const Pt r = bigcell_point(P, o, pt);
     unsigned bits = 0;
     {
         const int a = pr.a[slot];
-        double *dst = phiA + pt * PSTR + slot * GINT_ORB;
         bool in = false;
-        double x = 0, y = 0, z = 0, r2 = 0;
         if (a >= 0) {
             const GAtom at = ldc(P.atoms + (a));
-            x = r.x - at.x - pr.shiftA[0];
-            y = r.y - at.y - pr.shiftA[1];
-            z = r.z - at.z - pr.shiftA[2];
-            r2 = x * x + y * y + z * z;
+            const double x = r.x - at.x - pr.shiftA[0];
+            const double y = r.y - at.y - pr.shiftA[1];
+            const double z = r.z - at.z - pr.shiftA[2];
+            const double r2 = x * x + y * y + z * z;
             CSpecies &sp = cst(P.species)[at.species];
             in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
-            if (MODE != 2) {
-                if (in)
-                    with_shape<KS>(sp, [&](auto shp) {
-                        eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, 1.0, dst);
-                    });
-                else
-                    zero16(dst);
-            }
-        } else if (MODE != 2) {
-            zero16(dst);
         }
         if (in) bits |= 1u << slot;
     }
@@ -290,28 +278,25 @@ __device__ inline void stage(const GDev &P, CPair &pr, const GBig &o, const doub
         const unsigned long long act = __ballot(in);
         if (in) {
             CSpecies &sp = cst(P.species)[species];
-            const double scale = (MODE == 1) ? P.w * V[r.g] : 1.0;
             with_shape<KS>(sp, [&](auto shp) {
-                eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, scale, dst);
+                eval_phi<decltype(shp)::value>(sp, P.tab, x, y, z, r2, 1.0, dst);
             });
             bits |= 1u << (4 + slot);
-        } else if (!maskt || ((act >> (pt & ~15)) & 0xFFFFull)) {
+        } else if ((act >> (pt & ~15)) & 0xFFFFull) {
             zero16(dst);
         }
     }
     if (bits) atomicOr(&maskpt[pt], bits);
-    if (maskt) {
-        // activity per 16-point tile, packed in one word (tile t: bit 8t + slot
-        // for A, 8t + 4 + slot for B) from the wave's ballots: one atomic per wave
-        const unsigned long long ba = __ballot((bits >> slot) & 1u), bb = __ballot(bits >> 4);
-        unsigned tw = 0;
+    // activity per 16-point tile, packed in one word (tile t: bit 8t + slot
+    // for A, 8t + 4 + slot for B) from the wave's ballots: one atomic per wave
+    const unsigned long long ba = __ballot((bits >> slot) & 1u), bb = __ballot(bits >> 4);
+    unsigned tw = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if ((ba >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + slot);
-            if ((bb >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + 4 + slot);
-        }
-        if (pt == 0 && tw) atomicOr(maskt, tw);
+    for (int q = 0; q < 4; ++q) {
+        if ((ba >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + slot);
+        if ((bb >> (16 * q)) & 0xFFFFull) tw |= 1u << (8 * q + 4 + slot);
     }
+    if (pt == 0 && tw) atomicOr(maskt, tw);
 }
 
 // Row atom i of D_sym as MFMA B operands: dw[j][s] holds
@@ -563,7 +548,7 @@ __global__ __launch_bounds__(256, 4) void k_rho(GDev P0, const double *__restric
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
-        stage<2, KS>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
+        stage_b<KS>(P, pr, o, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;
@@ -641,7 +626,7 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
         unsigned *mpt = maskpt[cur], *mt = &maskt[cur];
         const long long gl = bigcell_point(P, o, lane).g;
         const double vpt = V[gl];   // requested early: its latency overlaps the stage
-        stage<2, KS>(P, pr, o, nullptr, nullptr, phiB, mpt, mt);
+        stage_b<KS>(P, pr, o, phiB, mpt, mt);
         __syncthreads();
         // the other buffer was last read before the previous bigcell's final barrier
         if (threadIdx.x < GINT_BCPTS) maskpt[cur ^ 1][threadIdx.x] = 0u;

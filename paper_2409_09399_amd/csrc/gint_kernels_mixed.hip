@@ -801,8 +801,13 @@ __global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 5) void k_rho_mx(GD
                 const float *ps = psi + lane * FSTR + w * 16;
                 CSpecies &sp = cst(P.species)[cst(P.atoms)[aw].species];
                 with_shape<KS>(sp, [&](auto shp) {
-                    eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f,
-                                                 [&](int mu, float x) { v += x * ps[mu]; });
+                    constexpr int SH = decltype(shp)::value;
+                    eval32<SH>(sp, P.tab32, da.x, da.y, da.z, da.kn, 1.f, [&](int mu, float x) {
+                        // padding orbitals are zero: no psi read for them
+                        if constexpr (SH != GINT_SHAPE_ANY)
+                            if (mu >= ChanShape<SH>::norb) return;
+                        v += x * ps[mu];
+                    });
                 });
                 // each wave adds its atom's term: no LDS sum over the waves and
                 // no barrier for it, at the price of more (FP64) atomics
