@@ -465,12 +465,11 @@ __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const dou
         for (int t = 0; t < 8; ++t) {
             if (!(km[t] & (1u << i))) continue;
             const double a = phiA[row0 + 4 * t * PSTR + i * GINT_ORB];
-            double b[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) b[j] = phiB[row0 + 4 * t * PSTR + j * GINT_ORB];
+            // B operands only of atoms active in this k-step (their zeros are
+            // written only there)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
-                if (km[t] & (1u << (4 + j))) acc[j] = mfma64(a, b[j], acc[j]);
+                if (km[t] & (1u << (4 + j))) acc[j] = mfma64(a, phiB[row0 + 4 * t * PSTR + j * GINT_ORB], acc[j]);
         }
         __syncthreads();
     }
