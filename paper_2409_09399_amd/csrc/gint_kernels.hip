@@ -334,16 +334,16 @@ __device__ inline void psi_row(const double dw[4][4], const double *phiB, const 
         const unsigned gm = (__builtin_amdgcn_readfirstlane(*maskt) >> (8 * t)) & 0xFFu;
         if (!(gm & (1u << w))) continue;
         const double *base = phiB + (16 * t + (lane & 15)) * PSTR + (lane >> 4);
-        double src[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) src[j][s] = base[j * GINT_ORB + 4 * s];
+        // operands only of B atoms active on the tile (their zeros are written
+        // only there)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             if (!(gm & (1u << (4 + j)))) continue;
+            double src[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) c[t] = mfma64(src[j][s], dw[j][s], c[t]);
+            for (int s = 0; s < 4; ++s) src[s] = base[j * GINT_ORB + 4 * s];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c[t] = mfma64(src[s], dw[j][s], c[t]);
         }
     }
 }
