@@ -750,10 +750,12 @@ struct TileBuf {
 // ---------------------------------------------------------------------------
 // rho_g (Eq. 3), mixed precision: canonical pairs, weight 2 off the self
 // pair.  Wave w owns A atom slot w: psi by MFMA, then per point (lane)
-// phi_{a_w} . psi with phi evaluated on the fly.
+// phi_{a_w} . psi with phi evaluated on the fly.  The psi tile reuses the B
+// tile's LDS (19 KB a workgroup), so six workgroups fit a CU; the fixed-layout
+// instance is built for six (a few registers spill, still faster than five).
 // ---------------------------------------------------------------------------
 template <class T, int KS>
-__global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 5) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 6) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
