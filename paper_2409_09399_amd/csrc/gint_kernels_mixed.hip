@@ -752,10 +752,11 @@ struct TileBuf {
 // pair.  Wave w owns A atom slot w: psi by MFMA, then per point (lane)
 // phi_{a_w} . psi with phi evaluated on the fly.  The psi tile reuses the B
 // tile's LDS (19 KB a workgroup), so six workgroups fit a CU; the fixed-layout
-// instance is built for six (a few registers spill, still faster than five).
+// instance is built for six and the per-species one for five (a few
+// registers spill in each, still faster than one workgroup fewer).
 // ---------------------------------------------------------------------------
 template <class T, int KS>
-__global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 4 : 6) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
+__global__ __launch_bounds__(256, KS == GINT_SHAPE_ANY ? 5 : 6) void k_rho_mx(GDev P0, const double *__restrict__ D, double *__restrict__ rho0) {
     typedef typename Split16<T>::vec vec;
     __shared__ __attribute__((aligned(16))) unsigned char buf[TileBuf<T>::bytes];
     __shared__ unsigned maskpt[2][GINT_BCPTS];
