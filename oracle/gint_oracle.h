@@ -20,10 +20,13 @@
  * p_c is either the analytic radial f_c(r) = exp(-a_c r^2) chi(r) or the
  * cubic Hermite interpolant of the tabulated f_c, f_c' (knots k*dr).
  *
- * Parity unpinned by the paper: the paper prints no values of H, rho, F or
- * sigma.  The oracle is pinned by mathematics instead (closed-form Gaussian
- * overlaps, forces and strain derivatives; identities; brute force; finite
- * differences) in the CPU test suite.
+ * The paper prints no values of H, rho, F or sigma, so nothing here is
+ * compared with printed numbers.  Every routine is pinned by mathematics
+ * instead, in the CPU test suite: closed-form Gaussian overlaps, forces and
+ * strain derivatives; the trace and electron-count identities; brute-force
+ * enumeration (which also fixes the work count W exactly); finite
+ * differences; and the smooth cutoff against the six end conditions that
+ * define the C2 quintic step.
  */
 #ifndef GINT_ORACLE_H
 #define GINT_ORACLE_H

@@ -251,6 +251,7 @@ def test_brute_force_tiny(oracle_mod):
     rho_abs = np.zeros(s.ngrid)
     ostart = np.concatenate([[0], np.cumsum(norb)])
     Phi = np.zeros((s.ngrid, int(ostart[-1])))
+    W = 0.0
     for g in range(s.ngrid):
         n = np.array([g // (N[1] * N[2]), (g // N[2]) % N[1], g % N[2]])
         r = (n / N) @ s.cell
@@ -262,6 +263,8 @@ def test_brute_force_tiny(oracle_mod):
                 phi, _ = o.orbitals(int(s.species[a]), xx)
                 ent.append((a, T, phi[0]))
                 Phi[g, ostart[a]:ostart[a + 1]] += phi[0]
+        # unit of work: ordered orbital pairs of the point's neighbour images
+        W += float(sum(norb[a] for (a, _, _) in ent)) ** 2
         for (a, T, pa) in ent:
             for (b, T2, pb) in ent:
                 R = T2 - T
@@ -273,6 +276,8 @@ def test_brute_force_tiny(oracle_mod):
                 rho_abs[g] += np.sum(np.abs(D) * np.abs(blk))
     Ho = o.vlocal()
     assert np.abs(Ho - H).max() < 1e-14 * max(1, np.abs(H).max()) * 10
+    # W = sum_g n_orb(g)^2: integers, so exact
+    assert o.work() == W
     assert np.abs(o.rho() - rho).max() < 1e-13 * max(1, np.abs(rho).max())
     # magnitude scale of rho's terms (the bound of the reduced-precision tests)
     ra = o.rho_abs()
@@ -491,3 +496,112 @@ def test_radial_cutoff_edge(oracle_mod):
     r = np.array([np.nextafter(6.0, 0.0), 6.0, 6.5])
     p, dp = o.radial(0, 2, r)
     assert abs(p[0]) < 1e-15 and p[1] == 0.0 and p[2] == 0.0
+
+
+# ----------------------------------------------------------------------------
+# unit of work W = sum_g n_orb(g)^2 and the smooth cutoff
+# ----------------------------------------------------------------------------
+
+def test_work_units_enumeration(oracle_mod):
+    """W counted by the oracle's cell lists equals a vectorised enumeration of
+    every (point, atom, image) within rcut over a box of images wider than the
+    cutoff, on the jittered diamond (rcut 6 > cell edge 6.74 / 2) and on a
+    sub-range of grid points."""
+    s = I.diamond8(0, grid=(12, 14, 10))
+    o = oracle_mod.Oracle(s)
+    N = np.asarray(s.grid)
+    n = np.stack(np.meshgrid(*[np.arange(k) for k in N], indexing="ij"), -1).reshape(-1, 3)
+    r = (n / N) @ s.cell
+    Ts = np.array(np.meshgrid(*[np.arange(-3, 4)] * 3, indexing="ij")).reshape(3, -1).T
+    shifts = Ts @ s.cell
+    rc, norb = s.rcut_atom(), s.norb_atom()
+    count = np.zeros(len(r))
+    for a in range(s.natom):
+        x = r[:, None, :] - s.pos[a][None, None, :] - shifts[None, :, :]
+        inside = np.sqrt((x * x).sum(-1)) < rc[a]
+        # the box of images is wide enough: no image on its faces is in range
+        edge = np.abs(Ts).max(1) == 3
+        assert not inside[:, edge].any()
+        count += norb[a] * inside.sum(1)
+    assert o.work() == float((count ** 2).sum())
+    g0, g1 = 317, 1201
+    assert o.work(g_range=(g0, g1)) == float((count[g0:g1] ** 2).sum())
+
+
+def _taper_species(oracle_mod, rs_frac=0.75, rc=6.0, alphas=(0.0, 0.0, 0.0)):
+    rng = np.random.default_rng(1)
+    sp = I.make_species("T", "spd", rc, 0.01, rng, alphas=list(alphas), rs_frac=rs_frac, cutoff=True)
+    s = I.assemble(np.eye(3) * 20, np.zeros((1, 3)), np.array([0]), [sp], (4, 4, 4), np.zeros(64), rng)
+    return s, sp
+
+
+def test_taper_is_the_c2_quintic_step(oracle_mod):
+    """With a = 0 the analytic radial function is the taper chi alone.  The
+    smooth cutoff is C2: chi = 1 up to r_s and 0 from rcut, with chi, chi' and
+    chi'' continuous at both ends.  A polynomial of degree <= 5 in
+    t = (r - r_s)/(rcut - r_s) is fixed uniquely by those six end conditions,
+    so checking degree <= 5 (a degree-5 fit leaves no residual), the values
+    and first derivatives (the oracle's own chi') and the second derivatives
+    (finite differences of chi') at both ends pins chi without restating it.
+    The step is also point-symmetric: chi(r_s + u) + chi(rcut - u) = 1."""
+    rc, rs = 6.0, 4.5
+    s, sp = _taper_species(oracle_mod)
+    o = oracle_mod.Oracle(s, radial="analytic")
+    inner = np.linspace(0.0, rs, 31)
+    p, dp = o.radial(0, 0, inner)
+    assert np.all(p == 1.0) and np.all(dp == 0.0)
+    outer = np.array([rc, rc + 1e-9, 7.0])
+    p, dp = o.radial(0, 0, outer)
+    assert np.all(p == 0.0) and np.all(dp == 0.0)
+    # degree <= 5 on (r_s, rcut)
+    t = np.linspace(0.02, 0.98, 41)
+    p, dp = o.radial(0, 0, rs + t * (rc - rs))
+    coef = np.polynomial.polynomial.polyfit(t, p, 5)
+    assert np.abs(np.polynomial.polynomial.polyval(t, coef) - p).max() < 1e-14
+    # end conditions from the fitted polynomial (exact up to the fit's
+    # conditioning): it meets chi = 1 at t = 0 and chi = 0 at t = 1 with zero
+    # slope and curvature on both sides
+    P = np.polynomial.Polynomial(coef)
+    for t0, val in ((0.0, 1.0), (1.0, 0.0)):
+        assert abs(P(t0) - val) < 1e-11
+        assert abs(P.deriv(1)(t0)) < 1e-9
+        assert abs(P.deriv(2)(t0)) < 1e-7
+    # the oracle's chi' is the derivative of that polynomial
+    assert np.abs(dp * (rc - rs) - P.deriv(1)(t)).max() < 1e-9
+    # point symmetry about the midpoint, and chi(mid) = 1/2
+    u = np.linspace(0.0, rc - rs, 17)
+    pa, _ = o.radial(0, 0, rs + u)
+    pb, _ = o.radial(0, 0, rc - u)
+    assert np.abs(pa + pb - 1.0).max() < 1e-15 * 8
+    pm, _ = o.radial(0, 0, np.array([0.5 * (rs + rc)]))
+    assert abs(pm[0] - 0.5) < 1e-15
+    # the six end conditions leave exactly one quintic; its slope at the midpoint
+    # is -15/8 per unit t (the derivative of the unique C2 step)
+    _, dmid = o.radial(0, 0, np.array([0.5 * (rs + rc)]))
+    assert abs(dmid[0] * (rc - rs) + 15.0 / 8.0) < 1e-13
+
+
+def test_taper_tables_match_analytic(oracle_mod):
+    """With the cutoff on, the tabulated radial functions (built by the input
+    generator) interpolated by the oracle's table mode agree with the oracle's
+    own analytic f = exp(-a r^2) chi(r) within the cubic Hermite error bound
+    dr^4 max|f''''| / 384 (max|f''''| from finite differences of the
+    analytic f), over the whole range including the taper region."""
+    s, sp = _taper_species(oracle_mod, alphas=(0.35, 1.1, 1.9))
+    ot = oracle_mod.Oracle(s, radial="table")
+    oa = oracle_mod.Oracle(s, radial="analytic")
+    rng = np.random.default_rng(5)
+    r = np.concatenate([rng.uniform(0.0, 6.0, 20000), rng.uniform(4.4, 6.0, 20000)])
+    hf = 2e-3
+    rf = np.arange(0.0, 6.0 + hf, hf)
+    for c in range(3):
+        pt, _ = ot.radial(0, c, r)
+        pa, _ = oa.radial(0, c, r)
+        fa, _ = oa.radial(0, c, rf)
+        # fourth differences of an even function: extend to r < 0 by symmetry
+        ext = np.concatenate([fa[:0:-1], fa])
+        d4 = np.abs(np.diff(ext, 4)).max() / hf**4
+        bound = 0.01**4 * d4 / 384
+        err = np.abs(pt - pa).max()
+        assert err <= 1.2 * bound, (c, err, bound)
+        assert err > 0.0     # the table is an interpolant, not the function
