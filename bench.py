@@ -4,30 +4,33 @@ One step = gint_vlocal + gint_rho + gint_force_stress (Eq. 2-5), the three
 calls a DFT code makes (rho comes first in a self-consistent step, V is built
 from it, and the force uses that V).  The fused gint_rho_force_stress (rho
 and the force from one pass, for callers that hold V and D together) is
-timed once and reported beside the step, not in it.  Default
-workload: the 868-atom twisted bilayer graphene slab (commensurate i = 8,
-3.89 deg, 312 x 312 x 120 grid, 13 orbitals per C, rcut 8 Bohr).  Inputs are
-synthetic and already resident in HBM when the timed region starts; the plan
+timed once and reported beside the step, not in it.  Default workload: the
+868-atom twisted bilayer graphene slab (commensurate i = 8, 3.89 deg,
+312 x 312 x 120 grid, 13 orbitals per C, rcut 8 Bohr).  Inputs are synthetic
+and already resident in HBM when the timed region starts; the plan
 (neighbour lists and work items) is built once per geometry, outside the
 timed region, and its build time is reported separately.
 
 The metric compares the mixed-precision form with the plain FP64 path on the
 same workload: `value` is the throughput of the form named by --precision
-(default fp16x3), and the line carries the FP64 path's throughput and the
-speedup over it (--compare fp64, the default).  The errors of each form
-against the FP64 oracle are measured by the GPU tests.
+(default fp16x3); the line carries the FP64 path's throughput, the speedup
+over it, and the largest differences between the two forms' outputs in this
+run (H, rho, F, sigma, E), which is the "stated error" of the metric (the
+FP64 path itself matches the oracle to 1e-11, checked by the GPU tests).
 
 Throughput: W / t_step with W = sum_g n_orb(g)^2 (grid points x ordered
 orbital pairs within rcut), counted exactly by the library.  Prints one JSON
-line.  --config 3 runs the batch of 64 random C/H/O crystals in one plan;
---graph replays a captured HIP graph of the step; --autotune picks the tile
-shape by timed trials first.
+line.  Besides the default workload the line carries (unless --no-extra)
+records of the 10,444-atom bilayer (both forms) and of the batch of 64 random
+C/H/O crystals in one plan (graph replay, autotuned tile shape), each with
+its own steps, timings, W and roofline.
 """
 from __future__ import annotations
 
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -36,43 +39,73 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_FP64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
-PEAK_FP16_TFLOPS = 2500.0  # MI355X dense FP16 / BF16 matrix
+# MI355X datasheet peaks (dense)
+PEAK_FP64_TFLOPS = 78.6      # FP64 matrix (and vector)
+PEAK_FP16_TFLOPS = 2500.0    # FP16 / BF16 matrix
+PEAK_HBM_GBS = 8000.0
 PRECISIONS = {"fp64": 0, "fp16x3": 1, "bf16x3": 2}
 DTYPES = {0: "f64", 1: "f16x3 (f32 acc)", 2: "bf16x3 (f32 acc)"}
 UNIT = "grid-pts*orbital-pairs/s"
+CLOCK_GHZ = 2.4
+N_CU = 256
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(system, target_seconds: float = 15.0):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(system, target_seconds: float = 15.0, single_seconds: float = 5.0):
     """The FP64 oracle (as it stands) on a slab of the same workload's grid
     points: Vlocal + rho + force/stress restricted to a contiguous range of
-    flat grid indices (whole n1-planes near the middle of the cell)."""
+    flat grid indices (whole n1-planes near the middle of the cell), on all
+    host threads, then on one thread over a smaller slab for a per-core rate."""
     from oracle import oracle as orc
     o = orc.Oracle(system)
     plane = int(system.grid[1]) * int(system.grid[2])
     n1 = int(system.grid[0])
     g0 = (n1 // 2) * plane
-    # calibrate on one plane, then size the slab to the target time
-    t = time.perf_counter()
-    o.vlocal(g_range=(g0, g0 + plane))
-    o.rho(g_range=(g0, g0 + plane))
-    o.force_stress(g_range=(g0, g0 + plane))
-    dt1 = time.perf_counter() - t
+
+    def timed(g1):
+        t = time.perf_counter()
+        o.vlocal(g_range=(g0, g1))
+        o.rho(g_range=(g0, g1))
+        o.force_stress(g_range=(g0, g1))
+        return time.perf_counter() - t
+
+    nthreads = orc.num_threads()
+    dt1 = timed(g0 + plane)                      # calibration: one plane
     nplanes = int(max(1, min(n1 // 2, round(target_seconds / max(dt1, 1e-3)))))
     g1 = g0 + nplanes * plane
     ws = o.work((g0, g1))
-    t = time.perf_counter()
-    o.vlocal(g_range=(g0, g1))
-    o.rho(g_range=(g0, g1))
-    o.force_stress(g_range=(g0, g1))
-    dt = time.perf_counter() - t
-    return {"value": ws / dt, "unit": UNIT, "cores": orc.num_threads(), "kind": "oracle",
+    dt = timed(g1)
+    # one thread: a slab of whole rows within one plane, sized to single_seconds
+    orc.set_num_threads(1)
+    try:
+        row = int(system.grid[2])
+        rows = int(max(1, min(int(system.grid[1]), round(single_seconds / max(dt1 * nthreads, 1e-3)
+                                                          * int(system.grid[1])))))
+        gs1 = g0 + rows * row
+        ws1 = o.work((g0, gs1))
+        dts = timed(gs1)
+    finally:
+        orc.set_num_threads(nthreads)
+    return {"value": ws / dt, "unit": UNIT, "cores": nthreads, "kind": "oracle",
             "sample": f"{system.name}: Vlocal+rho+force/stress over grid planes n1={n1 // 2}.."
-                      f"{n1 // 2 + nplanes - 1} ({nplanes} of {n1} planes, W_sample={ws:.4g}, {dt:.1f} s)"}
+                      f"{n1 // 2 + nplanes - 1} ({nplanes} of {n1} planes, W_sample={ws:.4g}, {dt:.1f} s)",
+            "single_thread": {"value": ws1 / dts, "unit": UNIT, "cores": 1,
+                              "sample": f"{rows} rows of plane n1={n1 // 2} (W_sample={ws1:.4g}, {dts:.1f} s)"},
+            "cpu_model": cpu_model()}
 
 
 def workload_name(cfg, systems):
@@ -87,20 +120,33 @@ def workload_name(cfg, systems):
             f"13 orbitals/atom, rcut 8 Bohr")
 
 
-def run_form(G, torch, dev, systems, prec, args, bufs):
-    """Plan, warm up and time one precision form; returns its measurements."""
+def alloc(torch, dev, systems):
+    natom = sum(x.natom for x in systems)
+    ngrid = sum(x.ngrid for x in systems)
+    nnz = sum(x.nnz for x in systems)
+    n = len(systems)
+
+    def e(k):
+        return torch.empty(k, dtype=torch.float64, device=dev)
+    return {"h": e(nnz), "rho": e(ngrid), "ne": e(n), "F": e(3 * natom), "sig": e(9 * n), "E": e(n), "W": e(n)}
+
+
+def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, autotune=False, tune_seconds=2.0,
+             opts=None):
+    """Plan, warm up and time one precision form; returns its measurements.
+    Outputs stay in `out` (the last step's results)."""
     target = systems if len(systems) > 1 else systems[0]
     tune = None
-    opts = dict(cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells)
-    if args.autotune:
-        chosen, tune = G.autotune(target, precision=prec, budget_seconds=args.tune_seconds)
+    opts = dict(opts or {})
+    if autotune:
+        chosen, tune = G.autotune(target, precision=prec, budget_seconds=tune_seconds)
         opts = dict(cluster_atoms=chosen["cluster_atoms"], max_bigcells_per_item=chosen["max_bigcells_per_item"])
         log(f"[bench] autotune {DTYPES[prec]}: {opts} {tune}")
     t = time.perf_counter()
     plan = G.Plan(target, precision=prec, **opts)
     plan_s = time.perf_counter() - t
     log(f"[bench] plan {DTYPES[prec]} {plan.info()} wall {plan_s:.2f} s")
-    v, d, h, rho, ne, F, sig, E, Wt = (bufs[k] for k in ("v", "d", "h", "rho", "ne", "F", "sig", "E", "W"))
+    h, rho, ne, F, sig, E, Wt = (out[k] for k in ("h", "rho", "ne", "F", "sig", "E", "W"))
     G.gint_work_units(plan, Wt)
     torch.cuda.synchronize()
     W = float(Wt.cpu().sum())
@@ -119,57 +165,59 @@ def run_form(G, torch, dev, systems, prec, args, bufs):
         if ev is not None:
             ev[3].record(stream)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    # the fused rho + force pass, once (reported, not part of the timed step)
+    # the fused rho + force pass, once (reported, not part of the timed step);
+    # the step after it restores rho
     fev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    G.gint_rho_force_stress(plan, v, d, rho, F, sig, n_elec=ne, energy=E)
     fev[0].record(stream)
     G.gint_rho_force_stress(plan, v, d, rho, F, sig, n_elec=ne, energy=E)
     fev[1].record(stream)
     torch.cuda.synchronize()
     fused_ms = fev[0].elapsed_time(fev[1])
     # per-kernel durations: HIP events on the stream the library launches on
-    if args.graph:
-        graph = G.Graph(plan, v_loc=v, d_vals=d, h_vals=h, rho=rho, n_elec=ne, force=F, stress=sig, energy=E)
-        graph.launch()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    if graph:
+        g = G.Graph(plan, v_loc=v, d_vals=d, h_vals=h, rho=rho, n_elec=ne, force=F, stress=sig, energy=E)
+        g.launch()
         torch.cuda.synchronize()
-        kev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        step(kev)
+        for k in range(steps):       # eager steps for the per-kernel split
+            step(evs[k])
         torch.cuda.synchronize()
-        kern_ms = {"vlocal": kev[0].elapsed_time(kev[1]), "rho": kev[1].elapsed_time(kev[2]),
-                   "force_stress": kev[2].elapsed_time(kev[3])}
         t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.launch()
+        for _ in range(steps):
+            g.launch()
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        graph.close()
+        g.close()
     else:
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for k in range(args.steps):
+        for k in range(steps):
             step(evs[k])
         torch.cuda.synchronize()
         elapsed = time.perf_counter() - t0
-        ms = {"vlocal": [], "rho": [], "force_stress": []}
-        for e in evs:
-            ms["vlocal"].append(e[0].elapsed_time(e[1]))
-            ms["rho"].append(e[1].elapsed_time(e[2]))
-            ms["force_stress"].append(e[2].elapsed_time(e[3]))
-        kern_ms = {k: float(np.mean(x)) for k, x in ms.items()}
+    ms = {"vlocal": [], "rho": [], "force_stress": []}
+    for e in evs:
+        ms["vlocal"].append(e[0].elapsed_time(e[1]))
+        ms["rho"].append(e[1].elapsed_time(e[2]))
+        ms["force_stress"].append(e[2].elapsed_time(e[3]))
+    kern_ms = {k: float(np.mean(x)) for k, x in ms.items()}
     log(f"[bench] {DTYPES[prec]} per-call ms {kern_ms} (fused rho+force {fused_ms:.2f} ms), "
-        f"step {elapsed / args.steps * 1e3:.2f} ms")
+        f"step {elapsed / steps * 1e3:.2f} ms{' (graph)' if graph else ''}")
     plan.close()
-    return {"value": W * args.steps / elapsed, "ms_per_step": elapsed / args.steps * 1e3, "kernel_ms": kern_ms,
-            "fused_rho_force_stress_ms": fused_ms, "W": W, "plan_seconds": plan_s, "options": opts, "autotune": tune}
+    return {"value": W * steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "kernel_ms": kern_ms,
+            "fused_rho_force_stress_ms": fused_ms, "W": W, "plan_seconds": plan_s, "options": opts,
+            "autotune": tune, "steps": steps, "warmup": warmup, "graph": graph}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "gint_tbg868_counters.md")
 KERNEL_NAMES = {0: {"vlocal": "k_vlocal", "rho": "k_rho", "force_stress": "k_force<false>"},
                 1: {"vlocal": "k_vlocal_mx<fp16>", "rho": "k_rho_mx<fp16>", "force_stress": "k_force_mx<fp16,false>"},
                 2: {"vlocal": "k_vlocal_mx<bf16>", "rho": "k_rho_mx<bf16>", "force_stress": "k_force_mx<bf16,false>"}}
+# flops per MFMA instruction of each form's contraction
+MFMA_FLOPS = {0: 2 * 16 * 16 * 4, 1: 2 * 16 * 16 * 32, 2: 2 * 16 * 16 * 32}
 
 
 def sources_sha256(prec):
@@ -185,11 +233,12 @@ def sources_sha256(prec):
     return h.hexdigest()
 
 
-def profiled_traffic(cfg, prec, key):
-    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
-    summary of the bilayer workload (FETCH_SIZE and WRITE_SIZE calibrated
-    with a plain copy), or None when the workload differs, the kernel was not
-    profiled, or its sources changed since the counters were taken."""
+def profiled_counters(cfg, prec, key):
+    """Per-launch counters of a kernel from the committed rocprofv3 summary
+    of the bilayer workload (HBM bytes from FETCH_SIZE and WRITE_SIZE
+    calibrated with a plain copy; instruction counts), or None when the
+    workload differs, the kernel was not profiled, or its sources changed
+    since the counters were taken."""
     import re
     if cfg != 2 or not os.path.exists(PROFILE):
         return None
@@ -200,18 +249,79 @@ def profiled_traffic(cfg, prec, key):
     name, sha = KERNEL_NAMES[prec].get(key), sources_sha256(prec)
     for r in json.loads(m.group(1)):
         if r["kernel"] == name and r.get("sources_sha256") == sha:
-            return r["read_bytes"] + r["write_bytes"]
+            return r
     return None
 
 
-def roofline(form, prec, cfg):
-    # dominant kernel against its contraction roofline: 2 flops per unit of W
+def roofline(form, prec, cfg, peaks):
+    """Dominant kernel against its contraction roofline: the algorithmic work
+    is 2 flops per unit of W (the per-point dot products and the orbital
+    evaluation are not counted), at the MFMA peak of the form's dtype, both
+    the datasheet figure and the rate measured on this device.  When the
+    committed counter profile matches the kernel sources: HBM traffic, the
+    executed MFMA rate and the VALU issue fraction, which say what limits it."""
     km = form["kernel_ms"]
     dom = max(km, key=km.get)
     peak = PEAK_FP64_TFLOPS if prec == 0 else PEAK_FP16_TFLOPS
-    achieved = 2.0 * form["W"] / (km[dom] * 1e-3) / 1e12
-    return {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": profiled_traffic(cfg, prec, dom)}
+    measured = None
+    if peaks:
+        measured = peaks["mfma_f64"] if prec == 0 else peaks["mfma_f16"]
+    t = km[dom] * 1e-3
+    achieved = 2.0 * form["W"] / t / 1e12
+    r = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+         "frac": achieved / peak, "peak_measured": measured,
+         "frac_measured": (achieved / measured) if measured else None,
+         "algorithmic_flops": 2.0 * form["W"], "duration_ms": km[dom], "traffic": None}
+    c = profiled_counters(cfg, prec, dom)
+    if c:
+        traffic = c["read_bytes"] + c["write_bytes"]
+        r["traffic"] = traffic
+        r["hbm_GBs"] = traffic / t / 1e9
+        r["hbm_frac"] = r["hbm_GBs"] / PEAK_HBM_GBS
+        if c.get("mfma_insts"):
+            ex = c["mfma_insts"] * MFMA_FLOPS[prec] / t / 1e12
+            r["executed_mfma_tflops"] = ex
+            r["executed_mfma_frac"] = ex / peak
+        if c.get("valu_insts"):
+            # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
+            issue = c["valu_insts"] * 4.0 / (N_CU * 4 * CLOCK_GHZ * 1e9 * t)
+            r["valu_issue_frac"] = issue
+            r["limiter"] = "valu" if issue > 0.5 else "latency"
+    return r
+
+
+def compare_outputs(a, b, systems):
+    """Largest differences of form a's outputs from form b's (same workload)."""
+    def mx(x):
+        return float(x.abs().max())
+    e = {"H_abs": mx(a["h"] - b["h"]), "F_abs": mx(a["F"] - b["F"]),
+         "rho_rel": mx(a["rho"] - b["rho"]) / mx(b["rho"]),
+         "sigma_rel": mx(a["sig"] - b["sig"]) / mx(b["sig"]),
+         "E_rel": mx(a["E"] - b["E"]) / mx(b["E"]),
+         "N_e_rel": mx(a["ne"] - b["ne"]) / mx(b["ne"])}
+    return e
+
+
+def extra_record(G, torch, dev, name, systems, forms, steps, warmup, graph=False, autotune=False, peaks=None):
+    v = torch.tensor(np.concatenate([x.v for x in systems]), device=dev)
+    d = torch.tensor(np.concatenate([x.d for x in systems]), device=dev)
+    rec = {"workload": name, "natom": sum(x.natom for x in systems), "ngrid": sum(x.ngrid for x in systems),
+           "nnz": sum(x.nnz for x in systems), "n_sys": len(systems)}
+    outs = {}
+    for prec in forms:
+        out = alloc(torch, dev, systems)
+        f = run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=graph, autotune=autotune)
+        outs[prec] = out
+        rec[DTYPES[prec]] = {"value": f["value"], "unit": UNIT, "ms_per_step": f["ms_per_step"],
+                             "kernel_ms": f["kernel_ms"], "W": f["W"], "steps": steps, "warmup": warmup,
+                             "graph": graph, "plan_seconds": f["plan_seconds"], "plan_options": f["options"],
+                             "autotune": f["autotune"], "roofline": roofline(f, prec, 0, peaks)}
+    if len(forms) == 2:
+        rec["speedup"] = rec[DTYPES[forms[0]]]["value"] / rec[DTYPES[forms[1]]]["value"]
+        rec["error_vs_" + DTYPES[forms[1]]] = compare_outputs(outs[forms[0]], outs[forms[1]], systems)
+    del v, d, outs
+    torch.cuda.empty_cache()
+    return rec
 
 
 def main():
@@ -222,9 +332,12 @@ def main():
     ap.add_argument("--config", type=int, default=2, help="1 diamond, 2 bilayer (868 atoms), 3 batch of 64")
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp16x3")
     ap.add_argument("--compare", choices=sorted(PRECISIONS) + ["none"], default="fp64",
-                    help="second form timed on the same workload (speedup reported against it)")
+                    help="second form timed on the same workload (speedup and errors reported against it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the 10,444-atom and 64-crystal records")
+    ap.add_argument("--extra-steps", type=int, default=2)
     ap.add_argument("--cluster-atoms", type=int, default=0)
     ap.add_argument("--max-bigcells", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph of the step")
@@ -244,6 +357,8 @@ def main():
     from paper_2409_09399_amd import inputs as I
 
     dev = torch.device("cuda:0")
+    peaks = G.measure_peaks()
+    log(f"[bench] measured peaks (TFLOP/s): {peaks}")
     t = time.perf_counter()
     cfg = I.make_config(args.config)
     systems = cfg if isinstance(cfg, list) else [cfg]
@@ -253,15 +368,8 @@ def main():
     n = len(systems)
     log(f"[bench] inputs {n} system(s), first {systems[0].name}: natom={natom} ngrid={ngrid} nnz={nnz} "
         f"({time.perf_counter() - t:.1f} s)")
-    bufs = {"v": torch.tensor(np.concatenate([x.v for x in systems]), device=dev),
-            "d": torch.tensor(np.concatenate([x.d for x in systems]), device=dev),
-            "h": torch.empty(nnz, dtype=torch.float64, device=dev),
-            "rho": torch.empty(ngrid, dtype=torch.float64, device=dev),
-            "ne": torch.empty(n, dtype=torch.float64, device=dev),
-            "F": torch.empty(3 * natom, dtype=torch.float64, device=dev),
-            "sig": torch.empty(9 * n, dtype=torch.float64, device=dev),
-            "E": torch.empty(n, dtype=torch.float64, device=dev),
-            "W": torch.empty(n, dtype=torch.float64, device=dev)}
+    v = torch.tensor(np.concatenate([x.v for x in systems]), device=dev)
+    d = torch.tensor(np.concatenate([x.d for x in systems]), device=dev)
 
     if args.copy_bytes > 0:
         src = torch.ones(args.copy_bytes // 8, dtype=torch.float64, device=dev)
@@ -273,15 +381,41 @@ def main():
         del src, dst
 
     prec = PRECISIONS[args.precision]
-    main_form = run_form(G, torch, dev, systems, prec, args, bufs)
+    opts = dict(cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells)
+    out_main = alloc(torch, dev, systems)
+    main_form = run_form(G, torch, systems, prec, args.steps, args.warmup, v, d, out_main, graph=args.graph,
+                         autotune=args.autotune, tune_seconds=args.tune_seconds, opts=opts)
     cmp_form = None
     if args.compare not in ("none", args.precision):
         cmp_prec = PRECISIONS[args.compare]
-        c = run_form(G, torch, dev, systems, cmp_prec, args, bufs)
+        out_cmp = alloc(torch, dev, systems)
+        c = run_form(G, torch, systems, cmp_prec, args.steps, args.warmup, v, d, out_cmp, graph=args.graph,
+                     opts=opts)
         cmp_form = {"precision": args.compare, "dtype": DTYPES[cmp_prec], "value": c["value"],
                     "ms_per_step": c["ms_per_step"], "kernel_ms": c["kernel_ms"],
                     "fused_rho_force_stress_ms": c["fused_rho_force_stress_ms"],
-                    "roofline": roofline(c, cmp_prec, args.config), "plan_options": c["options"]}
+                    "roofline": roofline(c, cmp_prec, args.config, peaks), "plan_options": c["options"],
+                    "error_of_main_form": compare_outputs(out_main, out_cmp, systems)}
+        log(f"[bench] {args.precision} vs {args.compare}: {cmp_form['error_of_main_form']}")
+        del out_cmp
+    del v, d
+    torch.cuda.empty_cache()
+
+    extra = None
+    if not args.no_extra and args.config == 2:
+        extra = []
+        log("[bench] extra: 10,444-atom bilayer ...")
+        big = I.make_config(5)
+        extra.append(extra_record(G, torch, dev, workload_name(5, [big]), [big], [prec, 0], args.extra_steps, 1,
+                                  peaks=peaks))
+        del big
+        log(f"[bench] extra: {extra[-1]}")
+        log("[bench] extra: batch of 64 crystals (graph, autotuned) ...")
+        batch = I.make_config(3)
+        extra.append(extra_record(G, torch, dev, workload_name(3, batch), batch, [prec, 0], args.extra_steps, 1,
+                                  graph=True, autotune=True, peaks=peaks))
+        del batch
+        log(f"[bench] extra: {extra[-1]}")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -308,10 +442,13 @@ def main():
         "kernel_ms": main_form["kernel_ms"],
         "fused_rho_force_stress_ms": main_form["fused_rho_force_stress_ms"],
         "plan_seconds": main_form["plan_seconds"],
-        "roofline": roofline(main_form, prec, args.config),
+        "roofline": roofline(main_form, prec, args.config, peaks),
+        "measured_peaks_tflops": peaks,
         "compare": cmp_form,
         "speedup_vs_compare": (main_form["value"] / cmp_form["value"]) if cmp_form else None,
+        "error_vs_compare": cmp_form["error_of_main_form"] if cmp_form else None,
         "autotune": main_form["autotune"],
+        "extra": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -35,9 +35,14 @@
  *    default stream) and returns without synchronising.  Scalar outputs are
  *    device pointers so that no call forces a host round trip.
  *  - A plan is not thread-safe; separate plans are independent.
- *  - Errors: every function returns GINT_OK (0) or a negative code; on error
- *    the outputs are left untouched and no work is enqueued.  No exception,
- *    abort or exit crosses this interface.
+ *  - Errors: every function returns GINT_OK (0) or a negative code.  Every
+ *    argument check (null pointers, the current device against the plan's)
+ *    comes before any work is enqueued, so a call rejected with GINT_EINVAL
+ *    leaves its outputs untouched and enqueues nothing.  A call runs as a
+ *    few launches in order (clear the outputs, the persistent kernel, small
+ *    reductions); if a launch itself fails (GINT_EHIP), launches already
+ *    enqueued before it are not undone, so outputs may have been cleared.
+ *    No exception, abort or exit crosses this interface.
  */
 #ifndef GINT_H
 #define GINT_H
@@ -104,7 +109,9 @@ typedef struct {
     int precision;           /* GINT_FP64, GINT_MIXED_FP16X3 or GINT_MIXED_BF16X3 */
     int cluster_atoms;       /* atoms per cluster tile, 1..4 (0 = default 4) */
     int max_bigcells_per_item; /* work-item length cap (0 = default) */
-    int reserved[5];
+    int device_mib_cap;      /* device memory the plan may hold, in MiB (0 = no cap): a plan
+                                that needs more fails with GINT_ENOMEM before any HIP call */
+    int reserved[4];
 } gint_options;
 
 /* Sizes of a plan (host struct filled by gint_plan_query). */
@@ -188,6 +195,12 @@ int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_val
  * The plan's device must be current (else GINT_EINVAL). */
 int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, void *stream);
 
+/* E = w sum_g V_g rho_g per system (the energy of Eq. 4-5 for a given rho),
+ * reduced in FP64 on the device in a fixed order (deterministic).  v_loc,
+ * rho: device f64[N_g] (packed as for gint_rho); energy: device f64[n_sys],
+ * overwritten. */
+int gint_energy(gint_plan *p, const double *v_loc, const double *rho, double *energy, void *stream);
+
 /* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
  * the unit of work of the throughput metric, counted exactly from the plan's
  * neighbour lists.  w_out: device f64[n_sys], overwritten. */
@@ -214,7 +227,7 @@ int gint_graph_launch(gint_graph *g, void *stream);
 void gint_graph_destroy(gint_graph *g);
 
 /* Autotuner of the tile shape (paper: short timed trials pick the kernel
- * parameters, "Performance Evaluation").  Candidates of (cluster_atoms,
+ * parameters, "Device Performance Optimization").  Candidates of (cluster_atoms,
  * max_bigcells_per_item) are tried in a fixed order; for each a plan is
  * built and one full step (Vlocal, rho, force/stress on constant V and D in
  * scratch buffers the tuner allocates and frees) is timed with HIP events on

@@ -951,3 +951,12 @@ int oracle_work(const oracle_system *s, long g0, long g1, double *w_out)
 }
 
 int oracle_num_threads(void) { return nthreads_max(); }
+
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -93,6 +93,8 @@ int oracle_neighbours(const oracle_system *s, long g, int cap, int *atom, int *T
 int oracle_work(const oracle_system *s, long g_begin, long g_end, double *w_out);
 /* OpenMP threads the oracle uses. */
 int oracle_num_threads(void);
+/* Threads used by later calls (the OpenMP team size); n <= 0 is ignored. */
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -72,6 +72,8 @@ def _load():
         lib.oracle_work.argtypes = [P, C.c_long, C.c_long, P]
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = C.c_int
+        lib.oracle_set_num_threads.argtypes = [C.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -82,6 +84,10 @@ def _p(a: np.ndarray):
 
 def num_threads() -> int:
     return int(_load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    _load().oracle_set_num_threads(int(n))
 
 
 class Oracle:

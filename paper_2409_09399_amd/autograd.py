@@ -13,8 +13,13 @@ because E = sum_g w V_g rho_g equals L when V = g / w.  energy(V, D, tau,
 eps) = w0 sum_g V_g rho_g (w0 the unstrained volume per point) has
 dE/dV = w0 rho, dE/dD = H[V], dE/dtau = -F (1 + eps), dE/deps = Z (1 + eps)^-T.
 
-A plan (neighbour lists) is built for the geometry of each forward call;
-every numeric step runs in the HIP library.
+A plan (neighbour lists) is built for the geometry of a forward call and
+reused by later calls with the same system, positions, strain and precision
+(an SCF loop calls rho at fixed geometry); its host build time is kept in
+`last_plan_seconds`.  Plans are released when the last autograd context
+holding them goes away, not in backward, so backward can run more than once
+(retain_graph).  Every numeric step runs in the HIP library; the energy is
+the library's FP64 reduction w sum_g V_g rho_g (gint_energy).
 """
 from __future__ import annotations
 
@@ -24,6 +29,25 @@ import numpy as np
 import torch
 
 from . import gint as G
+
+
+_plan_cache = {}
+last_plan_seconds = 0.0
+
+
+def _plan_for(system, tau: torch.Tensor, eps: torch.Tensor, precision: int):
+    """Plan of the strained geometry; one cached entry, reused while the
+    system, positions, strain and precision are the same."""
+    global last_plan_seconds
+    s, M = _geometry(system, tau, eps)
+    key = (id(system), precision, s.pos.tobytes(), s.cell.tobytes())
+    hit = _plan_cache.get("entry")
+    if hit is not None and hit[0] == key and hit[1] is system:
+        return hit[2], M
+    plan = G.Plan(s, precision=precision)
+    last_plan_seconds = float(plan.sizes.build_seconds)
+    _plan_cache["entry"] = (key, system, plan)
+    return plan, M
 
 
 def _geometry(system, tau: torch.Tensor, eps: torch.Tensor):
@@ -53,8 +77,7 @@ def _adjoints(plan, v_like: torch.Tensor, d: torch.Tensor, need_d: bool, need_ge
 class GintRho(torch.autograd.Function):
     @staticmethod
     def forward(ctx, d, tau, eps, system, precision):
-        s, M = _geometry(system, tau, eps)
-        plan = G.Plan(s, precision=precision)
+        plan, M = _plan_for(system, tau, eps, precision)
         rho = torch.empty(plan.ngrid, dtype=torch.float64, device=d.device)
         G.gint_rho(plan, d.contiguous(), rho)
         ctx.plan = plan
@@ -79,19 +102,21 @@ class GintRho(torch.autograd.Function):
         if need_geo and ctx.needs_input_grad[2]:
             minv_t = torch.tensor(np.linalg.inv(ctx.M).T, dtype=torch.float64, device=gbar.device)
             geps = adj["Z"] @ minv_t
-        plan.close()
         return gd, gtau, geps, None, None
 
 
 class GintEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, v, d, tau, eps, system, precision):
-        s, M = _geometry(system, tau, eps)
-        plan = G.Plan(s, precision=precision)
+        plan, M = _plan_for(system, tau, eps, precision)
         rho = torch.empty(plan.ngrid, dtype=torch.float64, device=d.device)
         G.gint_rho(plan, d.contiguous(), rho)
         w0 = float(abs(np.linalg.det(np.asarray(system.cell, dtype=np.float64)))) / plan.ngrid
-        e = w0 * torch.dot(v.to(torch.float64), rho)
+        # the plan's w is the strained w0 det(M); V rescaled so that w V = w0 V
+        scale = w0 / (plan.volume / plan.ngrid)
+        e = torch.empty(1, dtype=torch.float64, device=d.device)
+        G.gint_energy(plan, (v.to(torch.float64) * scale).contiguous(), rho, e)
+        e = e[0]
         ctx.plan, ctx.M, ctx.w0 = plan, M, w0
         ctx.save_for_backward(v, d, rho)
         return e
@@ -114,7 +139,6 @@ class GintEnergy(torch.autograd.Function):
         if need_geo and ctx.needs_input_grad[3]:
             minv_t = torch.tensor(np.linalg.inv(ctx.M).T, dtype=torch.float64, device=ebar.device)
             geps = ebar * (adj["Z"] @ minv_t)
-        plan.close()
         return gv, gd, gtau, geps, None, None
 
 

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgint.so")
-SOURCES = ["gint_kernels.hip", "gint_kernels_mixed.hip", "gint_api.cpp", "gint_plan.cpp", "gint_tune.cpp"]
+SOURCES = ["gint_kernels.hip", "gint_kernels_mixed.hip", "gint_api.cpp", "gint_plan.cpp", "gint_tune.cpp",
+           "gint_peaks.hip"]
 ARCH = os.environ.get("GINT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -18,8 +18,8 @@ hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, do
                              hipStream_t s);
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s);
 hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double *D, double *out, hipStream_t s);
-hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
-                               hipStream_t s);
+hipError_t gint_launch_seg_sum(const GDev &P, const double *x, const double *y, double *part, int nparts,
+                               double *out, hipStream_t s);
 hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
                                      hipStream_t s);
 void gint_prime_grids_fp64();
@@ -65,6 +65,10 @@ int hip_fail(hipError_t e) {
     return GINT_EHIP;
 }
 
+// The plan's device must be current (its descriptors live there).  Checked
+// before anything is enqueued.
+int check_device(const gint_plan *p);
+
 template <class T>
 int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
     b.bytes = v.size() * sizeof(T);
@@ -93,6 +97,18 @@ void release(gint_plan *p) {
         }
 }
 
+int check_device(const gint_plan *p) {
+    int cur = 0;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e);
+    return cur == p->device ? GINT_OK : GINT_EINVAL;
+}
+
+template <class T>
+size_t upload_bytes(const std::vector<T> &v) {
+    return v.empty() ? sizeof(T) : v.size() * sizeof(T);
+}
+
 }  // namespace
 
 extern "C" {
@@ -114,6 +130,16 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     }
     if (rc != GINT_OK) return rc;
     if (hp.items_canon.size() > 0x7fffffffu || hp.items_ordered.size() > 0x7fffffffu) return GINT_ENOMEM;
+    // workspace: [0] work counter (an int in the first 4 bytes), [1] max |V|,
+    // then ZE, then partial sums
+    std::vector<double> wsinit(2 + (size_t)n_sys * (10 + kParts), 0.0);
+    if (opt && opt->device_mib_cap > 0) {
+        const size_t need = upload_bytes(hp.species) + upload_bytes(hp.atoms) + upload_bytes(hp.tab) +
+                            upload_bytes(hp.tab32) + upload_bytes(hp.pairs) + upload_bytes(hp.bigcells) +
+                            upload_bytes(hp.items_canon) + upload_bytes(hp.items_ordered) + upload_bytes(hp.sys) +
+                            upload_bytes(wsinit);
+        if (need > ((size_t)opt->device_mib_cap << 20)) return GINT_ENOMEM;
+    }
 
     gint_plan *p = new (std::nothrow) gint_plan();
     if (!p) return GINT_ENOMEM;
@@ -123,9 +149,6 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         return hip_fail(e);
     }
     size_t total = 0;
-    // workspace: [0] work counter (an int in the first 4 bytes), [1] max |V|,
-    // then ZE, then partial sums
-    std::vector<double> wsinit(2 + (size_t)n_sys * (10 + kParts), 0.0);
     if ((rc = upload(p->species, hp.species, total)) || (rc = upload(p->atoms, hp.atoms, total)) ||
         (rc = upload(p->tab, hp.tab, total)) || (rc = upload(p->tab32, hp.tab32, total)) ||
         (rc = upload(p->pairs, hp.pairs, total)) ||
@@ -203,6 +226,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
 
 int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream) {
     if (!p || !v_loc || !h_vals) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(h_vals, p->sizes.nnz, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
@@ -214,6 +238,7 @@ int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream)
 
 int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, void *stream) {
     if (!p || !d_vals || !rho) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
@@ -221,7 +246,7 @@ int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, vo
                                   : gint_launch_rho_mx(p->canon, p->precision, d_vals, rho, s);
     if (e != hipSuccess) return hip_fail(e);
     if (n_elec) {
-        e = gint_launch_seg_sum(p->canon, rho, p->part, kParts, n_elec, s);
+        e = gint_launch_seg_sum(p->canon, rho, nullptr, p->part, kParts, n_elec, s);
         if (e != hipSuccess) return hip_fail(e);
     }
     return GINT_OK;
@@ -232,6 +257,7 @@ namespace {
 // force/stress (and rho when given) in one pass over the ordered pairs
 int force_pass(gint_plan *p, const double *v_loc, const double *d_vals, double *rho, double *n_elec,
                double *force, double *stress, double *energy, hipStream_t s) {
+    if (const int rc = check_device(p)) return rc;
     hipError_t e = gint_launch_fill(force, 3LL * p->sizes.natom, 0.0, s);
     if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10LL * p->n_sys, 0.0, s);
     if (e == hipSuccess && rho) e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
@@ -240,7 +266,7 @@ int force_pass(gint_plan *p, const double *v_loc, const double *d_vals, double *
                 ? gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, rho, s)
                 : gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, rho, s);
     if (e == hipSuccess) e = gint_launch_finish_stress(p->ordered, p->ZE, stress, energy, s);
-    if (e == hipSuccess && rho && n_elec) e = gint_launch_seg_sum(p->canon, rho, p->part, kParts, n_elec, s);
+    if (e == hipSuccess && rho && n_elec) e = gint_launch_seg_sum(p->canon, rho, nullptr, p->part, kParts, n_elec, s);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }
@@ -259,14 +285,11 @@ int gint_rho_force_stress(gint_plan *p, const double *v_loc, const double *d_val
     return force_pass(p, v_loc, d_vals, rho, n_elec, force, stress, energy, (hipStream_t)stream);
 }
 
-// W = sum_g n_orb(g)^2, the unit of work of the throughput metric.
+// Largest |D_IJR[mu,nu] - D_JI(-R)[nu,mu]| per system.
 int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, void *stream) {
     if (!p || !d_vals || !max_asym) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
     hipStream_t s = (hipStream_t)stream;
-    int cur = 0;
-    hipError_t ge = hipGetDevice(&cur);
-    if (ge != hipSuccess) return hip_fail(ge);
-    if (cur != p->device) return GINT_EINVAL;
     if (!p->blocks.p && !p->blocks_host.empty()) {
         size_t total = 0;
         const int rc = upload(p->blocks, p->blocks_host, total);
@@ -283,8 +306,19 @@ int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, vo
     return GINT_OK;
 }
 
+// E = w sum_g V_g rho_g per system (two-pass device reduction).
+int gint_energy(gint_plan *p, const double *v_loc, const double *rho, double *energy, void *stream) {
+    if (!p || !v_loc || !rho || !energy) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
+    const hipError_t e = gint_launch_seg_sum(p->canon, v_loc, rho, p->part, kParts, energy, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return GINT_OK;
+}
+
+// W = sum_g n_orb(g)^2, the unit of work of the throughput metric.
 int gint_work_units(gint_plan *p, double *w_out, void *stream) {
     if (!p || !w_out) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(w_out, p->n_sys, 0.0, s);
     if (e == hipSuccess) e = gint_launch_work(p->canon, w_out, s);

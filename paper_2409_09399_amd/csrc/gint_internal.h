@@ -98,7 +98,7 @@ struct GDev {
     const GSpecies *species;
     const GAtom *atoms;
     const double *tab;           // interleaved radial tables
-    const float *tab32;          // the same tables rounded to FP32 by knot interval (mixed precision): [k][chan][f_k, f'_k, f_k+1, f'_k+1] at 2 tab_off
+    const float *tab32;          // the same interpolant in FP32 by knot interval (mixed precision): [k][chan][c0, c1, c2, c3], p = c0 + c1 t + c2 t^2 + c3 t^3, at 2 tab_off
     const GPair *pairs;
     const GBig *bigcells;
     const GItem *items;

@@ -772,16 +772,24 @@ __global__ __launch_bounds__(256) void k_dsym_check(const GBlk *__restrict__ blk
     }
 }
 
-// Per-system sums of w_s * x over each system's grid range (two passes,
-// deterministic): part[s * nparts + b] then out[s].
-__global__ __launch_bounds__(256) void k_seg_sum_partial(GDev P, const double *__restrict__ x, int nparts,
+// Per-system sums of w_s * x (or w_s * x * y when y is given) over each
+// system's grid range (two passes, deterministic): part[s * nparts + b] then
+// out[s].
+__global__ __launch_bounds__(256) void k_seg_sum_partial(GDev P, const double *__restrict__ x,
+                                                         const double *__restrict__ y, int nparts,
                                                          double *__restrict__ part) {
     __shared__ double red[256];
     CSys &S = cst(P.sys)[blockIdx.y];
     const long long n = (long long)S.N[0] * S.N[1] * S.N[2];
     const double *xs = x + S.g_off;
     double acc = 0.0;
-    for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += xs[i];
+    if (y) {
+        const double *ys = y + S.g_off;
+        for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+            acc += xs[i] * ys[i];
+    } else {
+        for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += (long long)gridDim.x * 256) acc += xs[i];
+    }
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int st = 128; st > 0; st >>= 1) {
@@ -915,9 +923,9 @@ hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double 
     return hipGetLastError();
 }
 
-hipError_t gint_launch_seg_sum(const GDev &P, const double *x, double *part, int nparts, double *out,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_seg_sum_partial, dim3(nparts, P.nsys), dim3(256), 0, s, P, x, nparts, part);
+hipError_t gint_launch_seg_sum(const GDev &P, const double *x, const double *y, double *part, int nparts,
+                               double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_seg_sum_partial, dim3(nparts, P.nsys), dim3(256), 0, s, P, x, y, nparts, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_seg_sum_final, dim3(P.nsys), dim3(256), 0, s, P, part, nparts, out);

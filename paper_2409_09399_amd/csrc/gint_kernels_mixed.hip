@@ -20,6 +20,7 @@ typedef double d4v __attribute__((ext_vector_type(4)));
 typedef _Float16 h8v __attribute__((ext_vector_type(8)));
 typedef __bf16 b8v __attribute__((ext_vector_type(8)));
 typedef unsigned u4v __attribute__((ext_vector_type(4)));
+typedef float flt4_t __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -117,11 +118,12 @@ __device__ inline P3 point_of(const GDev &P, const GBig &o, int pt) {
     return r;
 }
 
-// Cubic Hermite on the FP32 table: the interval record of knot k
-// ([chan][f_k, f'_k, f_k+1, f'_k+1], 16 bytes a channel) and the weights.
+// Cubic Hermite interpolant on the FP32 table: the interval record of knot k
+// ([chan][c0, c1, c2, c3], 16 bytes a channel, the cubic's coefficients in
+// t = r/dr - k) and t.
 struct Herm32 {
     const float *rec;
-    float h00, h10, h01, h11, d00, d10, d01, d11;
+    float t, inv_dr;
 };
 
 // Knot interval of radius r, found in FP64: with t = r / dr of order 10^3 an
@@ -141,41 +143,33 @@ __device__ inline Knot knot_of(CSpecies &sp, double r) {
 }
 
 __device__ __attribute__((always_inline)) inline Herm32 hermite32(CSpecies &sp, const float *tab, Knot kn) {
-    const int k = kn.k;
-    const float t = kn.t;
-    const float t2 = t * t, t3 = t2 * t, dr = (float)sp.dr, idr = (float)sp.inv_dr;
     Herm32 h;
-    h.rec = tab + 2 * (size_t)sp.tab_off + (size_t)k * sp.nchan * 4;
-    h.h00 = 2.f * t3 - 3.f * t2 + 1.f;
-    h.h10 = (t3 - 2.f * t2 + t) * dr;
-    h.h01 = 3.f * t2 - 2.f * t3;
-    h.h11 = (t3 - t2) * dr;
-    h.d00 = (6.f * t2 - 6.f * t) * idr;
-    h.d10 = 3.f * t2 - 4.f * t + 1.f;
-    h.d01 = -h.d00;
-    h.d11 = 3.f * t2 - 2.f * t;
+    h.rec = tab + 2 * (size_t)sp.tab_off + (size_t)kn.k * sp.nchan * 4;
+    h.t = kn.t;
+    h.inv_dr = (float)sp.inv_dr;
     return h;
 }
 
-// Table values (f, f') of up to RCH32 channels at knots k and k + 1, all
-// loads issued before any is used (a loop that loads as it goes waits one
-// memory round trip per channel).
+// p(t) and dp/dt of one channel's record by Horner's rule (no cancellation:
+// each term is of the size of the derivative it carries)
+__device__ inline float cubic_val(const flt4_t &c, float t) { return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x); }
+__device__ inline float cubic_dt(const flt4_t &c, float t) {
+    return fmaf(fmaf(3.f * c.w, t, 2.f * c.z), t, c.y);
+}
+
+// Coefficient records of up to RCH32 channels, all loads issued before any
+// is used (a loop that loads as it goes waits one memory round trip per
+// channel).
 constexpr int RCH32 = 5;
-typedef float flt2 __attribute__((ext_vector_type(2)));
-typedef float flt4 __attribute__((ext_vector_type(4)));
 
 struct Rows32 {
-    flt2 a[RCH32], b[RCH32];
+    flt4_t c[RCH32];
 };
 
 __device__ __attribute__((always_inline)) inline void load_rows32(const Herm32 &h, int nchan, int c0, Rows32 &R) {
 #pragma unroll
     for (int q = 0; q < RCH32; ++q)
-        if (c0 + q < nchan) {
-            const flt4 v = *(const flt4 *)(h.rec + 4 * (c0 + q));
-            R.a[q] = v.xy;
-            R.b[q] = v.zw;
-        }
+        if (c0 + q < nchan) R.c[q] = *(const flt4_t *)(h.rec + 4 * (c0 + q));
 }
 
 // phi_mu(x) * scale in FP32 for the 16 slots of one atom, handed to emit(mu, v),
@@ -198,7 +192,7 @@ __device__ __attribute__((always_inline)) inline void eval32_rows(CSpecies &sp, 
 #pragma unroll
         for (int q = 0; q < RCH32; ++q) {
             if (c0 + q >= nchan) break;
-            const float p = (h.h00 * R.a[q].x + h.h10 * R.a[q].y + h.h01 * R.b[q].x + h.h11 * R.b[q].y) * scale;
+            const float p = cubic_val(R.c[q], h.t) * scale;
             const int l = ChanShape<SHAPE>::l(sp, c0 + q);
             if (l == 0) {
                 emit(slot, p * kC0f);
@@ -237,6 +231,7 @@ __device__ __attribute__((always_inline)) inline void dot_grad32_rows(CSpecies &
                                        float inv_r, const float *psi, float &e, float G[3]) {
     e = 0.f;
     G[0] = G[1] = G[2] = 0.f;
+    const float dscale = h.inv_dr * inv_r;
     const int nchan = ChanShape<SHAPE>::nchan(sp);
     int slot = 0;
     for (int c0 = 0; c0 < nchan; c0 += RCH32) {
@@ -248,9 +243,8 @@ __device__ __attribute__((always_inline)) inline void dot_grad32_rows(CSpecies &
 #pragma unroll
       for (int qq = 0; qq < RCH32; ++qq) {
         if (c0 + qq >= nchan) break;
-        const float f0 = R.a[qq].x, fp0 = R.a[qq].y, f1 = R.b[qq].x, fp1 = R.b[qq].y;
-        const float p = h.h00 * f0 + h.h10 * fp0 + h.h01 * f1 + h.h11 * fp1;
-        const float q = (h.d00 * f0 + h.d10 * fp0 + h.d01 * f1 + h.d11 * fp1) * inv_r;
+        const float p = cubic_val(R.c[qq], h.t);
+        const float q = cubic_dt(R.c[qq], h.t) * dscale;   // p'(r) / r
         const int l = ChanShape<SHAPE>::l(sp, c0 + qq);
         float A, Bx, By, Bz;
         if (l == 0) {

@@ -232,24 +232,35 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         hp.species.push_back(g);
     }
     if (hp.tab.size() > (size_t)0x7fffffff) return fail(GINT_EINVAL, "radial tables too large");
-    // FP32 tables by knot interval: [interval k][chan][f_k, f'_k, f_k+1, f'_k+1],
+    // FP32 tables by knot interval: [interval k][chan][c0, c1, c2, c3], the
+    // coefficients of the same cubic Hermite interpolant as a polynomial in
+    // t = r/dr - k, p = c0 + c1 t + c2 t^2 + c3 t^3, computed in FP64 and
+    // rounded once.  In this form p' = (c1 + 2 c2 t + 3 c3 t^2)/dr has no
+    // cancellation: the weighted-knot form h00' f_k + h01' f_k+1 cancels two
+    // terms of size 6 f/dr, which in FP32 cost about 8 bits of the gradient.
     // 16-byte records, so one evaluation reads each channel with one 16-byte
     // load.  Twice the length of the FP64 table, so species s starts at
     // 2 tab_off (also after the batch merge); the record of the last knot
-    // (never an interval start) repeats that knot.
+    // (never an interval start) holds the constant f_k.
     hp.tab32.assign(2 * hp.tab.size(), 0.f);
     for (const GSpecies &g : hp.species) {
         const size_t C = (size_t)g.nchan, K = (size_t)g.nknots;
         const double *t = hp.tab.data() + g.tab_off;
         float *o = hp.tab32.data() + 2 * (size_t)g.tab_off;
         for (size_t k = 0; k < K; ++k) {
-            const size_t k1 = k + 1 < K ? k + 1 : k;
             for (size_t c = 0; c < C; ++c) {
                 float *r = o + (k * C + c) * 4;
-                r[0] = (float)t[(k * C + c) * 2];
-                r[1] = (float)t[(k * C + c) * 2 + 1];
-                r[2] = (float)t[(k1 * C + c) * 2];
-                r[3] = (float)t[(k1 * C + c) * 2 + 1];
+                const double f0 = t[(k * C + c) * 2], d0 = g.dr * t[(k * C + c) * 2 + 1];
+                if (k + 1 < K) {
+                    const double f1 = t[((k + 1) * C + c) * 2], d1 = g.dr * t[((k + 1) * C + c) * 2 + 1];
+                    r[0] = (float)f0;
+                    r[1] = (float)d0;
+                    r[2] = (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1);
+                    r[3] = (float)(2.0 * (f0 - f1) + d0 + d1);
+                } else {
+                    r[0] = (float)f0;
+                    r[1] = r[2] = r[3] = 0.f;
+                }
             }
         }
     }

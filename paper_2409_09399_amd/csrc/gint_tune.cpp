@@ -1,7 +1,7 @@
 // Autotuner of the plan's tile shape: atoms per cluster tile and work-item
 // length, chosen by timing one full pass (Vlocal + rho + force/stress) of
 // each candidate on the caller's device (paper: parameters tuned by short
-// timed trials before the production run, "Performance Evaluation").
+// timed trials before the production run, "Device Performance Optimization").
 #include <hip/hip_runtime.h>
 
 #include <chrono>

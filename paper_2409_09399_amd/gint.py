@@ -42,7 +42,7 @@ class gint_system(C.Structure):
 
 class gint_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("cluster_atoms", C.c_int), ("max_bigcells_per_item", C.c_int),
-                ("reserved", C.c_int * 5)]
+                ("device_mib_cap", C.c_int), ("reserved", C.c_int * 4)]
 
 
 class gint_sizes(C.Structure):
@@ -67,10 +67,10 @@ class gint_tune_report(C.Structure):
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
-            "gint_check_symmetry",
+            "gint_check_symmetry", "gint_energy",
             "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
-            "gint_last_hip_error"]
+            "gint_last_hip_error", "gint_peaks_measure"]
 
 
 def _hip_runtimes():
@@ -109,6 +109,8 @@ def _load():
     lib.gint_force_stress.argtypes = [P, P, P, P, P, P, P]
     lib.gint_rho_force_stress.argtypes = [P] * 9
     lib.gint_work_units.argtypes = [P, P, P]
+    lib.gint_energy.argtypes = [P, P, P, P, P]
+    lib.gint_peaks_measure.argtypes = [C.POINTER(C.c_double), P]
     lib.gint_check_symmetry.argtypes = [P, P, P, P]
     lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
     lib.gint_plan_query_system.argtypes = [P, C.c_int, C.POINTER(gint_system_sizes)]
@@ -210,12 +212,13 @@ class Plan:
     of system i are given by `systems[i]` (dicts of offsets and sizes)."""
 
     def __init__(self, system, cluster_atoms: int = 0, max_bigcells_per_item: int = 0,
-                 precision: int = GINT_FP64, stream=None):
+                 precision: int = GINT_FP64, stream=None, device_mib_cap: int = 0):
         sts, keep, n = _marshal_batch(system)
         opt = gint_options()
         opt.precision = precision
         opt.cluster_atoms = cluster_atoms
         opt.max_bigcells_per_item = max_bigcells_per_item
+        opt.device_mib_cap = device_mib_cap
         ptr = C.c_void_p()
         rc = _lib.gint_plan_create(C.byref(ptr), sts, n, C.byref(opt),
                                    _stream(stream) if stream is not None else None)
@@ -269,6 +272,22 @@ def gint_force_stress(plan: Plan, v_loc, d_vals, force, stress, energy=None, str
     _check(_lib.gint_force_stress(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"),
                                   _dev_ptr(d_vals, plan.nnz, "d_vals"), _dev_ptr(force, 3 * plan.natom, "force"),
                                   _dev_ptr(stress, 9 * plan.n_sys, "stress"), en, _stream(stream)), "gint_force_stress")
+
+
+def gint_energy(plan: Plan, v_loc, rho, energy, stream=None):
+    """E = w sum_g V_g rho_g per system into energy (device, n_sys)."""
+    _check(_lib.gint_energy(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"), _dev_ptr(rho, plan.ngrid, "rho"),
+                            _dev_ptr(energy, plan.n_sys, "energy"), _stream(stream)), "gint_energy")
+
+
+def measure_peaks(stream=None) -> dict:
+    """Achievable TFLOP/s of FP64 MFMA, FP16 MFMA, FP32 and FP64 vector FMA
+    on the current device (gint_peaks_measure; synchronous)."""
+    out = (C.c_double * 4)()
+    rc = _lib.gint_peaks_measure(out, _stream(stream))
+    if rc != 0:
+        raise RuntimeError(f"gint_peaks_measure failed ({rc})")
+    return {"mfma_f64": out[0], "mfma_f16": out[1], "valu_f32": out[2], "valu_f64": out[3]}
 
 
 def gint_work_units(plan: Plan, w_out, stream=None):

@@ -9,13 +9,16 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "gint.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def _declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(gint_[a-z_]+)\s*\(", txt)))
+    names = set()
+    for f in sorted(os.listdir(INCLUDE)):
+        if f.endswith(".h"):
+            txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, f)).read(), flags=re.S)
+            names |= set(re.findall(r"\b(gint_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -139,3 +142,15 @@ def test_null_arguments(G):
     assert lib.gint_plan_query_system(None, 0, C.byref(G.gint_system_sizes())) == G.GINT_EINVAL
     lib.gint_graph_destroy(None)
     lib.gint_plan_destroy(None)
+
+
+def test_device_cap_gives_enomem_before_any_hip_call(G):
+    """A plan larger than the caller's device-memory cap fails with
+    GINT_ENOMEM; the check runs on the host plan before the device is
+    touched (so it holds here, without a GPU)."""
+    from paper_2409_09399_amd import inputs as I
+    s = I.diamond8(0)            # grid 32^3: a plan of a few MiB
+    assert _create(G, s, device_mib_cap=1) == G.GINT_ENOMEM
+    # the cap applies to a batch as a whole
+    t = _tiny()
+    assert _create(G, [t, s, t], device_mib_cap=1) == G.GINT_ENOMEM

@@ -99,3 +99,36 @@ def test_energy_fd_tbg868(torch_dev, oracle_mod):
     # and against the oracle's analytic force: dE/dtau = -F
     Fo, _ = oracle_mod.Oracle(s).force_atoms(atoms[:4])
     assert np.abs(-gtau[atoms[:4]] - Fo).max() <= 1e-10 * np.abs(Fo).max()
+
+
+def test_energy_from_library_and_plan_reuse(torch_dev):
+    """The energy is the library's reduction (equal to the force pass's E
+    and to sum w V rho), the plan is reused at fixed geometry, and backward
+    can run twice with retain_graph."""
+    from paper_2409_09399_amd import autograd as A
+    from paper_2409_09399_amd import gint as G
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.diamond8(2, grid=(16, 16, 16))
+    v = torch.tensor(s.v, device=dev)
+    d = torch.tensor(s.d, device=dev, requires_grad=True)
+    tau = torch.tensor(s.pos, device=dev, requires_grad=True)
+    E = A.energy(s, v, d, tau)
+    plan1 = A._plan_cache["entry"][2]
+    E2 = A.energy(s, v, d, tau)
+    assert A._plan_cache["entry"][2] is plan1          # same geometry: plan reused
+    assert float(E) == float(E2)
+    plan = G.Plan(s)
+    F = torch.empty(3 * s.natom, dtype=torch.float64, device=dev)
+    sig = torch.empty(9, dtype=torch.float64, device=dev)
+    Ef = torch.empty(1, dtype=torch.float64, device=dev)
+    G.gint_force_stress(plan, v, d.detach(), F, sig, Ef)
+    torch.cuda.synchronize()
+    assert abs(float(E) - float(Ef[0])) <= 1e-12 * abs(float(Ef[0]))
+    E.backward(retain_graph=True)
+    g1 = tau.grad.clone()
+    tau.grad = None
+    E.backward()
+    assert torch.equal(g1, tau.grad)
+    assert torch.allclose(-g1.reshape(-1), F, rtol=0, atol=1e-12 * float(F.abs().max()))
+    plan.close()

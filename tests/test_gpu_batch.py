@@ -4,8 +4,9 @@ launch per call, packed buffers (through the C ABI).
 Each system's slice of the packed outputs is compared with the FP64 oracle of
 that system alone, to the plain path's bar (max-norm relative 1e-11; W
 exact).  The 64-structure batch of random C/H/O crystals (40-600 atoms, grids
-32^3-96^3) is checked on sampled outputs the oracle computes one by one, and
-its mixed-precision form against the FP64 batch at the mixed bounds.
+32^3-96^3) is checked on sampled outputs the oracle computes one by one; its
+mixed-precision forms against the oracle on sampled and largest outputs and
+against the FP64 batch everywhere, at the absolute mixed bounds.
 """
 import numpy as np
 import pytest
@@ -181,37 +182,63 @@ def test_batch64_sampled(batch64, oracle_mod):
         assert abs(float(g["rho"].sum()) * w - g["ne"]) <= 1e-11 * abs(g["ne"])
 
 
+# Mixed-precision bounds.  FP16x3 is held to the stated targets: |dH| <= 1e-6
+# Ha and |dF| <= 1e-5 Ha/Bohr absolute.  BF16x3 carries 16 bits per split
+# operand instead of 22, so its bounds are 30x looser.  rho, sigma and E are
+# bounded relative to their magnitudes: rho and sigma against their largest
+# entry, E against the size of its terms <|D|, |H|> (E = <D, H> sums terms of
+# both signs, random V and D, which cancel by a factor of about 1000 here).
+MIXED_BOUNDS = {1: dict(H=1e-6, F=1e-5, rel=1e-5), 2: dict(H=3e-5, F=3e-4, rel=3e-4)}
+
+
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
-def test_batch64_mixed(G_mod, torch_dev, batch64, prec):
-    """The mixed forms of the 64-structure batch against its FP64 result
-    (itself within 1e-11 of the oracle).  These dense crystals have
-    |H| up to ~6 Ha and |F| up to ~17 Ha/Bohr, and a two-piece FP16 split
-    carries about 22 bits per operand, so the bounds here are relative to the
-    largest entry (FP16x3: H 5e-7, F 5e-6, rho and sigma 1e-5; BF16x3 100x
-    looser); the absolute errors are printed.  E = <D, H> = sum_g w V rho is
-    a sum whose terms cancel (random V and D), so its error is bounded
-    against the magnitude of those terms, <|D|, |H|>, at the same 1e-5.  The
-    absolute targets (H 1e-6 Ha, F 1e-5 Ha/Bohr) are asserted on the diamond
-    and bilayer cases in test_gpu_mixed.py."""
+def test_batch64_mixed(G_mod, torch_dev, batch64, oracle_mod, prec):
+    """The mixed forms of the 64-structure batch against the FP64 oracle.
+
+    On six systems (smallest, largest and four others): H on the blocks the
+    FP64 result marks as largest plus random ones, forces on the atoms with
+    the largest force plus random ones, rho at random points, each computed
+    by the oracle one by one, at the absolute bounds.  Over all 64 systems,
+    every output is also compared with the FP64 batch (itself within 1e-11 of
+    the oracle), at the same bounds."""
     torch, dev = torch_dev
     systems, ref = batch64
     got = run_batch(G_mod, torch, dev, systems, precision=prec)
-    bounds = {1: dict(H=5e-7, F=5e-6, rel=1e-5), 2: dict(H=5e-5, F=5e-4, rel=1e-3)}[prec]
-    worst = dict(H_abs=0.0, F_abs=0.0, H_rel=0.0, F_rel=0.0, rho_rel=0.0, sigma_rel=0.0, E_rel=0.0, E_scaled=0.0)
+    bd = MIXED_BOUNDS[prec]
+    order = np.argsort([s.natom for s in systems])
+    pick = [order[0], order[-1], order[13], order[27], order[41], order[55]]
+    rng = np.random.default_rng(7)
+    worst_or = dict(H=0.0, F=0.0, rho_rel=0.0)
+    for k in pick:
+        s, g, r = systems[k], got[k], ref[k]
+        o = oracle_mod.Oracle(s)
+        norb = s.norb_atom()
+        sizes = norb[s.blk_i] * norb[s.blk_j]
+        bmax = np.array([np.abs(r["h"][s.blk_off[b]:s.blk_off[b] + sizes[b]]).max() for b in range(len(s.blk_i))])
+        blks = np.unique(np.concatenate([np.argsort(bmax)[-6:], rng.choice(len(s.blk_i), 6, replace=False)]))
+        for b, hr in zip(blks, o.vlocal_blocks(blks)):
+            hg = g["h"][s.blk_off[b]:s.blk_off[b] + hr.size].reshape(hr.shape)
+            worst_or["H"] = max(worst_or["H"], float(np.abs(hg - hr).max()))
+        atoms = np.unique(np.concatenate([np.argsort(np.abs(r["F"]).max(1))[-3:], rng.choice(s.natom, 3, replace=False)]))
+        Fo, _ = o.force_atoms(atoms)
+        worst_or["F"] = max(worst_or["F"], float(np.abs(g["F"][atoms] - Fo).max()))
+        gi = rng.choice(s.ngrid, 40, replace=False)
+        ro = o.rho_points(gi)
+        worst_or["rho_rel"] = max(worst_or["rho_rel"], float(np.abs(g["rho"][gi] - ro).max() / np.abs(r["rho"]).max()))
+    worst = dict(H=0.0, F=0.0, rho_rel=0.0, sigma_rel=0.0, E_scaled=0.0, ne_rel=0.0)
     for s, g, r in zip(systems, got, ref):
-        worst["H_abs"] = max(worst["H_abs"], float(np.abs(g["h"] - r["h"]).max()))
-        worst["F_abs"] = max(worst["F_abs"], float(np.abs(g["F"] - r["F"]).max()))
-        worst["H_rel"] = max(worst["H_rel"], rel(g["h"], r["h"]))
-        worst["F_rel"] = max(worst["F_rel"], rel(g["F"], r["F"]))
+        worst["H"] = max(worst["H"], float(np.abs(g["h"] - r["h"]).max()))
+        worst["F"] = max(worst["F"], float(np.abs(g["F"] - r["F"]).max()))
         worst["rho_rel"] = max(worst["rho_rel"], rel(g["rho"], r["rho"]))
         worst["sigma_rel"] = max(worst["sigma_rel"], rel(g["sig"], r["sig"]))
-        worst["E_rel"] = max(worst["E_rel"], abs(g["E"] - r["E"]) / abs(r["E"]))
-        e_scale = float(np.dot(np.abs(s.d), np.abs(r["h"])))
-        worst["E_scaled"] = max(worst["E_scaled"], abs(g["E"] - r["E"]) / e_scale)
+        worst["E_scaled"] = max(worst["E_scaled"], abs(g["E"] - r["E"]) / float(np.dot(np.abs(s.d), np.abs(r["h"]))))
+        worst["ne_rel"] = max(worst["ne_rel"], abs(g["ne"] - r["ne"]) / abs(r["ne"]))
     hmax = max(float(np.abs(r["h"]).max()) for r in ref)
     fmax = max(float(np.abs(r["F"]).max()) for r in ref)
-    print(f"[mixed] batch64 prec={prec} worst {worst} max|H| {hmax:.4g} max|F| {fmax:.4g}", flush=True)
-    assert worst["H_rel"] <= bounds["H"]
-    assert worst["F_rel"] <= bounds["F"]
-    for k in ("sigma_rel", "E_scaled", "rho_rel"):
-        assert worst[k] <= bounds["rel"], k
+    print(f"[mixed] batch64 prec={prec} vs oracle (sampled) {worst_or}; all 64 vs FP64 {worst}; "
+          f"max|H| {hmax:.4g} max|F| {fmax:.4g}", flush=True)
+    assert worst_or["H"] <= bd["H"] and worst["H"] <= bd["H"]
+    assert worst_or["F"] <= bd["F"] and worst["F"] <= bd["F"]
+    assert worst_or["rho_rel"] <= bd["rel"]
+    for k in ("rho_rel", "sigma_rel", "E_scaled", "ne_rel"):
+        assert worst[k] <= bd["rel"], k

@@ -5,7 +5,9 @@ Checked on outputs the oracle computes one by one (rho at sampled points,
 sampled H blocks, forces on sampled atoms) and on identities that hold at any
 size (<D, H> = E = sum_g w V rho, N_e = sum_g w rho).
 Bars as elsewhere: FP64 1e-11 relative to the largest entry; FP16x3 within
-the mixed-precision targets (H 1e-6 Ha, F 1e-5 Ha/Bohr).
+the mixed-precision targets (H 1e-6 Ha, F 1e-5 Ha/Bohr), sampled against the
+oracle and everywhere against the FP64 result, with stress and energy
+relative 1e-5.
 """
 import numpy as np
 import pytest
@@ -50,7 +52,7 @@ def run(big, prec):
     rho_sum = float(rho.sum()) * s.volume / s.ngrid
     torch.cuda.synchronize()
     out = dict(h=h, rho=rho, F=F.cpu().numpy().reshape(-1, 3), E=float(E.cpu()[0]), ne=float(ne.cpu()[0]),
-               W=float(W.cpu()[0]), tr=tr, e_rho=e_rho, rho_sum=rho_sum)
+               W=float(W.cpu()[0]), tr=tr, e_rho=e_rho, rho_sum=rho_sum, sig=sig.cpu().numpy().reshape(3, 3))
     plan.close()
     return out
 
@@ -70,8 +72,13 @@ def sampled(big, out, oracle_mod, rng):
     return r_or, r_gpu, refs, h_gpu, Fo, out["F"][atoms], g, o
 
 
-def test_tbg29_fp64(big, oracle_mod):
-    out = run(big, 0)
+@pytest.fixture(scope="module")
+def f64(big):
+    return run(big, 0)
+
+
+def test_tbg29_fp64(big, f64, oracle_mod):
+    out = f64
     assert abs(out["tr"] - out["E"]) <= TOL * abs(out["E"])
     assert abs(out["e_rho"] - out["E"]) <= TOL * abs(out["E"])
     assert abs(out["rho_sum"] - out["ne"]) <= TOL * abs(out["ne"])
@@ -87,7 +94,7 @@ def test_tbg29_fp64(big, oracle_mod):
     assert out["W"] > 0 and out["W"] == float(int(out["W"]))
 
 
-def test_tbg29_fp16x3(big, oracle_mod):
+def test_tbg29_fp16x3(big, f64, oracle_mod):
     out = run(big, 1)
     r_or, r_gpu, refs, h_gpu, Fo, Fg, g, o = sampled(big, out, oracle_mod, np.random.default_rng(4))
     herr = max(float(np.abs(g - r).max()) for r, g in zip(refs, h_gpu))
@@ -97,7 +104,17 @@ def test_tbg29_fp16x3(big, oracle_mod):
     # the other mixed-precision tests)
     ra = o.rho_abs_points(g)
     rpt = float(np.max(np.abs(r_gpu - r_or) / (ra + 1e-10 * ra.max())))
-    print(f"[mixed] tbg29 H_abs {herr:.3g} F_abs {ferr:.3g} rho_rel {rerr:.3g} rho_pt {rpt:.3g}", flush=True)
-    assert herr <= 1e-6
-    assert ferr <= 1e-5
+    # every output against the FP64 path on the same workload: H and rho on
+    # the device, F, stress and energy on the host
+    h_all = float((out["h"] - f64["h"]).abs().max())
+    rho_all = float((out["rho"] - f64["rho"]).abs().max()) / float(f64["rho"].abs().max())
+    f_all = float(np.abs(out["F"] - f64["F"]).max())
+    sig_rel = float(np.abs(out["sig"] - f64["sig"]).max() / np.abs(f64["sig"]).max())
+    e_rel = abs(out["E"] - f64["E"]) / abs(f64["E"])
+    print(f"[mixed] tbg29 H_abs {herr:.3g} F_abs {ferr:.3g} rho_rel {rerr:.3g} rho_pt {rpt:.3g}; vs FP64 "
+          f"H_abs_all {h_all:.3g} F_abs_all {f_all:.3g} rho_rel_all {rho_all:.3g} sigma_rel {sig_rel:.3g} "
+          f"E_rel {e_rel:.3g}", flush=True)
+    assert herr <= 1e-6 and h_all <= 1e-6
+    assert ferr <= 1e-5 and f_all <= 1e-5
     assert rpt <= 1e-5
+    assert sig_rel <= 1e-5 and e_rel <= 1e-5

@@ -123,10 +123,46 @@ def test_mixed_tbg868_sampled(torch_dev, oracle_mod, prec):
     errs = {"H_abs": herr, "rho_rel": float(np.abs(gpu["rho"][g] - r_or).max() / np.abs(gpu["rho"]).max()),
             "rho_pt": rho_scaled(gpu["rho"][g], r_or, o.rho_abs_points(g)),
             "F_abs": float(np.abs(gpu["F"][atoms] - Fo).max())}
+    # every output against the FP64 path on the same workload (itself checked
+    # against the oracle in the parity tests): stress and energy included
+    f64 = run(G, torch, dev, s, 0)
+    full = {"H_abs_all": float(np.abs(gpu["h"] - f64["h"]).max()),
+            "F_abs_all": float(np.abs(gpu["F"] - f64["F"]).max()),
+            "rho_rel_all": float(np.abs(gpu["rho"] - f64["rho"]).max() / np.abs(f64["rho"]).max()),
+            "sigma_rel": float(np.abs(gpu["sig"] - f64["sig"]).max() / np.abs(f64["sig"]).max()),
+            "E_rel": abs(gpu["E"] - f64["E"]) / abs(f64["E"])}
+    errs.update(full)
     print("[mixed] tbg868", prec, errs, flush=True)
     record("tbg868_sampled", prec, errs)
-    for k in ("H_abs", "rho_pt", "F_abs"):
+    for k in ("H_abs", "rho_pt", "F_abs", "sigma_rel", "E_rel"):
         assert errs[k] <= BOUNDS[prec][k], (k, errs[k])
+    assert errs["H_abs_all"] <= BOUNDS[prec]["H_abs"] and errs["F_abs_all"] <= BOUNDS[prec]["F_abs"]
+
+
+def test_tbg148_coarse_full_oracle(torch_dev, oracle_mod):
+    """A 148-atom twisted bilayer (commensurate i = 3) on a coarse grid
+    (h = 0.44 Bohr) against the full oracle: every output of the FP64 path to
+    1e-11 (stress included), and of FP16x3 and BF16x3 to their bounds."""
+    from paper_2409_09399_amd import gint as G
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.tbg_system(3, h=0.44)
+    print(f"[mixed] tbg148 coarse grid {tuple(int(x) for x in s.grid)} natom {s.natom}", flush=True)
+    o = oracle_mod.Oracle(s)
+    F, Z, E, sig = o.force_stress()
+    ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
+    e64 = errors(run(G, torch, dev, s, 0), ref)
+    e64["F_rel"] = e64["F_abs"] / float(np.abs(F).max())
+    e64["H_rel"] = e64["H_abs"] / float(np.abs(ref["h"]).max())
+    print("[mixed] tbg148 fp64", e64, flush=True)
+    for k in ("H_rel", "rho_rel", "F_rel", "sigma_rel", "E_rel"):
+        assert e64[k] <= 1e-11, (k, e64[k])
+    for prec in (1, 2):
+        errs = errors(run(G, torch, dev, s, prec), ref)
+        print("[mixed] tbg148", prec, errs, flush=True)
+        record("tbg148_coarse", prec, errs)
+        for k, b in BOUNDS[prec].items():
+            assert errs[k] <= b, (prec, k, errs[k], b)
 
 
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
