@@ -139,8 +139,10 @@ def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, aut
     tune = None
     opts = dict(opts or {})
     if autotune:
-        chosen, tune = G.autotune(target, precision=prec, budget_seconds=tune_seconds)
-        opts = dict(cluster_atoms=chosen["cluster_atoms"], max_bigcells_per_item=chosen["max_bigcells_per_item"])
+        chosen, tune = G.autotune(target, precision=prec, budget_seconds=tune_seconds,
+                                  decomposition=opts.get("decomposition", 0))
+        opts = dict(cluster_atoms=chosen["cluster_atoms"], max_bigcells_per_item=chosen["max_bigcells_per_item"],
+                    brick=tuple(chosen["brick"]), decomposition=opts.get("decomposition", 0))
         log(f"[bench] autotune {DTYPES[prec]}: {opts} {tune}")
     t = time.perf_counter()
     plan = G.Plan(target, precision=prec, **opts)
@@ -338,6 +340,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 10,444-atom and 64-crystal records")
     ap.add_argument("--extra-steps", type=int, default=2)
+    ap.add_argument("--decomposition", choices=["default", "cluster_pairs", "bigcell"], default="default",
+                    help="work decomposition of rho and the force pass")
+    ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0], help="bigcells per brick (0 = plan's choice)")
     ap.add_argument("--cluster-atoms", type=int, default=0)
     ap.add_argument("--max-bigcells", type=int, default=0)
     ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph of the step")
@@ -381,7 +386,9 @@ def main():
         del src, dst
 
     prec = PRECISIONS[args.precision]
-    opts = dict(cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells)
+    opts = dict(cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells,
+                decomposition={"default": 0, "cluster_pairs": 1, "bigcell": 2}[args.decomposition],
+                brick=tuple(args.brick))
     out_main = alloc(torch, dev, systems)
     main_form = run_form(G, torch, systems, prec, args.steps, args.warmup, v, d, out_main, graph=args.graph,
                          autotune=args.autotune, tune_seconds=args.tune_seconds, opts=opts)
@@ -389,8 +396,11 @@ def main():
     if args.compare not in ("none", args.precision):
         cmp_prec = PRECISIONS[args.compare]
         out_cmp = alloc(torch, dev, systems)
+        cmp_opts = dict(opts)
+        if cmp_prec == 0:
+            cmp_opts["decomposition"] = 0     # the FP64 path runs over cluster pairs
         c = run_form(G, torch, systems, cmp_prec, args.steps, args.warmup, v, d, out_cmp, graph=args.graph,
-                     opts=opts)
+                     opts=cmp_opts)
         cmp_form = {"precision": args.compare, "dtype": DTYPES[cmp_prec], "value": c["value"],
                     "ms_per_step": c["ms_per_step"], "kernel_ms": c["kernel_ms"],
                     "fused_rho_force_stress_ms": c["fused_rho_force_stress_ms"],

@@ -111,8 +111,19 @@ typedef struct {
     int max_bigcells_per_item; /* work-item length cap (0 = default) */
     int device_mib_cap;      /* device memory the plan may hold, in MiB (0 = no cap): a plan
                                 that needs more fails with GINT_ENOMEM before any HIP call */
-    int reserved[4];
+    int brick[3];            /* bigcell-stationary path: bigcells per brick along a1, a2, a3
+                                (each 1..8; 0 = chosen by the plan) */
+    int decomposition;       /* GINT_DECOMP_*: how rho and the force are divided into work */
 } gint_options;
+
+/* Work decomposition of rho and the force/stress pass (Vlocal always runs
+ * over cluster pairs).  CLUSTER_PAIRS: output-stationary cluster-pair items,
+ * every orbital evaluated once per cluster pair that needs it.  BIGCELL:
+ * bigcell-stationary bricks (the paper's grid batches, "Computational
+ * Collaboration Between Host and Device"): every orbital evaluated once per
+ * bigcell, rho written once per point without atomics; available in the
+ * mixed forms.  DEFAULT: BIGCELL for the mixed forms, CLUSTER_PAIRS for FP64. */
+enum { GINT_DECOMP_DEFAULT = 0, GINT_DECOMP_CLUSTER_PAIRS = 1, GINT_DECOMP_BIGCELL = 2 };
 
 /* Sizes of a plan (host struct filled by gint_plan_query). */
 typedef struct {
@@ -129,6 +140,10 @@ typedef struct {
     int precision;           /* the plan's precision form */
     double build_seconds;    /* host time of gint_plan_create */
     int n_sys;               /* systems in the plan (packed buffers when > 1) */
+    int decomposition;       /* GINT_DECOMP_CLUSTER_PAIRS or GINT_DECOMP_BIGCELL (rho and force) */
+    int brick[3];            /* bigcells per brick (bigcell-stationary plans; of system 0) */
+    int64_t nbricks;         /* bricks with at least one atom image (bigcell-stationary plans) */
+    int64_t brick_images;    /* atom images summed over the bricks' unions */
 } gint_sizes;
 
 /* Where system i of a plan lives in the packed buffers (host struct filled by
@@ -226,22 +241,31 @@ int gint_graph_create(gint_graph **out, gint_plan *p, const double *v_loc, const
 int gint_graph_launch(gint_graph *g, void *stream);
 void gint_graph_destroy(gint_graph *g);
 
-/* Autotuner of the tile shape (paper: short timed trials pick the kernel
- * parameters, "Device Performance Optimization").  Candidates of (cluster_atoms,
- * max_bigcells_per_item) are tried in a fixed order; for each a plan is
- * built and one full step (Vlocal, rho, force/stress on constant V and D in
- * scratch buffers the tuner allocates and frees) is timed with HIP events on
- * `stream`.  No new candidate starts once budget_seconds of wall time have
- * passed (the first always runs).  On input opt->precision selects the form;
- * on success opt->cluster_atoms and opt->max_bigcells_per_item hold the
- * fastest candidate and *report every trial.  Synchronous. */
+/* Autotuner of the tile shapes (paper: short timed trials pick the kernel
+ * parameters, "Device Performance Optimization").  Two independent choices:
+ * the cluster tile of the Vlocal kernel (cluster_atoms,
+ * max_bigcells_per_item) and, for the bigcell-stationary rho/force path, the
+ * brick shape (bigcells per brick along a1, a2, a3).  Trial k builds a plan
+ * with cluster candidate k and brick candidate k (fixed orders) and times,
+ * with HIP events on `stream`, one Vlocal call and one rho + force/stress
+ * pass on constant V and D in scratch buffers the tuner allocates and frees;
+ * the Vlocal time scores the cluster candidate, the rho + force time the
+ * brick candidate.  No new trial starts once budget_seconds of wall time
+ * have passed (the first always runs).  On input opt->precision and
+ * opt->decomposition select the form (FP64 plans have no brick choice); on
+ * success opt->cluster_atoms, opt->max_bigcells_per_item and opt->brick hold
+ * the fastest candidates and *report every trial.  Synchronous. */
 #define GINT_TUNE_MAX 16
 typedef struct {
-    int ntrials;                         /* candidates timed */
-    int best;                            /* index of the chosen one */
+    int ntrials;                         /* trials timed */
+    int best;                            /* trial with the fastest Vlocal (cluster choice) */
+    int best_brick;                      /* trial with the fastest rho + force (brick choice) */
     int cluster_atoms[GINT_TUNE_MAX];
     int max_bigcells_per_item[GINT_TUNE_MAX];
-    double step_ms[GINT_TUNE_MAX];       /* one Vlocal + rho + force/stress pass */
+    int brick[GINT_TUNE_MAX][3];         /* as resolved by the plan (0 when the plan has no bricks) */
+    double vlocal_ms[GINT_TUNE_MAX];     /* one Vlocal call */
+    double rho_force_ms[GINT_TUNE_MAX];  /* one rho + force/stress pass */
+    double step_ms[GINT_TUNE_MAX];       /* their sum */
     double seconds;                      /* wall time of the search */
 } gint_tune_report;
 int gint_autotune(const gint_system *sys, int n_sys, gint_options *opt, double budget_seconds,

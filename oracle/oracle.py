@@ -256,3 +256,62 @@ class Oracle:
         w = np.zeros(1)
         self._check(self.lib.oracle_work(self._ps, g_range[0], g_range[1], _p(w)))
         return float(w[0])
+
+    # ---- one SCF step at the Gamma point (paper: "GPU Acceleration of
+    # Diagonalization", Eq. 6-8), the plain definitions
+
+    def _orb_offsets(self):
+        norb = self.system.norb_atom()
+        return np.concatenate([[0], np.cumsum(norb)]).astype(np.int64)
+
+    def fold_gamma(self, vals) -> np.ndarray:
+        """M[I mu, J nu] = sum_R vals_IJR[mu, nu]: the Bloch sum of a block
+        matrix at k = 0, dense over the atoms' orbitals in order."""
+        s = self.system
+        o = self._orb_offsets()
+        norb = s.norb_atom()
+        M = np.zeros((int(o[-1]), int(o[-1])))
+        for k in range(len(s.blk_i)):
+            i, j = int(s.blk_i[k]), int(s.blk_j[k])
+            M[o[i]:o[i + 1], o[j]:o[j + 1]] += \
+                np.asarray(vals[s.blk_off[k]:s.blk_off[k] + norb[i] * norb[j]]).reshape(norb[i], norb[j])
+        return M
+
+    def scatter_gamma(self, dense) -> np.ndarray:
+        """Block values vals_IJR[mu, nu] = dense[I mu, J nu] for every R: a
+        Gamma-point matrix on the block pattern."""
+        s = self.system
+        o = self._orb_offsets()
+        norb = s.norb_atom()
+        out = np.zeros(s.nnz)
+        for k in range(len(s.blk_i)):
+            i, j = int(s.blk_i[k]), int(s.blk_j[k])
+            out[s.blk_off[k]:s.blk_off[k] + norb[i] * norb[j]] = dense[o[i]:o[i + 1], o[j]:o[j + 1]].ravel()
+        return out
+
+    @staticmethod
+    def occupations(eig, n_electrons: float, kT: float = 0.0) -> np.ndarray:
+        """2 per orbital in increasing order of energy until n_electrons are
+        placed (kT <= 0), or 2 / (1 + exp((e - mu)/kT)) with sum = n_electrons."""
+        e = np.asarray(eig, dtype=np.float64)
+        if not kT > 0:
+            return np.clip(n_electrons - 2.0 * np.arange(e.size), 0.0, 2.0)
+        from scipy.optimize import brentq
+
+        def f(mu):
+            return 2.0 / (1.0 + np.exp(np.clip((e - mu) / kT, -700, 700)))
+        mu = brentq(lambda m: f(m).sum() - n_electrons, e[0] - 40 * kT - 1, e[-1] + 40 * kT + 1,
+                    xtol=1e-15, rtol=1e-15, maxiter=500)
+        return f(mu)
+
+    def scf_gamma(self, h_vals, s_vals, n_electrons: float, kT: float = 0.0):
+        """(eigenvalues, occupations, eigenvectors, D(R) on the pattern) of
+        H^G c = e S^G c with the occupations above and D^G = sum_i f_i c_i c_i^T."""
+        from scipy.linalg import eigh
+        HG = self.fold_gamma(h_vals)
+        SG = self.fold_gamma(s_vals)
+        e, Z = eigh(0.5 * (HG + HG.T), 0.5 * (SG + SG.T))
+        f = self.occupations(e, n_electrons, kT)
+        DG = (Z * f) @ Z.T
+        return e, f, Z, self.scatter_gamma(DG)
+

@@ -9,8 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgint.so")
-SOURCES = ["gint_kernels.hip", "gint_kernels_mixed.hip", "gint_api.cpp", "gint_plan.cpp", "gint_tune.cpp",
-           "gint_peaks.hip"]
+SOURCES = ["gint_kernels.hip", "gint_kernels_mixed.hip", "gint_kernels_bc.hip", "gint_api.cpp", "gint_plan.cpp", "gint_tune.cpp",
+           "gint_peaks.hip", "gint_scf.hip"]
 ARCH = os.environ.get("GINT_OFFLOAD_ARCH", "gfx950")
 
 
@@ -21,7 +21,7 @@ def build(verbose: bool = False) -> str:
            "-mllvm", "-amdgpu-mfma-vgpr-form",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES],
-           "-o", LIB + ".tmp", "-lpthread"]
+           "-o", LIB + ".tmp", "-lpthread", "-lrocsolver", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

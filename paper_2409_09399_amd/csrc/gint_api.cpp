@@ -10,6 +10,7 @@
 #include "gint.h"
 #include "gint_internal.h"
 #include "gint_plan.hpp"
+#include "gint_plan_impl.h"
 
 hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s);
@@ -29,34 +30,17 @@ hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long 
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s);
 hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
                                 double *rho, hipStream_t s);
+hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
+                              double *rho, hipStream_t s);
+hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
+                                const double *D, double *F, double *ZE, double *rho, hipStream_t s);
+void gint_prime_grids_bc(int prec);
 
 namespace {
-
 thread_local int g_last_hip = 0;
-constexpr int kParts = 256;   // partial sums per system for N_e
-
-struct DevBuf {
-    void *p = nullptr;
-    size_t bytes = 0;
-};
-
 }  // namespace
 
-struct gint_plan {
-    int device = 0;
-    GDev canon{};      // canonical items (vlocal, rho, work)
-    GDev ordered{};    // canonical + swapped items (force)
-    DevBuf species, atoms, tab, tab32, pairs, bigcells, items_canon, items_ordered, sys, ws;
-    int precision = GINT_FP64;
-    int n_sys = 1;
-    int *counter = nullptr;    // work counter of the persistent launches
-    double *ZE = nullptr;      // [n_sys][10]: Z (9) and E
-    double *part = nullptr;    // [n_sys][kParts]
-    std::vector<GSys> sys_host;
-    std::vector<GBlk> blocks_host;   // pattern blocks, uploaded by the first symmetry check
-    DevBuf blocks;
-    gint_sizes sizes{};
-};
+void gint_record_hip_error(int e) { g_last_hip = e; }
 
 namespace {
 
@@ -89,7 +73,7 @@ int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
 
 void release(gint_plan *p) {
     DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->tab32, &p->pairs, &p->bigcells, &p->items_canon,
-                      &p->items_ordered, &p->sys, &p->ws, &p->blocks};
+                      &p->items_ordered, &p->sys, &p->ws, &p->blocks, &p->bricks, &p->uatoms, &p->ptab, &p->d16};
     for (DevBuf *b : bufs)
         if (b->p) {
             (void)hipFree(b->p);
@@ -118,11 +102,16 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     if (!out || !sys || n_sys < 1) return GINT_EINVAL;
     const int prec = opt ? opt->precision : GINT_FP64;
     if (prec != GINT_FP64 && prec != GINT_MIXED_FP16X3 && prec != GINT_MIXED_BF16X3) return GINT_EUNSUPPORTED;
+    const int decomp = opt ? opt->decomposition : GINT_DECOMP_DEFAULT;
+    if (decomp != GINT_DECOMP_DEFAULT && decomp != GINT_DECOMP_CLUSTER_PAIRS && decomp != GINT_DECOMP_BIGCELL)
+        return GINT_EINVAL;
+    if (decomp == GINT_DECOMP_BIGCELL && prec == GINT_FP64) return GINT_EUNSUPPORTED;
+    const bool bc = prec != GINT_FP64 && decomp != GINT_DECOMP_CLUSTER_PAIRS;
     const auto t0 = std::chrono::steady_clock::now();
     HostPlan hp;
     int rc;
     try {
-        rc = gint_build_host_plan(sys, n_sys, opt, hp);
+        rc = gint_build_host_plan(sys, n_sys, opt, bc, hp);
     } catch (const std::bad_alloc &) {
         return GINT_ENOMEM;
     } catch (...) {
@@ -131,13 +120,18 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     if (rc != GINT_OK) return rc;
     if (hp.items_canon.size() > 0x7fffffffu || hp.items_ordered.size() > 0x7fffffffu) return GINT_ENOMEM;
     // workspace: [0] work counter (an int in the first 4 bytes), [1] max |V|,
-    // then ZE, then partial sums
-    std::vector<double> wsinit(2 + (size_t)n_sys * (10 + kParts), 0.0);
+    // [2] max |D|, then ZE, then partial sums
+    std::vector<double> wsinit(3 + (size_t)n_sys * (10 + kParts), 0.0);
+    const size_t d16_bytes = bc ? hp.blocks.size() * (size_t)1024 : 0;
+    if (bc && hp.blocks.size() > 0x7fffffffu) return GINT_ENOMEM;
     if (opt && opt->device_mib_cap > 0) {
-        const size_t need = upload_bytes(hp.species) + upload_bytes(hp.atoms) + upload_bytes(hp.tab) +
-                            upload_bytes(hp.tab32) + upload_bytes(hp.pairs) + upload_bytes(hp.bigcells) +
-                            upload_bytes(hp.items_canon) + upload_bytes(hp.items_ordered) + upload_bytes(hp.sys) +
-                            upload_bytes(wsinit);
+        size_t need = upload_bytes(hp.species) + upload_bytes(hp.atoms) + upload_bytes(hp.tab) +
+                      upload_bytes(hp.tab32) + upload_bytes(hp.pairs) + upload_bytes(hp.bigcells) +
+                      upload_bytes(hp.items_canon) + upload_bytes(hp.items_ordered) + upload_bytes(hp.sys) +
+                      upload_bytes(wsinit);
+        if (bc)
+            need += upload_bytes(hp.bricks) + upload_bytes(hp.uatoms) + upload_bytes(hp.ptab) +
+                    upload_bytes(hp.blocks) + d16_bytes;
         if (need > ((size_t)opt->device_mib_cap << 20)) return GINT_ENOMEM;
     }
 
@@ -159,15 +153,37 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         delete p;
         return rc;
     }
+    if (bc) {
+        if ((rc = upload(p->bricks, hp.bricks, total)) || (rc = upload(p->uatoms, hp.uatoms, total)) ||
+            (rc = upload(p->ptab, hp.ptab, total)) || (rc = upload(p->blocks, hp.blocks, total))) {
+            release(p);
+            delete p;
+            return rc;
+        }
+        p->d16.bytes = d16_bytes > 0 ? d16_bytes : 1024;
+        e = hipMalloc(&p->d16.p, p->d16.bytes);
+        if (e != hipSuccess) {
+            g_last_hip = (int)e;
+            p->d16.p = nullptr;
+            release(p);
+            delete p;
+            return GINT_ENOMEM;
+        }
+        total += p->d16.bytes;
+    }
+    p->bc = bc;
     p->n_sys = n_sys;
     p->sys_host = hp.sys;
+    p->atom_norb.resize(hp.atoms.size());
+    for (size_t a = 0; a < hp.atoms.size(); ++a) p->atom_norb[a] = hp.atoms[a].norb;
     p->blocks_host = std::move(hp.blocks);
     // resident-block counts of the persistent kernels, queried once here so
     // that no launch (eager or captured) needs a device query
     gint_prime_grids_fp64();   // k_work serves every precision form
     if (prec != GINT_FP64) gint_prime_grids_mx(prec);
+    if (bc) gint_prime_grids_bc(prec);
     p->counter = (int *)p->ws.p;
-    p->ZE = (double *)p->ws.p + 2;
+    p->ZE = (double *)p->ws.p + 3;
     p->part = p->ZE + 10 * n_sys;
 
     GDev d{};
@@ -198,6 +214,15 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     for (const GSpecies &g : hp.species)
         if (g.shape != d.shape_all) d.shape_all = GINT_SHAPE_ANY;
     d.vmax = (const double *)p->ws.p + 1;
+    d.dmax = (const double *)p->ws.p + 2;
+    if (bc) {
+        d.bricks = (const GBrick *)p->bricks.p;
+        d.uatoms = (const GUAtom *)p->uatoms.p;
+        d.ptab = (const int *)p->ptab.p;
+        d.d16 = (const unsigned short *)p->d16.p;
+        d.nbricks = (int)hp.bricks.size();
+        d.nblocks = (int)p->blocks_host.size();   // (hp.blocks has been moved into the plan)
+    }
     p->canon = d;
     p->canon.items = (const GItem *)p->items_canon.p;
     p->canon.nitems = (int)hp.items_canon.size();
@@ -218,6 +243,10 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     s.device_bytes = (int64_t)total;
     s.precision = prec;
     s.n_sys = n_sys;
+    s.decomposition = bc ? GINT_DECOMP_BIGCELL : GINT_DECOMP_CLUSTER_PAIRS;
+    s.nbricks = (int64_t)hp.bricks.size();
+    s.brick_images = (int64_t)hp.uatoms.size();
+    for (int k = 0; k < 3; ++k) s.brick[k] = hp.brick[k];
     p->precision = prec;
     s.build_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
@@ -242,8 +271,11 @@ int gint_rho(gint_plan *p, const double *d_vals, double *rho, double *n_elec, vo
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
-    e = p->precision == GINT_FP64 ? gint_launch_rho(p->canon, d_vals, rho, s)
-                                  : gint_launch_rho_mx(p->canon, p->precision, d_vals, rho, s);
+    e = p->precision == GINT_FP64
+            ? gint_launch_rho(p->canon, d_vals, rho, s)
+            : (p->bc ? gint_launch_rho_bc(p->canon, p->precision, (const GBlk *)p->blocks.p, p->sizes.nnz, d_vals,
+                                          rho, s)
+                     : gint_launch_rho_mx(p->canon, p->precision, d_vals, rho, s));
     if (e != hipSuccess) return hip_fail(e);
     if (n_elec) {
         e = gint_launch_seg_sum(p->canon, rho, nullptr, p->part, kParts, n_elec, s);
@@ -261,10 +293,15 @@ int force_pass(gint_plan *p, const double *v_loc, const double *d_vals, double *
     hipError_t e = gint_launch_fill(force, 3LL * p->sizes.natom, 0.0, s);
     if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10LL * p->n_sys, 0.0, s);
     if (e == hipSuccess && rho) e = gint_launch_fill(rho, p->sizes.ngrid, 0.0, s);
-    if (e == hipSuccess)
-        e = p->precision == GINT_FP64
-                ? gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, rho, s)
-                : gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, rho, s);
+    if (e == hipSuccess) {
+        if (p->precision == GINT_FP64)
+            e = gint_launch_force(p->ordered, v_loc, d_vals, force, p->ZE, rho, s);
+        else if (p->bc)
+            e = gint_launch_force_bc(p->ordered, p->precision, (const GBlk *)p->blocks.p, p->sizes.nnz, v_loc,
+                                     d_vals, force, p->ZE, rho, s);
+        else
+            e = gint_launch_force_mx(p->ordered, p->precision, v_loc, d_vals, force, p->ZE, rho, s);
+    }
     if (e == hipSuccess) e = gint_launch_finish_stress(p->ordered, p->ZE, stress, energy, s);
     if (e == hipSuccess && rho && n_elec) e = gint_launch_seg_sum(p->canon, rho, nullptr, p->part, kParts, n_elec, s);
     if (e != hipSuccess) return hip_fail(e);

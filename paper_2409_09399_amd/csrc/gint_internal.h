@@ -69,6 +69,7 @@ struct GBlk {
     long long off, off_t;        // element offsets of the block and of its transpose
     int ni, nj;                  // orbitals of I and J (the block is ni x nj, row-major)
     int sys;                     // system of a batched plan
+    int i, j;                    // atoms I and J (packed over the systems of a plan)
     int pad;
 };
 
@@ -77,6 +78,31 @@ struct GItem {
     int bc_begin;
     int bc_count;
     int pad;                     // 1: the item covers its whole pair (H written with plain stores)
+};
+
+// Bigcell-stationary decomposition (rho and force).  The grid of each system
+// is tiled by bricks of bigcells (4x4x4 points each); a brick lists every atom
+// image whose orbitals reach one of its points (its "union") and, for every
+// ordered pair (i, j) of those images, the index of the pattern block that
+// couples them, (atom_i, atom_j, T_j - T_i), or -1 if the pattern has none
+// (then the two never overlap at a grid point: the plan checks the pattern
+// against every overlapping pair).  One workgroup owns a brick: it evaluates
+// each orbital once per bigcell and writes each grid point's rho once.
+#define GINT_UMAX 256        // atom images per brick (max)
+
+struct GUAtom {
+    double x, y, z;              // position of the image: tau + T.h
+    int atom;                    // atom index (packed over the systems of a plan)
+    int species;
+};
+
+struct GBrick {
+    int o[3];                    // origin point (grid indices in [0, N), multiples of 4)
+    int sys;                     // system of a batched plan
+    int u_begin, u_count;        // union atom images [u_begin, u_begin + u_count)
+    long long pt_off;            // pair table: u_count^2 block indices, row i (k side), column j
+    int nb[3];                   // bigcells of the brick along each axis that start inside the grid
+    int pad;
 };
 
 // Geometry of one system of a (possibly batched) plan and the offsets of its
@@ -98,7 +124,9 @@ struct GDev {
     const GSpecies *species;
     const GAtom *atoms;
     const double *tab;           // interleaved radial tables
-    const float *tab32;          // the same interpolant in FP32 by knot interval (mixed precision): [k][chan][c0, c1, c2, c3], p = c0 + c1 t + c2 t^2 + c3 t^3, at 2 tab_off
+    const float *tab32;          // the same interpolant in FP32 by knot interval (mixed precision), times the
+                                 // channel's harmonic constant K_l: [k][chan][c0, c1, c2, c3],
+                                 // K_l p = c0 + c1 t + c2 t^2 + c3 t^3, at 2 tab_off
     const GPair *pairs;
     const GBig *bigcells;
     const GItem *items;
@@ -118,4 +146,12 @@ struct GDev {
     const double *vmax;
     int shape_all;               // GINT_SHAPE_* shared by every species of the plan, else GINT_SHAPE_ANY
     int pad_;
+    // bigcell-stationary path (mixed-precision rho and force)
+    const GBrick *bricks;
+    const GUAtom *uatoms;
+    const int *ptab;             // pair tables of the bricks
+    const unsigned short *d16;   // per pattern block: D_sym * dscale as 16-bit hi [nu][mu] then lo [nu][mu] (1 KiB)
+    const double *dmax;          // max |D| of the current call (reduced on the device)
+    int nbricks;
+    int nblocks;
 };

@@ -1,0 +1,450 @@
+// Bigcell-stationary rho and force/stress, mixed precision (gfx950).
+//
+// The cluster-pair kernels evaluate an atom's orbitals once for every
+// cluster pair whose region covers a bigcell, which on the bilayer workloads
+// means each (point, orbital) value is computed tens of times.  Here one
+// workgroup owns a brick of bigcells (gint_internal.h): for each bigcell it
+// finds the atom images active on its 64 points, evaluates their orbitals
+// once into LDS, and forms
+//
+//     psi_J[p, nu] = sum_{I, mu} phi_I[p, mu] D_sym(I, J, T_J - T_I)[mu, nu]   (Eq. 3, 4)
+//
+// for every active image J on FP16/BF16 MFMA (hi/lo split operands, three
+// products, FP32 accumulation over all I).  Then per point p (one lane):
+//     rho_p  = sum_J phi_J(p) . psi_J(p)                      (written once, no atomics)
+//     F_J   += 2 w V_p grad phi_J(p) . psi_J(p),  Z += 2 w V_p grad phi_J x^T . psi_J,
+//     E     += w V_p rho_p                                     (Eq. 4-5)
+// with the per-point terms in FP32 and every sum across points in FP64.
+// D_sym enters as a per-call 16-bit hi/lo copy in MFMA operand order
+// (k_d16), scaled by one power of two so that its largest entry maps below
+// 2^13 (the split then stays clear of the FP16 subnormal range).
+#include <hip/hip_runtime.h>
+
+#include "gint_mixed.h"
+
+namespace {
+
+constexpr int BC_CI = 8;                    // I images per staged chunk (four 32-wide k-steps)
+constexpr int BC_ROW = 16 * BC_CI + 8;      // 16-bit elements per point row of the chunk tile
+// J images per wave in one J group (their psi accumulators stay in
+// registers through the group): eight for rho, six for the force pass, whose
+// per-point gradient code needs the registers of the other two
+template <bool FORCE>
+constexpr int bc_jw() {
+    return FORCE ? 6 : 8;
+}
+constexpr int BC_PSTR = 17;                 // floats per point row of a wave's psi buffer
+
+// D_sym of pattern block b as 16-bit hi/lo, scaled by sD, in the order the
+// B operand of v_mfma_f32_16x16x32 reads it: [nu][mu] (column nu of the
+// block is contiguous), 16 x 16 with zero padding; hi then lo, 1 KiB a block.
+template <class T>
+__global__ __launch_bounds__(256) void k_d16(const GBlk *__restrict__ blk, int nblk, const double *__restrict__ D,
+                                             const double *__restrict__ dmax, unsigned short *__restrict__ d16) {
+    const float sD = pow2_scale(*dmax);
+    const int e = threadIdx.x, nu = e >> 4, mu = e & 15;
+    for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+        const GBlk k = ldc(blk + b);
+        float v = 0.f;
+        if (mu < k.ni && nu < k.nj) {
+            const double s = 0.5 * (D[k.off + (long long)mu * k.nj + nu] + D[k.off_t + (long long)nu * k.ni + mu]);
+            v = (float)(s * (double)sD);
+        }
+        T hi, lo;
+        Split16<T>::split(v, hi, lo);
+        unsigned short *o = d16 + (size_t)b * 512;
+        o[nu * 16 + mu] = __builtin_bit_cast(unsigned short, hi);
+        o[256 + nu * 16 + mu] = __builtin_bit_cast(unsigned short, lo);
+    }
+}
+
+// Position and species of union image i as a Slot (disp_at's input).
+__device__ inline Slot uslot(const GUAtom *U, int i) {
+    const GUAtom u = ldc(U + i);
+    return Slot{u.x, u.y, u.z, u.species};
+}
+
+// A value every lane holds the same copy of, as a wave-uniform (scalar) one.
+__device__ inline unsigned long long uniform64(unsigned long long v) {
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// One (point, image) row of the chunk tile: 16 hi and 16 lo values of the
+// image's orbitals (scaled by sphi), zeros where the image is inactive.
+template <class T, int KS>
+__device__ __attribute__((always_inline)) inline void stage_row(const GDev &P, const P3 &r, const Slot &s, float sphi,
+                                                                 T *h0, T *h1) {
+    const Disp d = disp_at(P, r, s);
+    if (d.in) {
+        CSpecies &sp = cst(P.species)[s.species];
+        with_shape<KS>(sp, [&](auto shp) {
+            constexpr int SH = decltype(shp)::value;
+            if constexpr (SH != GINT_SHAPE_ANY) {
+                stage_b16_rows<T, SH>(sp, P.tab32, d, sphi, h0, h1);
+            } else {
+                eval32<SH>(sp, P.tab32, d.x, d.y, d.z, d.kn, sphi, [&](int mu, float v) {
+                    T hi, lo;
+                    Split16<T>::split(v, hi, lo);
+                    h0[mu] = hi;
+                    h1[mu] = lo;
+                });
+            }
+        });
+    } else {
+        const u4v z = {0u, 0u, 0u, 0u};
+        *(u4v *)h0 = z;
+        *(u4v *)(h0 + 8) = z;
+        *(u4v *)h1 = z;
+        *(u4v *)(h1 + 8) = z;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// rho (FORCE = false) or force/stress/E (FORCE = true, with rho when RHO),
+// one brick per claimed work item.
+// ---------------------------------------------------------------------------
+template <class T, int KS, bool FORCE, bool RHO>
+__global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ F,
+                                                  double *__restrict__ ZE0, double *__restrict__ rho0) {
+    typedef Split16<T> S;
+    typedef typename S::vec vec;
+    constexpr bool WRHO = !FORCE || RHO;
+    constexpr int BC_JW = bc_jw<FORCE>();   // J images per wave in one J group
+    constexpr int BC_JG = 4 * BC_JW;         // J images per J group (four waves, round-robin)
+    __shared__ __attribute__((aligned(16))) T tA[2][GINT_BCPTS][BC_ROW];
+    __shared__ float psb[4][GINT_BCPTS * BC_PSTR];
+    __shared__ unsigned long long act[GINT_UMAX];
+    __shared__ short lst[GINT_UMAX];
+    __shared__ double red[4][GINT_BCPTS];
+    __shared__ double fbuf[FORCE ? GINT_UMAX : 1][3];
+    __shared__ double zred[4][10];
+    __shared__ int s_nact;
+    __shared__ int s_item;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const float sphi = (float)P0.phi_scale;
+    const float unscale = 1.f / (sphi * pow2_scale(*cst(P0.dmax)));
+    const unsigned short *__restrict__ d16 = P0.d16;
+    for (;;) {
+        const int item_ = claim_item(P0.counter, &s_item);
+        if (item_ >= P0.nbricks) break;
+        const GBrick bk = ldc(P0.bricks + item_);
+        GDev P = P0;
+        bind_system(P, bk.sys);
+        CSys &SY = cst(P0.sys)[bk.sys];
+        const int n = bk.u_count;
+        const GUAtom *U = P0.uatoms + bk.u_begin;
+        const cptr<int> pt = cst(P0.ptab + bk.pt_off);
+        double z9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
+        if constexpr (FORCE) {
+            for (int i = threadIdx.x; i < n; i += 256) fbuf[i][0] = fbuf[i][1] = fbuf[i][2] = 0.0;
+        }
+        for (int s0 = 0; s0 < bk.nb[0]; ++s0)
+        for (int s1 = 0; s1 < bk.nb[1]; ++s1)
+        for (int s2 = 0; s2 < bk.nb[2]; ++s2) {
+            // this lane's point of the bigcell
+            const int n0 = bk.o[0] + 4 * s0 + (lane >> 4), n1 = bk.o[1] + 4 * s1 + ((lane >> 2) & 3),
+                      n2 = bk.o[2] + 4 * s2 + (lane & 3);
+            const bool inside = n0 < P.N[0] && n1 < P.N[1] && n2 < P.N[2];
+            P3 r;
+            r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
+            r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
+            r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
+            r.g = inside ? ((long long)n0 * P.N[1] + n1) * P.N[2] + n2 : 0;
+            double vpt = 0.0;
+            if (FORCE && inside) vpt = V0[SY.g_off + r.g];
+            // phase 1: activity of every union image on the 64 points
+            for (int i = w; i < n; i += 4) {
+                const Disp d = disp_at(P, r, uslot(U, i));
+                const unsigned long long m = __ballot(inside && d.in);
+                if (lane == 0) act[i] = m;
+            }
+            __syncthreads();
+            // compact list of the active images (wave 0, in union order)
+            if (w == 0) {
+                int cnt = 0;
+                for (int base = 0; base < n; base += 64) {
+                    const int i = base + lane;
+                    const bool f = i < n && act[i] != 0ull;
+                    const unsigned long long b = __ballot(f);
+                    const int pos = cnt + __builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0));
+                    if (f) lst[pos] = (short)i;
+                    cnt += __popcll(b);
+                }
+                if (lane == 0) s_nact = cnt;
+            }
+            __syncthreads();
+            const int nact = __builtin_amdgcn_readfirstlane(s_nact);
+            double racc = 0.0;
+            for (int jg = 0; jg < nact; jg += BC_JG) {
+                f4v c[BC_JW][4];
+#pragma unroll
+                for (int jj = 0; jj < BC_JW; ++jj)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) c[jj][t] = (f4v){0.f, 0.f, 0.f, 0.f};
+                for (int ic = 0; ic < nact; ic += BC_CI) {
+                    // pair-table entries of the chunk's I images and the wave's J
+                    // images, one per lane (lane 8 q + jj: I image ic + q, J image
+                    // jg + w + 4 jj), loaded before the stage so that their latency
+                    // is hidden behind it
+                    int ptv = -1;
+                    {
+                        const int ix = ic + (lane >> 3), jx = jg + w + 4 * (lane & 7);
+                        if ((lane & 7) < BC_JW && ix < nact && jx < nact)
+                            ptv = P0.ptab[bk.pt_off + (long long)lst[ix] * n + lst[jx]];
+                    }
+                    // stage the chunk: wave w writes slots 2w and 2w+1
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int slot = 2 * w + q, idx = ic + slot;
+                        T *h0 = &tA[0][lane][slot * 16];
+                        T *h1 = &tA[1][lane][slot * 16];
+                        if (idx < nact) {
+                            const int i = __builtin_amdgcn_readfirstlane((int)lst[idx]);
+                            stage_row<T, KS>(P, r, uslot(U, i), sphi, h0, h1);
+                        } else {
+                            const u4v z = {0u, 0u, 0u, 0u};
+                            *(u4v *)h0 = z;
+                            *(u4v *)(h0 + 8) = z;
+                            *(u4v *)h1 = z;
+                            *(u4v *)(h1 + 8) = z;
+                        }
+                    }
+                    __syncthreads();
+                    // psi_J += phi_chunk D_sym(chunk, J) for the wave's J images: the
+                    // B operands of all four k-steps of a J are requested first
+#pragma unroll
+                    for (int jj = 0; jj < BC_JW; ++jj) {
+                        const int jidx = jg + w + 4 * jj;
+                        if (jidx >= nact) break;
+                        const int j = __builtin_amdgcn_readfirstlane((int)lst[jidx]);
+                        const unsigned long long mj = uniform64(act[j]);
+                        vec bh[BC_CI / 2], blo[BC_CI / 2];
+                        unsigned long long mm[BC_CI / 2];
+#pragma unroll
+                        for (int s = 0; s < BC_CI / 2; ++s) {
+                            mm[s] = 0ull;
+                            const int i0x = ic + 2 * s, i1x = i0x + 1;
+                            if (i0x >= nact) continue;
+                            const int i0 = __builtin_amdgcn_readfirstlane((int)lst[i0x]);
+                            const int i1 = i1x < nact ? __builtin_amdgcn_readfirstlane((int)lst[i1x]) : -1;
+                            const int b0 = __builtin_amdgcn_readlane(ptv, 16 * s + jj);
+                            const int b1 = i1 >= 0 ? __builtin_amdgcn_readlane(ptv, 16 * s + 8 + jj) : -1;
+                            if (b0 < 0 && b1 < 0) continue;
+                            mm[s] = uniform64((act[i0] | (i1 >= 0 ? act[i1] : 0ull)) & mj);
+                            const int bl = lane < 32 ? b0 : b1;
+                            if (bl >= 0) {
+                                const unsigned short *src =
+                                    d16 + (size_t)bl * 512 + (lane & 15) * 16 + 8 * ((lane >> 4) & 1);
+                                bh[s] = *(const vec *)src;
+                                blo[s] = *(const vec *)(src + 256);
+                            } else {
+#pragma unroll
+                                for (int e = 0; e < 8; ++e) {
+                                    bh[s][e] = (T)0.f;
+                                    blo[s][e] = (T)0.f;
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int s = 0; s < BC_CI / 2; ++s) {
+                            if (mm[s] == 0ull) continue;
+                            const int col = (2 * s + (lane >> 5)) * 16 + 8 * ((lane >> 4) & 1);
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                if (!((mm[s] >> (16 * t)) & 0xFFFFull)) continue;
+                                const vec ah = *(const vec *)&tA[0][16 * t + (lane & 15)][col];
+                                const vec al = *(const vec *)&tA[1][16 * t + (lane & 15)][col];
+                                c[jj][t] = S::mfma(ah, bh[s], c[jj][t]);
+                                c[jj][t] = S::mfma(ah, blo[s], c[jj][t]);
+                                c[jj][t] = S::mfma(al, bh[s], c[jj][t]);
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+                // per point: the wave's J images against their psi
+                float *ps = psb[w];
+#pragma unroll
+                for (int jj = 0; jj < BC_JW; ++jj) {
+                    const int jidx = jg + w + 4 * jj;
+                    if (jidx >= nact) break;
+                    const int j = __builtin_amdgcn_readfirstlane((int)lst[jidx]);
+                    const unsigned long long mj = uniform64(act[j]);
+                    // psi_J to point rows (MFMA layout: lane l, register q holds
+                    // point 16 t + 4 (l >> 4) + q, orbital l & 15)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if (!((mj >> (16 * t)) & 0xFFFFull)) continue;
+                        float *dst = ps + (16 * t + 4 * (lane >> 4)) * BC_PSTR + (lane & 15);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) dst[q * BC_PSTR] = c[jj][t][q] * unscale;
+                    }
+                    const Slot sj = uslot(U, j);
+                    const Disp d = disp_at(P, r, sj);
+                    const bool on = inside && d.in;
+                    double f3[3] = {0.0, 0.0, 0.0};
+                    if (on) {
+                        CSpecies &sp = cst(P.species)[sj.species];
+                        const float *prow = ps + lane * BC_PSTR;
+                        if constexpr (!FORCE) {
+                            float v = 0.f;
+                            with_shape<KS>(sp, [&](auto shp) {
+                                constexpr int SH = decltype(shp)::value;
+                                eval32<SH>(sp, P.tab32, d.x, d.y, d.z, d.kn, 1.f, [&](int mu, float x) {
+                                    if constexpr (SH != GINT_SHAPE_ANY)
+                                        if (mu >= ChanShape<SH>::norb) return;
+                                    v += x * prow[mu];
+                                });
+                            });
+                            racc += (double)v;
+                        } else {
+                            const float rr = ((float)d.kn.k + d.kn.t) * (float)sp.dr;
+                            float e, G[3];
+                            with_shape<KS>(sp, [&](auto shp) {
+                                dot_grad32<decltype(shp)::value>(sp, P.tab32, d.x, d.y, d.z, d.kn,
+                                                                 rr > 0.f ? __builtin_amdgcn_rcpf(rr) : 0.f, prow, e, G);
+                            });
+                            const double wv = P.w * vpt, c2 = 2.0 * wv;
+                            const double gs[3] = {G[0], G[1], G[2]}, xs[3] = {d.x, d.y, d.z};
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                f3[a] = c2 * gs[a];
+#pragma unroll
+                                for (int b = 0; b < 3; ++b) z9[3 * a + b] += c2 * gs[a] * xs[b];
+                            }
+                            en += wv * (double)e;
+                            if (RHO) racc += (double)e;
+                        }
+                    }
+                    if constexpr (FORCE) {
+                        for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) f3[a] += __shfl_xor(f3[a], off);
+                        }
+                        if (lane == 0) {
+                            fbuf[j][0] += f3[0];
+                            fbuf[j][1] += f3[1];
+                            fbuf[j][2] += f3[2];
+                        }
+                    }
+                }
+            }
+            if constexpr (WRHO) {
+                red[w][lane] = racc;
+                __syncthreads();
+                if (w == 0 && inside)
+                    rho0[SY.g_off + r.g] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+            }
+            __syncthreads();
+        }
+        if constexpr (FORCE) {
+            // forces of the brick's images, then Z and E of the workgroup's points
+            for (int i = threadIdx.x; i < n; i += 256) {
+                const int a = U[i].atom;
+                if (fbuf[i][0] != 0.0 || fbuf[i][1] != 0.0 || fbuf[i][2] != 0.0) {
+                    atomicAdd(F + 3 * a + 0, fbuf[i][0]);
+                    atomicAdd(F + 3 * a + 1, fbuf[i][1]);
+                    atomicAdd(F + 3 * a + 2, fbuf[i][2]);
+                }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) z9[a] += __shfl_xor(z9[a], off);
+                en += __shfl_xor(en, off);
+            }
+            if (lane == 0) {
+#pragma unroll
+                for (int a = 0; a < 9; ++a) zred[w][a] = z9[a];
+                zred[w][9] = en;
+            }
+            __syncthreads();
+            if (threadIdx.x < 10) {
+                const int k = threadIdx.x;
+                const double v = (zred[0][k] + zred[1][k]) + (zred[2][k] + zred[3][k]);
+                if (v != 0.0) atomicAdd(ZE0 + 10 * bk.sys + k, v);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int gint_persistent_grid(const void *kernel, int nitems, int threads);
+int gint_resident_blocks(const void *kernel, int threads);
+hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
+hipError_t gint_launch_absmax(const double *x, long long n, double *out, hipStream_t s);
+
+namespace {
+
+template <class T, int KS, bool FORCE, bool RHO>
+const void *bc_kernel() {
+    return (const void *)k_bc_mx<T, KS, FORCE, RHO>;
+}
+
+template <bool FORCE, bool RHO>
+const void *bc_kernel_for(int prec, int shape_all) {
+    const bool fixed = shape_all == GINT_SHAPE_2S2P1D;
+    if (prec == 2)
+        return fixed ? bc_kernel<__bf16, GINT_SHAPE_2S2P1D, FORCE, RHO>() : bc_kernel<__bf16, GINT_SHAPE_ANY, FORCE, RHO>();
+    return fixed ? bc_kernel<_Float16, GINT_SHAPE_2S2P1D, FORCE, RHO>() : bc_kernel<_Float16, GINT_SHAPE_ANY, FORCE, RHO>();
+}
+
+// max |D| into P.dmax, then D_sym as 16-bit hi/lo into P.d16
+hipError_t prepare_d16(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D, hipStream_t s) {
+    hipError_t e = gint_launch_fill(const_cast<double *>(P.dmax), 1, 0.0, s);
+    if (e == hipSuccess) e = gint_launch_absmax(D, nnz, const_cast<double *>(P.dmax), s);
+    if (e != hipSuccess || P.nblocks <= 0) return e;
+    const int grid = P.nblocks < 8192 ? P.nblocks : 8192;
+    unsigned short *d16 = const_cast<unsigned short *>(P.d16);
+    if (prec == 2)
+        hipLaunchKernelGGL(k_d16<__bf16>, dim3(grid), dim3(256), 0, s, blocks, P.nblocks, D, P.dmax, d16);
+    else
+        hipLaunchKernelGGL(k_d16<_Float16>, dim3(grid), dim3(256), 0, s, blocks, P.nblocks, D, P.dmax, d16);
+    return hipGetLastError();
+}
+
+hipError_t launch_bc(const void *k, const GDev &P, hipStream_t s, const double *V, double *F, double *ZE, double *rho) {
+    if (P.nbricks <= 0) return hipSuccess;
+    hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
+    if (e != hipSuccess) return e;
+    const int grid = gint_persistent_grid(k, P.nbricks, 256);
+    void *argv[] = {const_cast<GDev *>(&P), &V, &F, &ZE, &rho};
+    e = hipLaunchKernel(k, dim3(grid), dim3(256), argv, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// rho (mixed forms, bigcell-stationary).  rho must be cleared by the caller
+// (points of bricks no atom reaches are not written).
+hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
+                              double *rho, hipStream_t s) {
+    hipError_t e = prepare_d16(P, prec, blocks, nnz, D, s);
+    if (e != hipSuccess) return e;
+    return launch_bc(bc_kernel_for<false, false>(prec, P.shape_all), P, s, nullptr, nullptr, nullptr, rho);
+}
+
+// force/stress/E (and rho when given; rho cleared by the caller).  F and ZE
+// cleared by the caller.
+hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
+                                const double *D, double *F, double *ZE, double *rho, hipStream_t s) {
+    hipError_t e = prepare_d16(P, prec, blocks, nnz, D, s);
+    if (e != hipSuccess) return e;
+    if (rho) return launch_bc(bc_kernel_for<true, true>(prec, P.shape_all), P, s, V, F, ZE, rho);
+    return launch_bc(bc_kernel_for<true, false>(prec, P.shape_all), P, s, V, F, ZE, nullptr);
+}
+
+void gint_prime_grids_bc(int prec) {
+    for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
+        gint_resident_blocks(bc_kernel_for<false, false>(prec, shape), 256);
+        gint_resident_blocks(bc_kernel_for<true, false>(prec, shape), 256);
+        gint_resident_blocks(bc_kernel_for<true, true>(prec, shape), 256);
+    }
+}

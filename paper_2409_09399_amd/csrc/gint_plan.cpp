@@ -132,9 +132,214 @@ struct PairOut {
     std::vector<GBig> bcs;
 };
 
+// (I, J, R) -> block index, open addressing with linear probing.
+struct BlockIndex {
+    struct Slot {
+        int i, j, r0, r1, r2, b;
+    };
+    std::vector<Slot> t;
+    size_t mask = 0;
+    static size_t hash(int i, int j, int r0, int r1, int r2) {
+        return BlockKeyHash()(BlockKey{i, j, r0, r1, r2});
+    }
+    void build(int nblk, const int *bi, const int *bj, const int *br) {
+        size_t cap = 16;
+        while (cap < 2 * (size_t)nblk + 16) cap <<= 1;
+        t.assign(cap, Slot{0, 0, 0, 0, 0, -1});
+        mask = cap - 1;
+        for (int b = 0; b < nblk; ++b) {
+            size_t h = hash(bi[b], bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2]) & mask;
+            while (t[h].b >= 0) h = (h + 1) & mask;
+            t[h] = Slot{bi[b], bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2], b};
+        }
+    }
+    int find(int i, int j, int r0, int r1, int r2) const {
+        size_t h = hash(i, j, r0, r1, r2) & mask;
+        for (;;) {
+            const Slot &s = t[h];
+            if (s.b < 0) return -1;
+            if (s.i == i && s.j == j && s.r0 == r0 && s.r1 == r1 && s.r2 == r2) return s.b;
+            h = (h + 1) & mask;
+        }
+    }
+};
+
+// One (brick, atom image) incidence found by the union enumeration.
+struct Incidence {
+    int brick, atom, t0, t1, t2;
+    bool operator<(const Incidence &o) const {
+        if (brick != o.brick) return brick < o.brick;
+        if (atom != o.atom) return atom < o.atom;
+        if (t0 != o.t0) return t0 < o.t0;
+        if (t1 != o.t1) return t1 < o.t1;
+        return t2 < o.t2;
+    }
+};
+
+unsigned worker_count() {
+    unsigned nth = std::thread::hardware_concurrency();
+    if (nth == 0) nth = 4;
+    return std::min(nth, 16u);
+}
+
+// Runs f(k) for k in [0, n) on worker threads (dynamic assignment).
+template <class F>
+void parallel_for(int n, F f) {
+    std::atomic<int> next{0};
+    auto body = [&]() {
+        for (;;) {
+            const int k = next.fetch_add(1);
+            if (k >= n) break;
+            f(k);
+        }
+    };
+    const unsigned nth = std::min<unsigned>(worker_count(), (unsigned)std::max(1, n));
+    std::vector<std::thread> th;
+    for (unsigned t = 1; t < nth; ++t) th.emplace_back(body);
+    body();
+    for (auto &t : th) t.join();
+}
+
+// Bricks of B[0] x B[1] x B[2] bigcells tiling the grid [0, N) of one
+// system, the atom images whose sphere (radius rcut) reaches a bigcell of
+// each brick (tested against the bigcell's circumscribed sphere, radius Rb),
+// and the pair tables.  Bricks no atom reaches (vacuum) are left out: their
+// points get rho = 0 from the clear that precedes every rho pass.  Returns
+// GINT_OK, or 1 if some brick's union exceeds GINT_UMAX (the caller retries
+// with smaller bricks).
+int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vector<double> &rc,
+                 const std::vector<int> &spec, const BlockIndex &bidx, const int B[3], double Rb, HostPlan &hp) {
+    const int natom = (int)pos.size();
+    int nbk[3];
+    for (int k = 0; k < 3; ++k) nbk[k] = (G.N[k] + 4 * B[k] - 1) / (4 * B[k]);
+    const long long nbricks_all = (long long)nbk[0] * nbk[1] * nbk[2];
+    if (nbricks_all > 0x7fffffffLL) return GINT_EINVAL;
+    std::vector<std::vector<Incidence>> found(natom);
+    parallel_for(natom, [&](int a) {
+        const double ext_r = rc[a] + Rb;
+        double u[3], ext[3];
+        for (int k = 0; k < 3; ++k) {
+            u[k] = G.frac(pos[a], k);
+            ext[k] = ext_r / G.spacing[k];
+        }
+        int tlo[3], thi[3];
+        for (int k = 0; k < 3; ++k) {
+            tlo[k] = (int)std::floor(-u[k] - ext[k]) - 1;
+            thi[k] = (int)std::ceil(1.0 - u[k] + ext[k]) + 1;
+        }
+        const double R2 = ext_r * ext_r;
+        std::vector<Incidence> &out = found[a];
+        for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+            for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+                for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+                    const int t[3] = {t0, t1, t2};
+                    const Vec3 p = add(pos[a], G.lat(t0, t1, t2));
+                    long long blo[3], bhi[3];
+                    bool empty = false;
+                    for (int k = 0; k < 3; ++k) {
+                        const double uu = u[k] + t[k];
+                        long long nlo = (long long)std::floor((uu - ext[k]) * G.N[k]) - 4;
+                        long long nhi = (long long)std::ceil((uu + ext[k]) * G.N[k]) + 4;
+                        nlo = std::max(nlo, 0LL);
+                        nhi = std::min(nhi, (long long)G.N[k] - 1);
+                        if (nlo > nhi) { empty = true; break; }
+                        blo[k] = nlo / (4 * B[k]);
+                        bhi[k] = nhi / (4 * B[k]);
+                    }
+                    if (empty) continue;
+                    for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
+                        for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
+                            for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
+                                bool hit = false;
+                                for (int s0 = 0; s0 < B[0] && !hit; ++s0) {
+                                    const long long n0 = 4 * (b0 * B[0] + s0);
+                                    if (n0 >= G.N[0]) break;
+                                    for (int s1 = 0; s1 < B[1] && !hit; ++s1) {
+                                        const long long n1 = 4 * (b1 * B[1] + s1);
+                                        if (n1 >= G.N[1]) break;
+                                        for (int s2 = 0; s2 < B[2] && !hit; ++s2) {
+                                            const long long n2 = 4 * (b2 * B[2] + s2);
+                                            if (n2 >= G.N[2]) break;
+                                            const Vec3 d = sub(G.point(n0 + 1.5, n1 + 1.5, n2 + 1.5), p);
+                                            if (dot(d, d) < R2) hit = true;
+                                        }
+                                    }
+                                }
+                                if (hit)
+                                    out.push_back(Incidence{(int)((b0 * nbk[1] + b1) * nbk[2] + b2), a, t0, t1, t2});
+                            }
+                }
+    });
+    std::vector<Incidence> all;
+    {
+        size_t n = 0;
+        for (auto &v : found) n += v.size();
+        all.reserve(n);
+        for (auto &v : found) {
+            all.insert(all.end(), v.begin(), v.end());
+            std::vector<Incidence>().swap(v);
+        }
+    }
+    std::sort(all.begin(), all.end());
+    hp.bricks.clear();
+    hp.uatoms.clear();
+    std::vector<int> utrip;       // image triple of each union entry (pair-table lookups)
+    std::vector<int> uatom_idx;
+    for (size_t k = 0; k < all.size();) {
+        size_t e = k;
+        while (e < all.size() && all[e].brick == all[k].brick) ++e;
+        const int n = (int)(e - k);
+        if (n > GINT_UMAX) return 1;
+        const int bid = all[k].brick;
+        GBrick br{};
+        const int b2 = bid % nbk[2], b1 = (bid / nbk[2]) % nbk[1], b0 = bid / (nbk[1] * nbk[2]);
+        const int bb[3] = {b0, b1, b2};
+        for (int q = 0; q < 3; ++q) {
+            br.o[q] = 4 * B[q] * bb[q];
+            br.nb[q] = std::min(B[q], (G.N[q] - br.o[q] + 3) / 4);
+        }
+        br.sys = 0;
+        br.u_begin = (int)hp.uatoms.size();
+        br.u_count = n;
+        for (size_t q = k; q < e; ++q) {
+            const Incidence &in = all[q];
+            const Vec3 p = add(pos[in.atom], G.lat(in.t0, in.t1, in.t2));
+            hp.uatoms.push_back(GUAtom{p.x, p.y, p.z, in.atom, spec[in.atom]});
+            utrip.push_back(in.t0);
+            utrip.push_back(in.t1);
+            utrip.push_back(in.t2);
+            uatom_idx.push_back(in.atom);
+        }
+        hp.bricks.push_back(br);
+        k = e;
+    }
+    long long total = 0;
+    for (GBrick &br : hp.bricks) {
+        br.pt_off = total;
+        total += (long long)br.u_count * br.u_count;
+    }
+    hp.ptab.assign((size_t)total, -1);
+    parallel_for((int)hp.bricks.size(), [&](int k) {
+        const GBrick &br = hp.bricks[k];
+        const int n = br.u_count;
+        int *pt = hp.ptab.data() + br.pt_off;
+        for (int i = 0; i < n; ++i) {
+            const int ui = br.u_begin + i;
+            const int *ti = &utrip[3 * (size_t)ui];
+            for (int j = 0; j < n; ++j) {
+                const int uj = br.u_begin + j;
+                const int *tj = &utrip[3 * (size_t)uj];
+                pt[(size_t)i * n + j] = bidx.find(uatom_idx[ui], uatom_idx[uj], tj[0] - ti[0], tj[1] - ti[1], tj[2] - ti[2]);
+            }
+        }
+    });
+    (void)natom;
+    return GINT_OK;
+}
+
 }  // namespace
 
-static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &hp) {
+static int build_one(const gint_system *sys, const gint_options *opt, bool bricks, HostPlan &hp) {
     auto fail = [&](int code, const char *msg) {
         hp.error = msg;
         return code;
@@ -234,8 +439,14 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
     if (hp.tab.size() > (size_t)0x7fffffff) return fail(GINT_EINVAL, "radial tables too large");
     // FP32 tables by knot interval: [interval k][chan][c0, c1, c2, c3], the
     // coefficients of the same cubic Hermite interpolant as a polynomial in
-    // t = r/dr - k, p = c0 + c1 t + c2 t^2 + c3 t^3, computed in FP64 and
-    // rounded once.  In this form p' = (c1 + 2 c2 t + 3 c3 t^2)/dr has no
+    // t = r/dr - k, p = c0 + c1 t + c2 t^2 + c3 t^3, times the normalisation
+    // constant of the channel's solid harmonics (K_0 = 1/(2 sqrt(pi)),
+    // K_1 = sqrt(3/(4 pi)), K_2 = sqrt(15/pi)/2), computed in FP64 and
+    // rounded once.  Folding K_l in here keeps it out of the FP32 arithmetic:
+    // rounded to FP32 on its own, K_0 and K_2 carry a relative error of
+    // 5e-8 that every orbital of the channel would share, a bias that does
+    // not average out over grid points (it doubled on diagonal H elements,
+    // where both operands carry it).  In this form p' = (c1 + 2 c2 t + 3 c3 t^2)/dr has no
     // cancellation: the weighted-knot form h00' f_k + h01' f_k+1 cancels two
     // terms of size 6 f/dr, which in FP32 cost about 8 bits of the gradient.
     // 16-byte records, so one evaluation reads each channel with one 16-byte
@@ -249,16 +460,19 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         float *o = hp.tab32.data() + 2 * (size_t)g.tab_off;
         for (size_t k = 0; k < K; ++k) {
             for (size_t c = 0; c < C; ++c) {
+                const int l = g.chan_l[c];
+                const double kl = l == 0 ? 0.5 / std::sqrt(M_PI)
+                                         : (l == 1 ? std::sqrt(3.0 / (4.0 * M_PI)) : 0.5 * std::sqrt(15.0 / M_PI));
                 float *r = o + (k * C + c) * 4;
                 const double f0 = t[(k * C + c) * 2], d0 = g.dr * t[(k * C + c) * 2 + 1];
                 if (k + 1 < K) {
                     const double f1 = t[((k + 1) * C + c) * 2], d1 = g.dr * t[((k + 1) * C + c) * 2 + 1];
-                    r[0] = (float)f0;
-                    r[1] = (float)d0;
-                    r[2] = (float)(3.0 * (f1 - f0) - 2.0 * d0 - d1);
-                    r[3] = (float)(2.0 * (f0 - f1) + d0 + d1);
+                    r[0] = (float)(kl * f0);
+                    r[1] = (float)(kl * d0);
+                    r[2] = (float)(kl * (3.0 * (f1 - f0) - 2.0 * d0 - d1));
+                    r[3] = (float)(kl * (2.0 * (f0 - f1) + d0 + d1));
                 } else {
-                    r[0] = (float)f0;
+                    r[0] = (float)(kl * f0);
                     r[1] = r[2] = r[3] = 0.f;
                 }
             }
@@ -315,7 +529,8 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
         const int *r = sys->blk_r + 3 * b;
         const long long ot = bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]);
         if (ot < 0) return fail(GINT_EPATTERN, "pattern is not transpose-closed");
-        hp.blocks[b] = GBlk{sys->blk_off[b], ot, norb[sys->blk_i[b]], norb[sys->blk_j[b]], 0, 0};
+        hp.blocks[b] = GBlk{sys->blk_off[b], ot, norb[sys->blk_i[b]], norb[sys->blk_j[b]], 0, sys->blk_i[b],
+                            sys->blk_j[b], 0};
     }
     hp.nnz = nnz;
 
@@ -546,10 +761,44 @@ static int build_one(const gint_system *sys, const gint_options *opt, HostPlan &
     };
     std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
     std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
+
+    // ---- bigcell-stationary bricks.  Default shape: about 2 Bohr along each
+    // axis (anisotropic grids get anisotropic bricks), at most 8 bigcells;
+    // halved along the longest axis while a union exceeds GINT_UMAX.
+    if (bricks) {
+        int B[3];
+        for (int k = 0; k < 3; ++k) {
+            const int req = opt ? opt->brick[k] : 0;
+            if (req < 0 || req > 8) return fail(GINT_EINVAL, "brick dimension out of range (1..8)");
+            if (req > 0) {
+                B[k] = req;
+            } else {
+                const double hk = std::sqrt(dot(G.e[k], G.e[k]));
+                B[k] = (int)std::lround(2.0 / (4.0 * hk));
+                B[k] = std::max(1, std::min(8, B[k]));
+            }
+        }
+        BlockIndex bidx;
+        bidx.build(sys->nblk, sys->blk_i, sys->blk_j, sys->blk_r);
+        std::vector<int> spec(natom);
+        for (int i = 0; i < natom; ++i) spec[i] = sys->species[i];
+        for (;;) {
+            const int r = build_bricks(G, pos, rc, spec, bidx, B, Rb, hp);
+            if (r == GINT_OK) break;
+            if (r != 1) return fail(r, "grid too large for the brick index");
+            int ax = 0;
+            for (int k = 1; k < 3; ++k)
+                if (B[k] > B[ax]) ax = k;
+            if (B[ax] == 1)
+                return fail(GINT_EUNSUPPORTED, "more atom images reach one bigcell than the kernels hold (256)");
+            B[ax] = (B[ax] + 1) / 2;
+        }
+        for (int k = 0; k < 3; ++k) hp.brick[k] = B[k];
+    }
     return GINT_OK;
 }
 
-int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, HostPlan &hp) {
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp) {
     if (!sys || n_sys < 1) {
         hp.error = "no systems";
         return GINT_EINVAL;
@@ -560,7 +809,7 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
     long long tab_off = 0;
     for (int i = 0; i < n_sys; ++i) {
         HostPlan one;
-        const int rc = build_one(sys + i, opt, one);
+        const int rc = build_one(sys + i, opt, bricks, one);
         if (rc != GINT_OK) {
             hp.error = "system " + std::to_string(i) + ": " + one.error;
             return rc;
@@ -589,6 +838,8 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             b.off += nnz_off;
             b.off_t += nnz_off;
             b.sys = i;
+            b.i += atom_off;
+            b.j += atom_off;
             hp.blocks.push_back(b);
         }
         for (GSpecies sp : one.species) {
@@ -621,6 +872,30 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             hp.pairs.push_back(P);
         }
         hp.bigcells.insert(hp.bigcells.end(), one.bigcells.begin(), one.bigcells.end());
+        {
+            const int ub = (int)hp.uatoms.size();
+            const long long pb = (long long)hp.ptab.size();
+            const int blk_base = (int)(hp.blocks.size() - one.blocks.size());
+            if (hp.uatoms.size() + one.uatoms.size() > (size_t)0x7fffffff) {
+                hp.error = "too many atom images in the bricks";
+                return GINT_ENOMEM;
+            }
+            for (GBrick b : one.bricks) {
+                b.sys = i;
+                b.u_begin += ub;
+                b.pt_off += pb;
+                hp.bricks.push_back(b);
+            }
+            for (GUAtom u : one.uatoms) {
+                u.atom += atom_off;
+                u.species += species_off;
+                hp.uatoms.push_back(u);
+            }
+            hp.ptab.reserve(hp.ptab.size() + one.ptab.size());
+            for (int b : one.ptab) hp.ptab.push_back(b >= 0 ? b + blk_base : -1);
+            if (i == 0)
+                for (int k = 0; k < 3; ++k) hp.brick[k] = one.brick[k];
+        }
         for (GItem it : one.items_canon) {
             it.pair += pair_off;
             it.bc_begin += bc_off;

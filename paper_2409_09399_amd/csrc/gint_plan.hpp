@@ -19,7 +19,11 @@ struct HostPlan {
     std::vector<GItem> items_canon;  // canonical pairs, longest first
     std::vector<GItem> items_ordered;// canonical + swapped, longest first
     std::vector<GSys> sys;           // one per system
-    std::vector<GBlk> blocks;        // pattern blocks with their transposes (symmetry check)
+    std::vector<GBlk> blocks;        // pattern blocks with their transposes (symmetry check, D16 conversion)
+    std::vector<GBrick> bricks;      // bigcell-stationary bricks (rho and force), empty unless built
+    std::vector<GUAtom> uatoms;      // their atom-image unions
+    std::vector<int> ptab;           // their pair tables (block indices, -1 = none)
+    int brick[3] = {0, 0, 0};        // bigcells per brick along a1, a2, a3
     int ncanon = 0;
     int ncluster = 0;
     int natom = 0;
@@ -36,5 +40,6 @@ struct HostPlan {
 };
 
 // Builds the plan of n_sys systems (their work items merged into one queue).
+// With bricks set, also the bigcell-stationary bricks of every system.
 // Returns GINT_OK or a negative gint error code (hp.error holds a message).
-int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, HostPlan &hp);
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp);

@@ -1,7 +1,8 @@
-// Autotuner of the plan's tile shape: atoms per cluster tile and work-item
-// length, chosen by timing one full pass (Vlocal + rho + force/stress) of
-// each candidate on the caller's device (paper: parameters tuned by short
-// timed trials before the production run, "Device Performance Optimization").
+// Autotuner of the plan's tile shapes: atoms per cluster tile and work-item
+// length of the Vlocal kernel, and the brick shape of the bigcell-stationary
+// rho/force kernels, each chosen by timing its own stage on the caller's
+// device (paper: parameters tuned by short timed trials before the
+// production run, "Device Performance Optimization").
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -13,10 +14,13 @@ hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 
 namespace {
 
-// candidate (cluster_atoms, max_bigcells_per_item) in trial order; 0 = plan default
+// candidates in trial order (0 = the plan's default): (cluster_atoms,
+// max_bigcells_per_item) of Vlocal, and bricks in bigcells along a1, a2, a3
 constexpr int kCand[][2] = {{4, 0}, {3, 0}, {4, 32}, {2, 0}, {4, 128}, {3, 32}, {4, 8}, {2, 32}};
+constexpr int kBrick[][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 1}, {1, 1, 2}, {2, 1, 1}, {1, 2, 1}, {2, 2, 2}, {4, 4, 2}};
 constexpr int kNCand = (int)(sizeof(kCand) / sizeof(kCand[0]));
 static_assert(kNCand <= GINT_TUNE_MAX, "candidate list longer than the report");
+static_assert(sizeof(kBrick) / sizeof(kBrick[0]) == (size_t)kNCand, "one brick candidate per trial");
 
 struct Buffers {
     double *v = nullptr, *d = nullptr, *h = nullptr, *rho = nullptr, *f = nullptr, *sig = nullptr;
@@ -34,6 +38,21 @@ int step(gint_plan *p, Buffers &b, hipStream_t s) {
     return rc;
 }
 
+// One timed step: Vlocal between e0 and e1, rho + force/stress between e1 and e2.
+int timed_step(gint_plan *p, Buffers &b, hipStream_t s, hipEvent_t ev[3], float *vl_ms, float *rf_ms) {
+    hipError_t e = hipEventRecord(ev[0], s);
+    int rc = e == hipSuccess ? gint_vlocal(p, b.v, b.h, s) : GINT_EHIP;
+    if (rc == GINT_OK && (e = hipEventRecord(ev[1], s)) != hipSuccess) rc = GINT_EHIP;
+    if (rc == GINT_OK) rc = gint_rho(p, b.d, b.rho, nullptr, s);
+    if (rc == GINT_OK) rc = gint_force_stress(p, b.v, b.d, b.f, b.sig, nullptr, s);
+    if (rc == GINT_OK && (e = hipEventRecord(ev[2], s)) != hipSuccess) rc = GINT_EHIP;
+    if (rc == GINT_OK && (e = hipEventSynchronize(ev[2])) != hipSuccess) rc = GINT_EHIP;
+    if (rc == GINT_OK && ((e = hipEventElapsedTime(vl_ms, ev[0], ev[1])) != hipSuccess ||
+                          (e = hipEventElapsedTime(rf_ms, ev[1], ev[2])) != hipSuccess))
+        rc = GINT_EHIP;
+    return rc;
+}
+
 }  // namespace
 
 extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *opt, double budget_seconds,
@@ -44,11 +63,14 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
     gint_tune_report rep{};
     rep.best = -1;
     Buffers b;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
-        if (e0) (void)hipEventDestroy(e0);
-        return GINT_EHIP;
-    }
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    for (hipEvent_t &x : ev)
+        if (hipEventCreate(&x) != hipSuccess) {
+            for (hipEvent_t y : ev)
+                if (y) (void)hipEventDestroy(y);
+            return GINT_EHIP;
+        }
+    rep.best_brick = -1;
     int rc = GINT_OK;
     for (int c = 0; c < kNCand; ++c) {
         const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
@@ -56,6 +78,7 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
         gint_options o = *opt;
         o.cluster_atoms = kCand[c][0];
         o.max_bigcells_per_item = kCand[c][1];
+        for (int k = 0; k < 3; ++k) o.brick[k] = kBrick[c][k];
         gint_plan *p = nullptr;
         rc = gint_plan_create(&p, sys, n_sys, &o, stream);
         if (rc != GINT_OK) break;
@@ -76,35 +99,28 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
                 rc = GINT_ENOMEM;
                 break;
             }
-            rc = step(p, b, s);   // untimed: first launches load the code objects
-            if (rc != GINT_OK) {
-                gint_plan_destroy(p);
-                break;
-            }
         }
-        hipError_t e = hipEventRecord(e0, s);
-        if (e == hipSuccess) rc = step(p, b, s);
-        if (e == hipSuccess && rc == GINT_OK) e = hipEventRecord(e1, s);
-        if (e == hipSuccess && rc == GINT_OK) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess && rc == GINT_OK) e = hipEventElapsedTime(&ms, e0, e1);
+        rc = step(p, b, s);   // untimed: first launches load the code objects
+        float vl = 0.f, rf = 0.f;
+        if (rc == GINT_OK) rc = timed_step(p, b, s, ev, &vl, &rf);
         gint_plan_destroy(p);
         if (rc != GINT_OK) break;
-        if (e != hipSuccess) {
-            rc = GINT_EHIP;
-            break;
-        }
-        rep.cluster_atoms[rep.ntrials] = o.cluster_atoms;
-        rep.max_bigcells_per_item[rep.ntrials] = o.max_bigcells_per_item;
-        rep.step_ms[rep.ntrials] = ms;
-        if (rep.best < 0 || ms < rep.step_ms[rep.best]) rep.best = rep.ntrials;
+        const int t = rep.ntrials;
+        rep.cluster_atoms[t] = o.cluster_atoms;
+        rep.max_bigcells_per_item[t] = o.max_bigcells_per_item;
+        for (int k = 0; k < 3; ++k) rep.brick[t][k] = q.decomposition == GINT_DECOMP_BIGCELL ? q.brick[k] : 0;
+        rep.vlocal_ms[t] = vl;
+        rep.rho_force_ms[t] = rf;
+        rep.step_ms[t] = (double)vl + (double)rf;
+        if (rep.best < 0 || vl < rep.vlocal_ms[rep.best]) rep.best = t;
+        if (rep.best_brick < 0 || rf < rep.rho_force_ms[rep.best_brick]) rep.best_brick = t;
         ++rep.ntrials;
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
     if (rc != GINT_OK) return rc;
     opt->cluster_atoms = rep.cluster_atoms[rep.best];
     opt->max_bigcells_per_item = rep.max_bigcells_per_item[rep.best];
+    for (int k = 0; k < 3; ++k) opt->brick[k] = rep.brick[rep.best_brick][k];
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     *report = rep;
     return GINT_OK;

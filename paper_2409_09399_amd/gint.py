@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libgint.so")
 
 GINT_OK, GINT_EINVAL, GINT_EPATTERN, GINT_ENOMEM, GINT_EHIP, GINT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GINT_FP64, GINT_MIXED_FP16X3, GINT_MIXED_BF16X3 = 0, 1, 2
+GINT_DECOMP_DEFAULT, GINT_DECOMP_CLUSTER_PAIRS, GINT_DECOMP_BIGCELL = 0, 1, 2
 
 
 class GintError(RuntimeError):
@@ -42,14 +43,16 @@ class gint_system(C.Structure):
 
 class gint_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("cluster_atoms", C.c_int), ("max_bigcells_per_item", C.c_int),
-                ("device_mib_cap", C.c_int), ("reserved", C.c_int * 4)]
+                ("device_mib_cap", C.c_int), ("brick", C.c_int * 3), ("decomposition", C.c_int)]
 
 
 class gint_sizes(C.Structure):
     _fields_ = [("ngrid", C.c_int64), ("nnz", C.c_int64), ("natom", C.c_int), ("ncluster", C.c_int),
                 ("npairs", C.c_int64), ("nitems", C.c_int64), ("nbigcells", C.c_int64),
                 ("work_units", C.c_double), ("volume", C.c_double), ("device_bytes", C.c_int64),
-                ("precision", C.c_int), ("build_seconds", C.c_double), ("n_sys", C.c_int)]
+                ("precision", C.c_int), ("build_seconds", C.c_double), ("n_sys", C.c_int),
+                ("decomposition", C.c_int), ("brick", C.c_int * 3), ("nbricks", C.c_int64),
+                ("brick_images", C.c_int64)]
 
 
 class gint_system_sizes(C.Structure):
@@ -61,8 +64,10 @@ GINT_TUNE_MAX = 16
 
 
 class gint_tune_report(C.Structure):
-    _fields_ = [("ntrials", C.c_int), ("best", C.c_int), ("cluster_atoms", C.c_int * GINT_TUNE_MAX),
-                ("max_bigcells_per_item", C.c_int * GINT_TUNE_MAX), ("step_ms", C.c_double * GINT_TUNE_MAX),
+    _fields_ = [("ntrials", C.c_int), ("best", C.c_int), ("best_brick", C.c_int),
+                ("cluster_atoms", C.c_int * GINT_TUNE_MAX), ("max_bigcells_per_item", C.c_int * GINT_TUNE_MAX),
+                ("brick", (C.c_int * 3) * GINT_TUNE_MAX), ("vlocal_ms", C.c_double * GINT_TUNE_MAX),
+                ("rho_force_ms", C.c_double * GINT_TUNE_MAX), ("step_ms", C.c_double * GINT_TUNE_MAX),
                 ("seconds", C.c_double)]
 
 
@@ -70,7 +75,8 @@ EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", 
             "gint_check_symmetry", "gint_energy",
             "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
-            "gint_last_hip_error", "gint_peaks_measure"]
+            "gint_last_hip_error", "gint_peaks_measure",
+            "gint_scf_create", "gint_scf_solve", "gint_scf_fold_gamma", "gint_scf_destroy"]
 
 
 def _hip_runtimes():
@@ -112,6 +118,11 @@ def _load():
     lib.gint_energy.argtypes = [P, P, P, P, P]
     lib.gint_peaks_measure.argtypes = [C.POINTER(C.c_double), P]
     lib.gint_check_symmetry.argtypes = [P, P, P, P]
+    lib.gint_scf_create.argtypes = [C.POINTER(C.c_void_p), P, C.POINTER(C.c_int64)]
+    lib.gint_scf_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P, P, P, P]
+    lib.gint_scf_fold_gamma.argtypes = [P, P, P, P]
+    lib.gint_scf_destroy.argtypes = [P]
+    lib.gint_scf_destroy.restype = None
     lib.gint_plan_query.argtypes = [P, C.POINTER(gint_sizes)]
     lib.gint_plan_query_system.argtypes = [P, C.c_int, C.POINTER(gint_system_sizes)]
     lib.gint_plan_destroy.argtypes = [P]
@@ -212,13 +223,17 @@ class Plan:
     of system i are given by `systems[i]` (dicts of offsets and sizes)."""
 
     def __init__(self, system, cluster_atoms: int = 0, max_bigcells_per_item: int = 0,
-                 precision: int = GINT_FP64, stream=None, device_mib_cap: int = 0):
+                 precision: int = GINT_FP64, stream=None, device_mib_cap: int = 0, brick=(0, 0, 0),
+                 decomposition: int = GINT_DECOMP_DEFAULT):
         sts, keep, n = _marshal_batch(system)
         opt = gint_options()
         opt.precision = precision
         opt.cluster_atoms = cluster_atoms
         opt.max_bigcells_per_item = max_bigcells_per_item
         opt.device_mib_cap = device_mib_cap
+        for k in range(3):
+            opt.brick[k] = int(brick[k])
+        opt.decomposition = decomposition
         ptr = C.c_void_p()
         rc = _lib.gint_plan_create(C.byref(ptr), sts, n, C.byref(opt),
                                    _stream(stream) if stream is not None else None)
@@ -253,7 +268,11 @@ class Plan:
 
     def info(self) -> dict:
         q = self.sizes
-        return {f: getattr(q, f) for f, _ in gint_sizes._fields_}
+        out = {}
+        for f, _ in gint_sizes._fields_:
+            v = getattr(q, f)
+            out[f] = tuple(v) if f == "brick" else v
+        return out
 
 
 def gint_vlocal(plan: Plan, v_loc, h_vals, stream=None):
@@ -278,6 +297,44 @@ def gint_energy(plan: Plan, v_loc, rho, energy, stream=None):
     """E = w sum_g V_g rho_g per system into energy (device, n_sys)."""
     _check(_lib.gint_energy(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"), _dev_ptr(rho, plan.ngrid, "rho"),
                             _dev_ptr(energy, plan.n_sys, "energy"), _stream(stream)), "gint_energy")
+
+
+class Scf:
+    """One SCF step at the Gamma point on the device (include/gint_scf.h):
+    H(R), S(R) -> H^G c = e S^G c (rocSOLVER) -> occupations -> D(R)."""
+
+    def __init__(self, plan: Plan):
+        ptr = C.c_void_p()
+        n = C.c_int64()
+        _check(_lib.gint_scf_create(C.byref(ptr), plan._p, C.byref(n)), "gint_scf_create")
+        self._p = ptr
+        self.plan = plan
+        self.n = int(n.value)
+
+    def solve(self, h_vals, s_vals, n_electrons: float, kT: float, eigvals, occupations, d_vals, info=None,
+              stream=None):
+        p = self.plan
+        inf = info.data_ptr() if info is not None else None
+        _check(_lib.gint_scf_solve(self._p, _dev_ptr(h_vals, p.nnz, "h_vals"), _dev_ptr(s_vals, p.nnz, "s_vals"),
+                                   float(n_electrons), float(kT), _dev_ptr(eigvals, self.n, "eigvals"),
+                                   _dev_ptr(occupations, self.n, "occupations"), _dev_ptr(d_vals, p.nnz, "d_vals"),
+                                   inf, _stream(stream)), "gint_scf_solve")
+
+    def fold_gamma(self, vals, dense, stream=None):
+        _check(_lib.gint_scf_fold_gamma(self._p, _dev_ptr(vals, self.plan.nnz, "vals"),
+                                        _dev_ptr(dense, self.n * self.n, "dense"), _stream(stream)),
+               "gint_scf_fold_gamma")
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.gint_scf_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def measure_peaks(stream=None) -> dict:
@@ -337,20 +394,25 @@ class Graph:
             pass
 
 
-def autotune(system, precision: int = GINT_FP64, budget_seconds: float = 2.0, stream=None):
-    """Pick cluster_atoms and max_bigcells_per_item by timed trials
-    (gint_autotune).  Returns (options dict for Plan, report dict)."""
+def autotune(system, precision: int = GINT_FP64, budget_seconds: float = 2.0, stream=None,
+             decomposition: int = GINT_DECOMP_DEFAULT):
+    """Pick the Vlocal cluster tile (cluster_atoms, max_bigcells_per_item) and
+    the rho/force brick shape by timed trials (gint_autotune).  Returns
+    (options dict for Plan, report dict)."""
     sts, keep, n = _marshal_batch(system)
     opt = gint_options()
     opt.precision = precision
+    opt.decomposition = decomposition
     rep = gint_tune_report()
     _check(_lib.gint_autotune(sts, n, C.byref(opt), float(budget_seconds), _stream(stream), C.byref(rep)),
            "gint_autotune")
     trials = [{"cluster_atoms": rep.cluster_atoms[k], "max_bigcells_per_item": rep.max_bigcells_per_item[k],
+               "brick": tuple(rep.brick[k]), "vlocal_ms": rep.vlocal_ms[k], "rho_force_ms": rep.rho_force_ms[k],
                "step_ms": rep.step_ms[k]} for k in range(rep.ntrials)]
     return ({"cluster_atoms": int(opt.cluster_atoms), "max_bigcells_per_item": int(opt.max_bigcells_per_item),
-             "precision": precision},
-            {"trials": trials, "best": int(rep.best), "seconds": float(rep.seconds)})
+             "brick": tuple(int(x) for x in opt.brick), "decomposition": decomposition, "precision": precision},
+            {"trials": trials, "best": int(rep.best), "best_brick": int(rep.best_brick),
+             "seconds": float(rep.seconds)})
 
 
 def gint_rho_force_stress(plan: Plan, v_loc, d_vals, rho, force, stress, n_elec=None, energy=None, stream=None):

@@ -117,7 +117,9 @@ def test_energy_from_library_and_plan_reuse(torch_dev):
     plan1 = A._plan_cache["entry"][2]
     E2 = A.energy(s, v, d, tau)
     assert A._plan_cache["entry"][2] is plan1          # same geometry: plan reused
-    assert float(E) == float(E2)
+    # rho is accumulated with FP64 atomics, so two calls agree to rounding
+    # (the order of the additions varies), not bit for bit
+    assert abs(float(E) - float(E2)) <= 1e-13 * abs(float(E2))
     plan = G.Plan(s)
     F = torch.empty(3 * s.natom, dtype=torch.float64, device=dev)
     sig = torch.empty(9, dtype=torch.float64, device=dev)
@@ -129,6 +131,7 @@ def test_energy_from_library_and_plan_reuse(torch_dev):
     g1 = tau.grad.clone()
     tau.grad = None
     E.backward()
-    assert torch.equal(g1, tau.grad)
+    # the force kernel reduces with atomics too: equal to rounding
+    assert torch.allclose(g1, tau.grad, rtol=0, atol=1e-13 * float(g1.abs().max()))
     assert torch.allclose(-g1.reshape(-1), F, rtol=0, atol=1e-12 * float(F.abs().max()))
     plan.close()

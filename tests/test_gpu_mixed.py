@@ -34,8 +34,13 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def run(G, torch, dev, s, precision):
-    plan = G.Plan(s, precision=precision)
+def run(G, torch, dev, s, precision, decomposition=0, brick=(0, 0, 0), fused=True):
+    """Vlocal, rho and force/stress of one system; with fused, also the
+    one-pass rho + force/stress (out["fused"]), checked by the callers at the
+    same bounds (in the mixed forms the two passes round differently)."""
+    plan = G.Plan(s, precision=precision, decomposition=decomposition, brick=brick)
+    print(f"[mixed] plan {s.name} prec={precision} decomposition={plan.sizes.decomposition} "
+          f"brick={tuple(plan.sizes.brick)} nbricks={plan.sizes.nbricks}", flush=True)
     v = torch.tensor(s.v, device=dev)
     d = torch.tensor(s.d, device=dev)
     h = torch.full((s.nnz,), float("nan"), dtype=torch.float64, device=dev)
@@ -49,6 +54,15 @@ def run(G, torch, dev, s, precision):
     torch.cuda.synchronize()
     out = dict(h=h.cpu().numpy(), rho=rho.cpu().numpy(), F=F.cpu().numpy().reshape(-1, 3),
                sig=sig.cpu().numpy().reshape(3, 3), E=float(E.cpu()[0]))
+    if fused:
+        rho2 = torch.full((s.ngrid,), float("nan"), dtype=torch.float64, device=dev)
+        F2 = torch.full((s.natom * 3,), float("nan"), dtype=torch.float64, device=dev)
+        sig2 = torch.full((9,), float("nan"), dtype=torch.float64, device=dev)
+        E2 = torch.zeros(1, dtype=torch.float64, device=dev)
+        G.gint_rho_force_stress(plan, v, d, rho2, F2, sig2, energy=E2)
+        torch.cuda.synchronize()
+        out["fused"] = dict(h=out["h"], rho=rho2.cpu().numpy(), F=F2.cpu().numpy().reshape(-1, 3),
+                            sig=sig2.cpu().numpy().reshape(3, 3), E=float(E2.cpu()[0]))
     plan.close()
     return out
 
@@ -84,8 +98,13 @@ def record(name, prec, errs):
             f.write(json.dumps({"case": name, "precision": prec, **errs}) + "\n")
 
 
+DECOMP = [1, 2]
+DECOMP_IDS = ["cluster_pairs", "bigcell"]
+
+
+@pytest.mark.parametrize("decomp", DECOMP, ids=DECOMP_IDS)
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
-def test_mixed_diamond(torch_dev, oracle_mod, prec):
+def test_mixed_diamond(torch_dev, oracle_mod, prec, decomp):
     from paper_2409_09399_amd import gint as G
     from paper_2409_09399_amd import inputs as I
     torch, dev = torch_dev
@@ -93,11 +112,13 @@ def test_mixed_diamond(torch_dev, oracle_mod, prec):
     o = oracle_mod.Oracle(s)
     F, Z, E, sig = o.force_stress()
     ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
-    errs = errors(run(G, torch, dev, s, prec), ref)
-    print("[mixed] diamond", prec, errs, flush=True)
-    record("diamond8", prec, errs)
+    got = run(G, torch, dev, s, prec, decomposition=decomp)
+    errs, errf = errors(got, ref), errors(got["fused"], ref)
+    print("[mixed] diamond", prec, decomp, errs, "fused", errf, flush=True)
+    record(f"diamond8/{DECOMP_IDS[decomp - 1]}", prec, errs)
     for k, b in BOUNDS[prec].items():
         assert errs[k] <= b, (k, errs[k], b)
+        assert errf[k] <= b, ("fused", k, errf[k], b)
 
 
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
@@ -165,10 +186,15 @@ def test_tbg148_coarse_full_oracle(torch_dev, oracle_mod):
             assert errs[k] <= b, (prec, k, errs[k], b)
 
 
+@pytest.mark.parametrize("case", [(1, (0, 0, 0)), (2, (0, 0, 0)), (2, (1, 1, 1)), (2, (3, 1, 2))],
+                         ids=["cluster_pairs", "bigcell", "bigcell_1x1x1", "bigcell_3x1x2"])
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
-def test_mixed_three_species(torch_dev, oracle_mod, prec):
-    """Species with different channel sets (spd, sp, 2s2p1d) in a skewed cell,
-    against the full oracle, at the same bounds."""
+def test_mixed_three_species(torch_dev, oracle_mod, prec, case):
+    """Species with different channel sets (spd, sp, 2s2p1d) in a skewed cell
+    on a grid that is not a multiple of 4 along any axis, against the full
+    oracle, at the same bounds; both decompositions, and bricks of several
+    shapes."""
+    decomp, brick = case
     from paper_2409_09399_amd import gint as G
     from paper_2409_09399_amd import inputs as I
     torch, dev = torch_dev
@@ -177,15 +203,17 @@ def test_mixed_three_species(torch_dev, oracle_mod, prec):
            I.make_species("Z", "2s2p1d", 5.0, 0.01, rng)]
     cell = np.array([[5.1, 0.0, 0.0], [1.2, 4.6, 0.0], [0.4, -0.7, 5.5]])
     pos = rng.uniform(0, 1, size=(5, 3)) @ cell
-    grid = (20, 18, 22)
+    grid = (21, 18, 22)
     millers = I.random_millers_box(rng, 8, 2)
     v = I.plane_wave_potential(grid, millers, np.full(8, 0.3), rng.uniform(0, 6.28, 8))
     s = I.assemble(cell, pos, np.array([0, 1, 2, 1, 0]), sps, grid, v, rng, name="mixed5")
     o = oracle_mod.Oracle(s)
     F, Z, E, sig = o.force_stress()
     ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
-    errs = errors(run(G, torch, dev, s, prec), ref)
-    print("[mixed] three species", prec, errs, flush=True)
-    record("mixed5", prec, errs)
+    got = run(G, torch, dev, s, prec, decomposition=decomp, brick=brick)
+    errs, errf = errors(got, ref), errors(got["fused"], ref)
+    print("[mixed] three species", prec, case, errs, "fused", errf, flush=True)
+    record(f"mixed5/{DECOMP_IDS[decomp - 1]}/{brick}", prec, errs)
     for k, b in BOUNDS[prec].items():
         assert errs[k] <= b, (k, errs[k], b)
+        assert errf[k] <= b, ("fused", k, errf[k], b)
