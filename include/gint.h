@@ -216,6 +216,21 @@ int gint_check_symmetry(gint_plan *p, const double *d_vals, double *max_asym, vo
  * overwritten. */
 int gint_energy(gint_plan *p, const double *v_loc, const double *rho, double *energy, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same E
+ * as gint_energy, from the same two-pass reduction in the same order (equal
+ * bit for bit), but its scratch (the partial sums, 256 doubles per system)
+ * is a static device array of 1 MiB in the library, so the call allocates
+ * nothing and writes no plan state.  Each GPU holds its own copy of that
+ * array for the life of the process; its address is looked up once per
+ * device on the first call made with that device current.  Every call on a
+ * GPU shares that GPU's array: calls that overlap on one GPU (several
+ * streams or threads) race and must be serialised by the caller.  Plans with
+ * n_sys > 512 (more partial sums than the array holds) are rejected with
+ * GINT_ENOMEM before anything is enqueued.  Arguments as for gint_energy. */
+int gint_energy_noalloc(gint_plan *p, const double *v_loc, const double *rho, double *energy,
+                        void *stream);
+
 /* W = sum_g n_orb(g)^2 (grid points x ordered orbital pairs within rcut),
  * the unit of work of the throughput metric, counted exactly from the plan's
  * neighbour lists.  w_out: device f64[n_sys], overwritten. */

@@ -32,6 +32,7 @@ hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const 
                                 double *rho, hipStream_t s);
 hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
                               double *rho, hipStream_t s);
+hipError_t gint_static_scratch(void **ptr, size_t *bytes);
 hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
                                 const double *D, double *F, double *ZE, double *rho, hipStream_t s);
 void gint_prime_grids_bc(int prec);
@@ -348,6 +349,23 @@ int gint_energy(gint_plan *p, const double *v_loc, const double *rho, double *en
     if (!p || !v_loc || !rho || !energy) return GINT_EINVAL;
     if (const int rc = check_device(p)) return rc;
     const hipError_t e = gint_launch_seg_sum(p->canon, v_loc, rho, p->part, kParts, energy, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e);
+    return GINT_OK;
+}
+
+// E as gint_energy, with the partial sums in the library's static device
+// scratch instead of the plan's workspace: no allocation, no plan state
+// written.
+int gint_energy_noalloc(gint_plan *p, const double *v_loc, const double *rho, double *energy, void *stream) {
+    if (!p || !v_loc || !rho || !energy) return GINT_EINVAL;
+    if (const int rc = check_device(p)) return rc;
+    const size_t need = (size_t)p->n_sys * kParts * sizeof(double);
+    void *scr = nullptr;
+    size_t cap = 0;
+    hipError_t e = gint_static_scratch(&scr, &cap);
+    if (e != hipSuccess) return hip_fail(e);
+    if (need > cap) return GINT_ENOMEM;
+    e = gint_launch_seg_sum(p->canon, v_loc, rho, (double *)scr, kParts, energy, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }

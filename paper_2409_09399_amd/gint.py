@@ -72,7 +72,7 @@ class gint_tune_report(C.Structure):
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
-            "gint_check_symmetry", "gint_energy",
+            "gint_check_symmetry", "gint_energy", "gint_energy_noalloc",
             "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
             "gint_last_hip_error", "gint_peaks_measure",
@@ -116,6 +116,7 @@ def _load():
     lib.gint_rho_force_stress.argtypes = [P] * 9
     lib.gint_work_units.argtypes = [P, P, P]
     lib.gint_energy.argtypes = [P, P, P, P, P]
+    lib.gint_energy_noalloc.argtypes = [P, P, P, P, P]
     lib.gint_peaks_measure.argtypes = [C.POINTER(C.c_double), P]
     lib.gint_check_symmetry.argtypes = [P, P, P, P]
     lib.gint_scf_create.argtypes = [C.POINTER(C.c_void_p), P, C.POINTER(C.c_int64)]
@@ -297,6 +298,14 @@ def gint_energy(plan: Plan, v_loc, rho, energy, stream=None):
     """E = w sum_g V_g rho_g per system into energy (device, n_sys)."""
     _check(_lib.gint_energy(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"), _dev_ptr(rho, plan.ngrid, "rho"),
                             _dev_ptr(energy, plan.n_sys, "energy"), _stream(stream)), "gint_energy")
+
+
+def gint_energy_noalloc(plan: Plan, v_loc, rho, energy, stream=None):
+    """gint_energy with its partial sums in the library's static device
+    scratch (no allocation, no plan workspace; calls on one GPU must not
+    overlap)."""
+    _check(_lib.gint_energy_noalloc(plan._p, _dev_ptr(v_loc, plan.ngrid, "v_loc"), _dev_ptr(rho, plan.ngrid, "rho"),
+                                    _dev_ptr(energy, plan.n_sys, "energy"), _stream(stream)), "gint_energy_noalloc")
 
 
 class Scf:
