@@ -147,6 +147,7 @@ def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, aut
     t = time.perf_counter()
     plan = G.Plan(target, precision=prec, **opts)
     plan_s = time.perf_counter() - t
+    decomposition = int(plan.sizes.decomposition)
     log(f"[bench] plan {DTYPES[prec]} {plan.info()} wall {plan_s:.2f} s")
     h, rho, ne, F, sig, E, Wt = (out[k] for k in ("h", "rho", "ne", "F", "sig", "E", "W"))
     G.gint_work_units(plan, Wt)
@@ -210,14 +211,28 @@ def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, aut
         f"step {elapsed / steps * 1e3:.2f} ms{' (graph)' if graph else ''}")
     plan.close()
     return {"value": W * steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "kernel_ms": kern_ms,
+            "decomposition": decomposition,
             "fused_rho_force_stress_ms": fused_ms, "W": W, "plan_seconds": plan_s, "options": opts,
             "autotune": tune, "steps": steps, "warmup": warmup, "graph": graph}
 
 
 PROFILE = os.path.join(ROOT, "profiles", "gint_tbg868_counters.md")
-KERNEL_NAMES = {0: {"vlocal": "k_vlocal", "rho": "k_rho", "force_stress": "k_force<false>"},
-                1: {"vlocal": "k_vlocal_mx<fp16>", "rho": "k_rho_mx<fp16>", "force_stress": "k_force_mx<fp16,false>"},
-                2: {"vlocal": "k_vlocal_mx<bf16>", "rho": "k_rho_mx<bf16>", "force_stress": "k_force_mx<bf16,false>"}}
+# the kernel that serves each stage, by precision form and decomposition
+# (gint_sizes.decomposition: 1 cluster pairs, 2 bricks, 3 bricks for rho and
+# force only)
+def kernel_names(prec, decomposition):
+    if prec == 0:
+        return {"vlocal": "k_vlocal", "rho": "k_rho", "force_stress": "k_force<false>"}
+    t = "fp16" if prec == 1 else "bf16"
+    pairs = {"vlocal": f"k_vlocal_mx<{t}>", "rho": f"k_rho_mx<{t}>", "force_stress": f"k_force_mx<{t},false>"}
+    bricks = {"vlocal": f"k_bcv_mx<{t}>", "rho": f"k_bc_mx<{t},rho>", "force_stress": f"k_bc_mx<{t},force>"}
+    if decomposition == 2:
+        return bricks
+    if decomposition == 3:
+        return dict(bricks, vlocal=pairs["vlocal"])
+    return pairs
+
+
 # flops per MFMA instruction of each form's contraction
 MFMA_FLOPS = {0: 2 * 16 * 16 * 4, 1: 2 * 16 * 16 * 32, 2: 2 * 16 * 16 * 32}
 
@@ -227,15 +242,16 @@ def sources_sha256(prec):
     counter profile)."""
     import hashlib
     base = os.path.join(ROOT, "paper_2409_09399_amd", "csrc")
-    main = "gint_kernels.hip" if prec == 0 else "gint_kernels_mixed.hip"
+    files = (["gint_kernels.hip"] if prec == 0 else ["gint_kernels_mixed.hip", "gint_kernels_bc.hip", "gint_mixed.h"]) \
+        + ["gint_device.h", "gint_internal.h"]
     h = hashlib.sha256()
-    for f in (main, "gint_device.h", "gint_internal.h"):
+    for f in files:
         with open(os.path.join(base, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profiled_counters(cfg, prec, key):
+def profiled_counters(cfg, prec, key, decomposition):
     """Per-launch counters of a kernel from the committed rocprofv3 summary
     of the bilayer workload (HBM bytes from FETCH_SIZE and WRITE_SIZE
     calibrated with a plain copy; instruction counts), or None when the
@@ -248,7 +264,7 @@ def profiled_counters(cfg, prec, key):
         m = re.search(r"<!-- traffic (\[.*\]) -->", fh.read())
     if not m:
         return None
-    name, sha = KERNEL_NAMES[prec].get(key), sources_sha256(prec)
+    name, sha = kernel_names(prec, decomposition).get(key), sources_sha256(prec)
     for r in json.loads(m.group(1)):
         if r["kernel"] == name and r.get("sources_sha256") == sha:
             return r
@@ -270,11 +286,12 @@ def roofline(form, prec, cfg, peaks):
         measured = peaks["mfma_f64"] if prec == 0 else peaks["mfma_f16"]
     t = km[dom] * 1e-3
     achieved = 2.0 * form["W"] / t / 1e12
-    r = {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-         "frac": achieved / peak, "peak_measured": measured,
+    dec = form.get("decomposition", 1)
+    r = {"bound": "mfma", "kernel": kernel_names(prec, dec)[dom], "stage": dom, "achieved": achieved, "peak": peak,
+         "unit": "TFLOP/s", "frac": achieved / peak, "peak_measured": measured,
          "frac_measured": (achieved / measured) if measured else None,
          "algorithmic_flops": 2.0 * form["W"], "duration_ms": km[dom], "traffic": None}
-    c = profiled_counters(cfg, prec, dom)
+    c = profiled_counters(cfg, prec, dom, dec)
     if c:
         traffic = c["read_bytes"] + c["write_bytes"]
         r["traffic"] = traffic
@@ -340,8 +357,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the 10,444-atom and 64-crystal records")
     ap.add_argument("--extra-steps", type=int, default=2)
-    ap.add_argument("--decomposition", choices=["default", "cluster_pairs", "bigcell"], default="default",
-                    help="work decomposition of rho and the force pass")
+    ap.add_argument("--decomposition", choices=["default", "cluster_pairs", "bigcell", "bigcell_rho_force"],
+                    default="default", help="work decomposition of the integrals")
     ap.add_argument("--brick", type=int, nargs=3, default=[0, 0, 0], help="bigcells per brick (0 = plan's choice)")
     ap.add_argument("--cluster-atoms", type=int, default=0)
     ap.add_argument("--max-bigcells", type=int, default=0)
@@ -387,7 +404,8 @@ def main():
 
     prec = PRECISIONS[args.precision]
     opts = dict(cluster_atoms=args.cluster_atoms, max_bigcells_per_item=args.max_bigcells,
-                decomposition={"default": 0, "cluster_pairs": 1, "bigcell": 2}[args.decomposition],
+                decomposition={"default": 0, "cluster_pairs": 1, "bigcell": 2,
+                               "bigcell_rho_force": 3}[args.decomposition],
                 brick=tuple(args.brick))
     out_main = alloc(torch, dev, systems)
     main_form = run_form(G, torch, systems, prec, args.steps, args.warmup, v, d, out_main, graph=args.graph,

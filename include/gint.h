@@ -116,14 +116,19 @@ typedef struct {
     int decomposition;       /* GINT_DECOMP_*: how rho and the force are divided into work */
 } gint_options;
 
-/* Work decomposition of rho and the force/stress pass (Vlocal always runs
- * over cluster pairs).  CLUSTER_PAIRS: output-stationary cluster-pair items,
- * every orbital evaluated once per cluster pair that needs it.  BIGCELL:
- * bigcell-stationary bricks (the paper's grid batches, "Computational
- * Collaboration Between Host and Device"): every orbital evaluated once per
- * bigcell, rho written once per point without atomics; available in the
- * mixed forms.  DEFAULT: BIGCELL for the mixed forms, CLUSTER_PAIRS for FP64. */
-enum { GINT_DECOMP_DEFAULT = 0, GINT_DECOMP_CLUSTER_PAIRS = 1, GINT_DECOMP_BIGCELL = 2 };
+/* Work decomposition of the three integrals.  CLUSTER_PAIRS:
+ * output-stationary cluster-pair items, every orbital evaluated once per
+ * cluster pair that needs it.  BIGCELL: bigcell-stationary bricks (the
+ * paper's grid batches, "Computational Collaboration Between Host and
+ * Device"): rho and the force pass evaluate every orbital once per bigcell
+ * and write rho once per point without atomics; Vlocal evaluates each
+ * orbital once per bigcell and chunk pair of the brick's atom images and adds
+ * each H block once per brick.  BIGCELL_RHO_FORCE: bricks for rho and the
+ * force pass, cluster pairs for Vlocal.  The brick forms exist in the mixed
+ * precisions.  DEFAULT: BIGCELL_RHO_FORCE for the mixed forms (measured
+ * fastest), CLUSTER_PAIRS for FP64. */
+enum { GINT_DECOMP_DEFAULT = 0, GINT_DECOMP_CLUSTER_PAIRS = 1, GINT_DECOMP_BIGCELL = 2,
+       GINT_DECOMP_BIGCELL_RHO_FORCE = 3 };
 
 /* Sizes of a plan (host struct filled by gint_plan_query). */
 typedef struct {
@@ -140,7 +145,7 @@ typedef struct {
     int precision;           /* the plan's precision form */
     double build_seconds;    /* host time of gint_plan_create */
     int n_sys;               /* systems in the plan (packed buffers when > 1) */
-    int decomposition;       /* GINT_DECOMP_CLUSTER_PAIRS or GINT_DECOMP_BIGCELL (rho and force) */
+    int decomposition;       /* the GINT_DECOMP_* in use (never DEFAULT) */
     int brick[3];            /* bigcells per brick (bigcell-stationary plans; of system 0) */
     int64_t nbricks;         /* bricks with at least one atom image (bigcell-stationary plans) */
     int64_t brick_images;    /* atom images summed over the bricks' unions */

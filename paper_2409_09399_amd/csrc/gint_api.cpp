@@ -23,6 +23,7 @@ hipError_t gint_launch_seg_sum(const GDev &P, const double *x, const double *y, 
                                double *out, hipStream_t s);
 hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
                                      hipStream_t s);
+hipError_t gint_static_scratch(void **ptr, size_t *bytes);
 void gint_prime_grids_fp64();
 void gint_prime_grids_mx(int prec);
 hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
@@ -32,10 +33,12 @@ hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const 
                                 double *rho, hipStream_t s);
 hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
                               double *rho, hipStream_t s);
-hipError_t gint_static_scratch(void **ptr, size_t *bytes);
 hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
                                 const double *D, double *F, double *ZE, double *rho, hipStream_t s);
 void gint_prime_grids_bc(int prec);
+hipError_t gint_launch_vlocal_bc(const GDev &P, int prec, const GBlk *blocks, const double *V, double *H,
+                                 hipStream_t s);
+hipError_t gint_launch_absmax(const double *x, long long n, double *out, hipStream_t s);
 
 namespace {
 thread_local int g_last_hip = 0;
@@ -104,10 +107,13 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     const int prec = opt ? opt->precision : GINT_FP64;
     if (prec != GINT_FP64 && prec != GINT_MIXED_FP16X3 && prec != GINT_MIXED_BF16X3) return GINT_EUNSUPPORTED;
     const int decomp = opt ? opt->decomposition : GINT_DECOMP_DEFAULT;
-    if (decomp != GINT_DECOMP_DEFAULT && decomp != GINT_DECOMP_CLUSTER_PAIRS && decomp != GINT_DECOMP_BIGCELL)
-        return GINT_EINVAL;
-    if (decomp == GINT_DECOMP_BIGCELL && prec == GINT_FP64) return GINT_EUNSUPPORTED;
+    if (decomp < GINT_DECOMP_DEFAULT || decomp > GINT_DECOMP_BIGCELL_RHO_FORCE) return GINT_EINVAL;
+    if ((decomp == GINT_DECOMP_BIGCELL || decomp == GINT_DECOMP_BIGCELL_RHO_FORCE) && prec == GINT_FP64)
+        return GINT_EUNSUPPORTED;
     const bool bc = prec != GINT_FP64 && decomp != GINT_DECOMP_CLUSTER_PAIRS;
+    // the default keeps Vlocal on cluster pairs: on the bilayers its brick
+    // form is slower (it stages each chunk pair's images once per bigcell)
+    const bool bc_vlocal = bc && decomp == GINT_DECOMP_BIGCELL;
     const auto t0 = std::chrono::steady_clock::now();
     HostPlan hp;
     int rc;
@@ -120,9 +126,10 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     }
     if (rc != GINT_OK) return rc;
     if (hp.items_canon.size() > 0x7fffffffu || hp.items_ordered.size() > 0x7fffffffu) return GINT_ENOMEM;
-    // workspace: [0] work counter (an int in the first 4 bytes), [1] max |V|,
-    // [2] max |D|, then ZE, then partial sums
-    std::vector<double> wsinit(3 + (size_t)n_sys * (10 + kParts), 0.0);
+    // workspace: [0, 4) work counters (eight ints: one queue per XCD for the
+    // brick kernels, the first for the others), [4] max |V|, [5] max |D|,
+    // then ZE, then partial sums
+    std::vector<double> wsinit(6 + (size_t)n_sys * (10 + kParts), 0.0);
     const size_t d16_bytes = bc ? hp.blocks.size() * (size_t)1024 : 0;
     if (bc && hp.blocks.size() > 0x7fffffffu) return GINT_ENOMEM;
     if (opt && opt->device_mib_cap > 0) {
@@ -173,6 +180,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         total += p->d16.bytes;
     }
     p->bc = bc;
+    p->bc_vlocal = bc_vlocal;
     p->n_sys = n_sys;
     p->sys_host = hp.sys;
     p->atom_norb.resize(hp.atoms.size());
@@ -184,7 +192,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     if (prec != GINT_FP64) gint_prime_grids_mx(prec);
     if (bc) gint_prime_grids_bc(prec);
     p->counter = (int *)p->ws.p;
-    p->ZE = (double *)p->ws.p + 3;
+    p->ZE = (double *)p->ws.p + 6;
     p->part = p->ZE + 10 * n_sys;
 
     GDev d{};
@@ -214,8 +222,8 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     d.shape_all = hp.species.empty() ? GINT_SHAPE_ANY : hp.species[0].shape;
     for (const GSpecies &g : hp.species)
         if (g.shape != d.shape_all) d.shape_all = GINT_SHAPE_ANY;
-    d.vmax = (const double *)p->ws.p + 1;
-    d.dmax = (const double *)p->ws.p + 2;
+    d.vmax = (const double *)p->ws.p + 4;
+    d.dmax = (const double *)p->ws.p + 5;
     if (bc) {
         d.bricks = (const GBrick *)p->bricks.p;
         d.uatoms = (const GUAtom *)p->uatoms.p;
@@ -244,7 +252,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     s.device_bytes = (int64_t)total;
     s.precision = prec;
     s.n_sys = n_sys;
-    s.decomposition = bc ? GINT_DECOMP_BIGCELL : GINT_DECOMP_CLUSTER_PAIRS;
+    s.decomposition = !bc ? GINT_DECOMP_CLUSTER_PAIRS : (bc_vlocal ? GINT_DECOMP_BIGCELL : GINT_DECOMP_BIGCELL_RHO_FORCE);
     s.nbricks = (int64_t)hp.bricks.size();
     s.brick_images = (int64_t)hp.uatoms.size();
     for (int k = 0; k < 3; ++k) s.brick[k] = hp.brick[k];
@@ -260,8 +268,16 @@ int gint_vlocal(gint_plan *p, const double *v_loc, double *h_vals, void *stream)
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = gint_launch_fill(h_vals, p->sizes.nnz, 0.0, s);
     if (e != hipSuccess) return hip_fail(e);
-    e = p->precision == GINT_FP64 ? gint_launch_vlocal(p->canon, v_loc, h_vals, s)
-                                  : gint_launch_vlocal_mx(p->canon, p->precision, v_loc, p->sizes.ngrid, h_vals, s);
+    if (p->precision == GINT_FP64) {
+        e = gint_launch_vlocal(p->canon, v_loc, h_vals, s);
+    } else if (p->bc_vlocal) {
+        e = gint_launch_fill(const_cast<double *>(p->canon.vmax), 1, 0.0, s);
+        if (e == hipSuccess) e = gint_launch_absmax(v_loc, p->sizes.ngrid, const_cast<double *>(p->canon.vmax), s);
+        if (e == hipSuccess)
+            e = gint_launch_vlocal_bc(p->canon, p->precision, (const GBlk *)p->blocks.p, v_loc, h_vals, s);
+    } else {
+        e = gint_launch_vlocal_mx(p->canon, p->precision, v_loc, p->sizes.ngrid, h_vals, s);
+    }
     if (e != hipSuccess) return hip_fail(e);
     return GINT_OK;
 }

@@ -101,6 +101,34 @@ __device__ __attribute__((always_inline)) inline void stage_row(const GDev &P, c
     }
 }
 
+// Work claim with one queue per XCD.  The bricks are in spatial order; queue
+// q holds the q-th eighth of the list, and workgroup b (which the dispatcher
+// places on XCD b mod 8) serves queue b mod 8 first, so the bricks an XCD
+// works on at any time are neighbours and share their D blocks in that XCD's
+// L2.  An exhausted queue is remembered in *done; then the other queues are
+// served in turn.  Returns -1 when every queue is empty.  counters: eight
+// ints, zero at launch.
+__device__ inline int claim_brick(int *counters, int nbricks, int *slot, unsigned *done) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int x = blockIdx.x & 7;
+        int got = -1;
+        for (int k = 0; k < 8 && got < 0; ++k) {
+            const int q = (x + k) & 7;
+            if ((*done >> q) & 1u) continue;
+            const int b0 = (int)((long long)nbricks * q / 8), b1 = (int)((long long)nbricks * (q + 1) / 8);
+            const int i = b1 > b0 ? atomicAdd(counters + q, 1) : 0;
+            if (i < b1 - b0)
+                got = b0 + i;
+            else
+                *done |= 1u << q;
+        }
+        *slot = got;
+    }
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*slot);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -124,13 +152,15 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
     __shared__ double zred[4][10];
     __shared__ int s_nact;
     __shared__ int s_item;
+    __shared__ unsigned s_done;
     const int lane = threadIdx.x & 63, w = wave_id();
     const float sphi = (float)P0.phi_scale;
     const float unscale = 1.f / (sphi * pow2_scale(*cst(P0.dmax)));
     const unsigned short *__restrict__ d16 = P0.d16;
+    if (threadIdx.x == 0) s_done = 0u;
     for (;;) {
-        const int item_ = claim_item(P0.counter, &s_item);
-        if (item_ >= P0.nbricks) break;
+        const int item_ = claim_brick(P0.counter, P0.nbricks, &s_item, &s_done);
+        if (item_ < 0) break;
         const GBrick bk = ldc(P0.bricks + item_);
         GDev P = P0;
         bind_system(P, bk.sys);
@@ -373,6 +403,180 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
 }
 
 // ---------------------------------------------------------------------------
+// H_IJR (Eq. 2), mixed precision, bigcell-stationary.  The brick's union is
+// cut into chunks of eight images; for each chunk pair (a <= b) the
+// workgroup sweeps the brick's bigcells, staging phi of chunk a (the MFMA A
+// operand, [slot][orbital][point]) and V phi of chunk b (B operand), and
+// accumulates the 8 x 8 tiles H(i, j) = sum_p phi_i(p) V_p phi_j(p) in FP32
+// registers across the brick (each wave owns the tiles of two i images).
+// Then every tile is added once to its pattern block (I_i, J_j, T_j - T_i)
+// and, for i != j, transposed to (J_j, I_i, T_i - T_j), with FP64 atomics.
+// Tiles of a chunk with itself are computed for i <= j only.
+// ---------------------------------------------------------------------------
+constexpr int BV_C = 8;   // images per chunk
+
+template <class T, int KS>
+__global__ __launch_bounds__(256, 2) void k_bcv_mx(GDev P0, const GBlk *__restrict__ blk, const double *__restrict__ V0,
+                                                   double *__restrict__ H) {
+    typedef Split16<T> S;
+    typedef typename S::vec vec;
+    __shared__ __attribute__((aligned(16))) T tA[2][BV_C][16][TSTR];
+    __shared__ __attribute__((aligned(16))) T tB[2][BV_C][16][TSTR];
+    __shared__ unsigned long long actA[BV_C], actB[BV_C];
+    __shared__ int s_item;
+    __shared__ unsigned s_done;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    // A = phi sphi, B = V phi sB, both below 2^13 in magnitude
+    const float sphi = (float)P0.phi_scale;
+    const float sB = pow2_scale(*cst(P0.vmax) * (8192.0 / P0.phi_scale));
+    const double unscale = 1.0 / ((double)sphi * (double)sB);
+    if (threadIdx.x == 0) s_done = 0u;
+    for (;;) {
+        const int item_ = claim_brick(P0.counter, P0.nbricks, &s_item, &s_done);
+        if (item_ < 0) break;
+        const GBrick bk = ldc(P0.bricks + item_);
+        GDev P = P0;
+        bind_system(P, bk.sys);
+        CSys &SY = cst(P0.sys)[bk.sys];
+        const int n = bk.u_count;
+        const GUAtom *U = P0.uatoms + bk.u_begin;
+        const cptr<int> pt = cst(P0.ptab + bk.pt_off);
+        const double *V = V0 + SY.g_off;
+        const int nch = (n + BV_C - 1) / BV_C;
+        for (int ca = 0; ca < nch; ++ca)
+        for (int cb = ca; cb < nch; ++cb) {
+            f4v c[2][BV_C];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int jb = 0; jb < BV_C; ++jb) c[a][jb] = (f4v){0.f, 0.f, 0.f, 0.f};
+            unsigned touched = 0u;   // bit 8 a + jb: the tile got a product
+            for (int s0 = 0; s0 < bk.nb[0]; ++s0)
+            for (int s1 = 0; s1 < bk.nb[1]; ++s1)
+            for (int s2 = 0; s2 < bk.nb[2]; ++s2) {
+                const int n0 = bk.o[0] + 4 * s0 + (lane >> 4), n1 = bk.o[1] + 4 * s1 + ((lane >> 2) & 3),
+                          n2 = bk.o[2] + 4 * s2 + (lane & 3);
+                const bool inside = n0 < P.N[0] && n1 < P.N[1] && n2 < P.N[2];
+                P3 r;
+                r.x = n0 * P.e[0][0] + n1 * P.e[1][0] + n2 * P.e[2][0];
+                r.y = n0 * P.e[0][1] + n1 * P.e[1][1] + n2 * P.e[2][1];
+                r.z = n0 * P.e[0][2] + n1 * P.e[1][2] + n2 * P.e[2][2];
+                r.g = inside ? ((long long)n0 * P.N[1] + n1) * P.N[2] + n2 : 0;
+                const float vg = inside ? (float)V[r.g] * sB : 0.f;
+                // stage: wave w writes slots 2w and 2w+1 of both tiles
+#pragma unroll
+                for (int side = 0; side < 2; ++side) {
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const int slot = 2 * w + q;
+                        const int idx = (side == 0 ? ca : cb) * BV_C + slot;
+                        T(*tile)[BV_C][16][TSTR] = side == 0 ? tA : tB;
+                        unsigned long long *act = side == 0 ? actA : actB;
+                        if (idx >= n) {
+                            if (lane == 0) act[slot] = 0ull;
+                            continue;
+                        }
+                        const Slot su = uslot(U, idx);
+                        const Disp d = disp_at(P, r, su);
+                        const bool in = inside && d.in;
+                        const unsigned long long m = __ballot(in);
+                        if (lane == 0) act[slot] = m;
+                        // taken by every lane, before the branch: a ballot inside
+                        // the inactive branch would see only inactive lanes
+                        const bool zero_half = half_active(in);
+                        if (in) {
+                            CSpecies &sp = cst(P.species)[su.species];
+                            const float scale = side == 0 ? sphi : vg;
+                            with_shape<KS>(sp, [&](auto shp) {
+                                constexpr int SH = decltype(shp)::value;
+                                eval32<SH>(sp, P.tab32, d.x, d.y, d.z, d.kn, scale, [&](int mu, float v) {
+                                    T hi, lo;
+                                    if constexpr (SH != GINT_SHAPE_ANY) {
+                                        // padding rows reach only output rows or columns
+                                        // beyond the orbital count, which are never stored
+                                        if (mu >= ChanShape<SH>::norb) return;
+                                        S::split_mix(v, hi, lo);
+                                    } else {
+                                        S::split(v, hi, lo);
+                                    }
+                                    tile[0][slot][mu][lane] = hi;
+                                    tile[1][slot][mu][lane] = lo;
+                                });
+                            });
+                        } else if (zero_half) {
+                            // zeros only where a 32-point k-step of this slot is read
+#pragma unroll
+                            for (int mu = 0; mu < rows_used<KS>(); ++mu) {
+                                tile[0][slot][mu][lane] = (T)0.f;
+                                tile[1][slot][mu][lane] = (T)0.f;
+                            }
+                        }
+                    }
+                }
+                __syncthreads();
+                const int row = lane & 15, col = 8 * (lane >> 4);
+#pragma unroll
+                for (int a = 0; a < 2; ++a) {
+                    const int il = 2 * w + a;
+                    if (ca * BV_C + il >= n) continue;
+                    const unsigned long long mi = uniform64(actA[il]);
+                    if (mi == 0ull) continue;
+#pragma unroll
+                    for (int jb = 0; jb < BV_C; ++jb) {
+                        if (cb * BV_C + jb >= n) break;
+                        if (ca == cb && jb < il) continue;
+                        const unsigned long long mm = mi & uniform64(actB[jb]);
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) {
+                            if (!((mm >> (32 * kk)) & 0xffffffffull)) continue;
+                            const vec ahi = *(const vec *)&tA[0][il][row][32 * kk + col];
+                            const vec alo = *(const vec *)&tA[1][il][row][32 * kk + col];
+                            const vec bhi = *(const vec *)&tB[0][jb][row][32 * kk + col];
+                            const vec blo = *(const vec *)&tB[1][jb][row][32 * kk + col];
+                            c[a][jb] = S::mfma(ahi, bhi, c[a][jb]);
+                            c[a][jb] = S::mfma(ahi, blo, c[a][jb]);
+                            c[a][jb] = S::mfma(alo, bhi, c[a][jb]);
+                            touched |= 1u << (8 * a + jb);
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
+            const int nu = lane & 15;
+#pragma unroll
+            for (int a = 0; a < 2; ++a) {
+#pragma unroll
+                for (int jb = 0; jb < BV_C; ++jb) {
+                    if (!((touched >> (8 * a + jb)) & 1u)) continue;
+                    const int i = ca * BV_C + 2 * w + a, j = cb * BV_C + jb;
+                    const int b = pt[(long long)i * n + j];
+                    const int bt = i != j ? pt[(long long)j * n + i] : -1;
+                    if (b >= 0) {
+                        const GBlk k = ldc(blk + b);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int mu = 4 * (lane >> 4) + q;
+                            if (mu < k.ni && nu < k.nj)
+                                atomicAdd(H + k.off + (long long)mu * k.nj + nu, P.w * unscale * (double)c[a][jb][q]);
+                        }
+                    }
+                    if (bt >= 0) {
+                        const GBlk k = ldc(blk + bt);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int mu = 4 * (lane >> 4) + q;
+                            if (mu < k.nj && nu < k.ni)
+                                atomicAdd(H + k.off + (long long)nu * k.nj + mu, P.w * unscale * (double)c[a][jb][q]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 int gint_persistent_grid(const void *kernel, int nitems, int threads);
@@ -411,7 +615,7 @@ hipError_t prepare_d16(const GDev &P, int prec, const GBlk *blocks, long long nn
 
 hipError_t launch_bc(const void *k, const GDev &P, hipStream_t s, const double *V, double *F, double *ZE, double *rho) {
     if (P.nbricks <= 0) return hipSuccess;
-    hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
+    hipError_t e = gint_launch_fill((double *)P.counter, 4, 0.0, s);   // the eight queue counters
     if (e != hipSuccess) return e;
     const int grid = gint_persistent_grid(k, P.nbricks, 256);
     void *argv[] = {const_cast<GDev *>(&P), &V, &F, &ZE, &rho};
@@ -441,10 +645,36 @@ hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, lon
     return launch_bc(bc_kernel_for<true, false>(prec, P.shape_all), P, s, V, F, ZE, nullptr);
 }
 
+// H (mixed forms, bigcell-stationary): P.vmax must hold max |V| of this call
+// and H must be cleared by the caller.
+hipError_t gint_launch_vlocal_bc(const GDev &P, int prec, const GBlk *blocks, const double *V, double *H,
+                                 hipStream_t s) {
+    if (P.nbricks <= 0) return hipSuccess;
+    const bool fixed = P.shape_all == GINT_SHAPE_2S2P1D;
+    const void *k = prec == 2 ? (fixed ? (const void *)k_bcv_mx<__bf16, GINT_SHAPE_2S2P1D>
+                                       : (const void *)k_bcv_mx<__bf16, GINT_SHAPE_ANY>)
+                              : (fixed ? (const void *)k_bcv_mx<_Float16, GINT_SHAPE_2S2P1D>
+                                       : (const void *)k_bcv_mx<_Float16, GINT_SHAPE_ANY>);
+    hipError_t e = gint_launch_fill((double *)P.counter, 4, 0.0, s);   // the eight queue counters
+    if (e != hipSuccess) return e;
+    const int grid = gint_persistent_grid(k, P.nbricks, 256);
+    void *argv[] = {const_cast<GDev *>(&P), &blocks, &V, &H};
+    e = hipLaunchKernel(k, dim3(grid), dim3(256), argv, 0, s);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
 void gint_prime_grids_bc(int prec) {
     for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
         gint_resident_blocks(bc_kernel_for<false, false>(prec, shape), 256);
         gint_resident_blocks(bc_kernel_for<true, false>(prec, shape), 256);
         gint_resident_blocks(bc_kernel_for<true, true>(prec, shape), 256);
+    }
+    if (prec == 2) {
+        gint_resident_blocks((const void *)k_bcv_mx<__bf16, GINT_SHAPE_2S2P1D>, 256);
+        gint_resident_blocks((const void *)k_bcv_mx<__bf16, GINT_SHAPE_ANY>, 256);
+    } else {
+        gint_resident_blocks((const void *)k_bcv_mx<_Float16, GINT_SHAPE_2S2P1D>, 256);
+        gint_resident_blocks((const void *)k_bcv_mx<_Float16, GINT_SHAPE_ANY>, 256);
     }
 }

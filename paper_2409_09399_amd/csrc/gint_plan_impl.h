@@ -22,6 +22,7 @@ struct gint_plan {
     DevBuf species, atoms, tab, tab32, pairs, bigcells, items_canon, items_ordered, sys, ws;
     DevBuf bricks, uatoms, ptab, d16;   // bigcell-stationary path (rho and force)
     bool bc = false;                    // rho and force run over bricks
+    bool bc_vlocal = false;             // and Vlocal too
     int precision = GINT_FP64;
     int n_sys = 1;
     int *counter = nullptr;    // work counter of the persistent launches

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_PKG, "libgint.so")
 
 GINT_OK, GINT_EINVAL, GINT_EPATTERN, GINT_ENOMEM, GINT_EHIP, GINT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 GINT_FP64, GINT_MIXED_FP16X3, GINT_MIXED_BF16X3 = 0, 1, 2
-GINT_DECOMP_DEFAULT, GINT_DECOMP_CLUSTER_PAIRS, GINT_DECOMP_BIGCELL = 0, 1, 2
+GINT_DECOMP_DEFAULT, GINT_DECOMP_CLUSTER_PAIRS, GINT_DECOMP_BIGCELL, GINT_DECOMP_BIGCELL_RHO_FORCE = 0, 1, 2, 3
 
 
 class GintError(RuntimeError):

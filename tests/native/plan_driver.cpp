@@ -5,6 +5,7 @@
 // grid points, every atom image within rcut of the point must be in the
 // union of the point's brick, and for every two such images the pair table
 // must name the pattern block (I, J, T_J - T_I).  Test infrastructure only.
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -39,9 +40,10 @@ int fail(const char *what, long a = 0, long b = 0) {
 
 int main(int argc, char **argv) {
     if (argc < 2) {
-        std::fprintf(stderr, "usage: %s <dir> [b0 b1 b2]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s <dir> [b0 b1 b2 [nocheck]]\n", argv[0]);
         return 2;
     }
+    const bool check = argc < 6;
     const std::string dir = argv[1];
     long natom, nspecies, nblk, ngrid, nnz, nchan, knots, mode;
     {
@@ -95,15 +97,22 @@ int main(int argc, char **argv) {
     sys.blk_off = off64.data();
     gint_options opt{};
     opt.precision = GINT_MIXED_FP16X3;
-    if (argc == 5)
+    if (argc >= 5)
         for (int k = 0; k < 3; ++k) opt.brick[k] = std::atoi(argv[2 + k]);
     HostPlan hp;
+    const auto t0 = std::chrono::steady_clock::now();
     const int rc = gint_build_host_plan(&sys, 1, &opt, true, hp);
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc != GINT_OK) {
         std::fprintf(stderr, "plan error %d: %s\n", rc, hp.error.c_str());
         return 1;
     }
     const int B[3] = {hp.brick[0], hp.brick[1], hp.brick[2]};
+    if (!check) {
+        std::printf("plan built in %.3f s: %zu pairs, %zu bricks (%d x %d x %d), %zu images, %zu pair-table entries\n",
+                    secs, hp.pairs.size(), hp.bricks.size(), B[0], B[1], B[2], hp.uatoms.size(), hp.ptab.size());
+        return 0;
+    }
 
     // brute-force checks of the bricks on sampled grid points
     std::map<std::tuple<int, int, int>, int> brick_at;

@@ -98,8 +98,8 @@ def record(name, prec, errs):
             f.write(json.dumps({"case": name, "precision": prec, **errs}) + "\n")
 
 
-DECOMP = [1, 2]
-DECOMP_IDS = ["cluster_pairs", "bigcell"]
+DECOMP = [1, 2, 3]
+DECOMP_IDS = ["cluster_pairs", "bigcell", "bigcell_rho_force"]
 
 
 @pytest.mark.parametrize("decomp", DECOMP, ids=DECOMP_IDS)
@@ -186,8 +186,8 @@ def test_tbg148_coarse_full_oracle(torch_dev, oracle_mod):
             assert errs[k] <= b, (prec, k, errs[k], b)
 
 
-@pytest.mark.parametrize("case", [(1, (0, 0, 0)), (2, (0, 0, 0)), (2, (1, 1, 1)), (2, (3, 1, 2))],
-                         ids=["cluster_pairs", "bigcell", "bigcell_1x1x1", "bigcell_3x1x2"])
+@pytest.mark.parametrize("case", [(1, (0, 0, 0)), (2, (0, 0, 0)), (2, (1, 1, 1)), (2, (3, 1, 2)), (3, (0, 0, 0))],
+                         ids=["cluster_pairs", "bigcell", "bigcell_1x1x1", "bigcell_3x1x2", "bigcell_rho_force"])
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
 def test_mixed_three_species(torch_dev, oracle_mod, prec, case):
     """Species with different channel sets (spd, sp, 2s2p1d) in a skewed cell
