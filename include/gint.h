@@ -107,7 +107,10 @@ typedef struct {
 /* Plan options; pass NULL for defaults. */
 typedef struct {
     int precision;           /* GINT_FP64, GINT_MIXED_FP16X3 or GINT_MIXED_BF16X3 */
-    int cluster_atoms;       /* atoms per cluster tile, 1..4 (0 = default 4) */
+    int cluster_atoms;       /* atoms per cluster of the cluster-pair work items, 1..8 (0 = default 4).
+                                Values above 4 select the eight-wave Vlocal kernel and are accepted
+                                only for mixed-precision plans whose rho and force run on bricks
+                                (GINT_DECOMP_DEFAULT, GINT_DECOMP_BIGCELL_RHO_FORCE); else GINT_EINVAL. */
     int max_bigcells_per_item; /* work-item length cap (0 = default) */
     int device_mib_cap;      /* device memory the plan may hold, in MiB (0 = no cap): a plan
                                 that needs more fails with GINT_ENOMEM before any HIP call */

@@ -76,7 +76,7 @@ int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
 }
 
 void release(gint_plan *p) {
-    DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->tab32, &p->pairs, &p->bigcells, &p->items_canon,
+    DevBuf *bufs[] = {&p->species, &p->atoms, &p->tab, &p->tab32, &p->pairs, &p->pairs8, &p->bigcells, &p->items_canon,
                       &p->items_ordered, &p->sys, &p->ws, &p->blocks, &p->bricks, &p->uatoms, &p->ptab, &p->d16};
     for (DevBuf *b : bufs)
         if (b->p) {
@@ -134,7 +134,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     if (bc && hp.blocks.size() > 0x7fffffffu) return GINT_ENOMEM;
     if (opt && opt->device_mib_cap > 0) {
         size_t need = upload_bytes(hp.species) + upload_bytes(hp.atoms) + upload_bytes(hp.tab) +
-                      upload_bytes(hp.tab32) + upload_bytes(hp.pairs) + upload_bytes(hp.bigcells) +
+                      upload_bytes(hp.tab32) + upload_bytes(hp.pairs) + upload_bytes(hp.pairs8) + upload_bytes(hp.bigcells) +
                       upload_bytes(hp.items_canon) + upload_bytes(hp.items_ordered) + upload_bytes(hp.sys) +
                       upload_bytes(wsinit);
         if (bc)
@@ -153,7 +153,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     size_t total = 0;
     if ((rc = upload(p->species, hp.species, total)) || (rc = upload(p->atoms, hp.atoms, total)) ||
         (rc = upload(p->tab, hp.tab, total)) || (rc = upload(p->tab32, hp.tab32, total)) ||
-        (rc = upload(p->pairs, hp.pairs, total)) ||
+        (rc = upload(p->pairs, hp.pairs, total)) || (rc = upload(p->pairs8, hp.pairs8, total)) ||
         (rc = upload(p->bigcells, hp.bigcells, total)) || (rc = upload(p->items_canon, hp.items_canon, total)) ||
         (rc = upload(p->items_ordered, hp.items_ordered, total)) || (rc = upload(p->sys, hp.sys, total)) ||
         (rc = upload(p->ws, wsinit, total))) {
@@ -200,7 +200,8 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
     d.atoms = (const GAtom *)p->atoms.p;
     d.tab = (const double *)p->tab.p;
     d.tab32 = (const float *)p->tab32.p;
-    d.pairs = (const GPair *)p->pairs.p;
+    d.pairs = hp.pairs8.empty() ? (const GPair *)p->pairs.p : nullptr;
+    d.pairs8 = hp.pairs8.empty() ? nullptr : (const GPair8 *)p->pairs8.p;
     d.bigcells = (const GBig *)p->bigcells.p;
     d.sys = (const GSys *)p->sys.p;
     d.counter = p->counter;

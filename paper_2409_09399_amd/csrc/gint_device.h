@@ -14,6 +14,7 @@
 template <class T>
 using cptr = const __attribute__((address_space(4))) T *;
 typedef const __attribute__((address_space(4))) GPair CPair;
+typedef const __attribute__((address_space(4))) GPair8 CPair8;
 typedef const __attribute__((address_space(4))) GSpecies CSpecies;
 typedef const __attribute__((address_space(4))) GSys CSys;
 typedef const __attribute__((address_space(4))) double cdouble;

@@ -13,7 +13,8 @@
 #pragma once
 #include <stdint.h>
 
-#define GINT_CL 4            // atoms per cluster (max)
+#define GINT_CL 4            // atoms per cluster of the four-wave cluster-pair kernels (max)
+#define GINT_CL8 8           // atoms per cluster of the eight-wave mixed Vlocal (max)
 #define GINT_ORB 16          // orbital slots per atom
 #define GINT_MAXCHAN 8       // radial channels per species
 #define GINT_BC 4            // bigcell edge in grid points
@@ -44,18 +45,23 @@ struct GAtom {
     int norb;
 };
 
-// One cluster pair.  hoff[i*4+j] is the element offset of block
-// (a_i -> b_j, R = TB - TA) or -1; hoff_t[i*4+j] that of (b_j -> a_i, -R).
-struct GPair {
-    int a[GINT_CL];              // atom ids, -1 = empty slot
-    int b[GINT_CL];
+// One cluster pair of clusters of at most CL atoms.  hoff[i*CL+j] is the
+// element offset of block (a_i -> b_j, R = TB - TA) or -1; hoff_t[i*CL+j]
+// that of (b_j -> a_i, -R).  Clusters of four serve every cluster-pair
+// kernel; clusters of eight serve the eight-wave mixed-precision Vlocal.
+template <int CL>
+struct GPairT {
+    int a[CL];                   // atom ids, -1 = empty slot
+    int b[CL];
     double shiftA[3];            // TA.h added to A-atom positions
     double shiftB[3];            // TB.h added to B-atom positions
     int self;                    // 1: A == B with TA == TB (tiles cover both orders)
     int sys;                     // system of a batched plan
-    long long hoff[GINT_CL * GINT_CL];
-    long long hoff_t[GINT_CL * GINT_CL];
+    long long hoff[CL * CL];
+    long long hoff_t[CL * CL];
 };
+typedef GPairT<GINT_CL> GPair;
+typedef GPairT<GINT_CL8> GPair8;
 
 struct GBig {
     int x, y, z;                 // origin point index of a bigcell (unwrapped)
@@ -127,7 +133,8 @@ struct GDev {
     const float *tab32;          // the same interpolant in FP32 by knot interval (mixed precision), times the
                                  // channel's harmonic constant K_l: [k][chan][c0, c1, c2, c3],
                                  // K_l p = c0 + c1 t + c2 t^2 + c3 t^3, at 2 tab_off
-    const GPair *pairs;
+    const GPair *pairs;          // clusters of <= 4 atoms (null when the plan has clusters of 8)
+    const GPair8 *pairs8;        // clusters of 5..8 atoms (null otherwise)
     const GBig *bigcells;
     const GItem *items;
     const GSys *sys;             // per-system geometry (one entry for a single system)

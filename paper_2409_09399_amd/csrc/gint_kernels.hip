@@ -694,14 +694,20 @@ __global__ __launch_bounds__(256, 3) void k_force(GDev P0, const double *__restr
 // ---------------------------------------------------------------------------
 // W = sum_g n_orb(g)^2 from the canonical pairs (exact in FP64: integers)
 // ---------------------------------------------------------------------------
+template <int CL>
 __global__ __launch_bounds__(256) void k_work(GDev P0, double *__restrict__ W0) {
     __shared__ double red[256];
     __shared__ int s_item;
+    const GPairT<CL> *pairs;
+    if constexpr (CL == GINT_CL8)
+        pairs = P0.pairs8;
+    else
+        pairs = P0.pairs;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
     const GItem it = ldc(P0.items + item_);
-    CPair &pr = cst(P0.pairs)[it.pair];
+    const __attribute__((address_space(4))) GPairT<CL> &pr = cst(pairs)[it.pair];
     GDev P = P0;
     bind_system(P, pr.sys);
     CSys &SY = cst(P0.sys)[pr.sys];
@@ -713,7 +719,7 @@ __global__ __launch_bounds__(256) void k_work(GDev P0, double *__restrict__ W0) 
         if (threadIdx.x < GINT_BCPTS) {
             const Pt r = bigcell_point(P, o, threadIdx.x);
             double na = 0, nb = 0;
-            for (int k = 0; k < GINT_CL; ++k) {
+            for (int k = 0; k < CL; ++k) {
                 if (pr.a[k] >= 0) {
                     const GAtom at = ldc(P.atoms + pr.a[k]);
                     const double x = r.x - at.x - pr.shiftA[0], y = r.y - at.y - pr.shiftA[1],
@@ -912,7 +918,8 @@ hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, do
 }
 
 hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s) {
-    GINT_PERSISTENT_LAUNCH(k_work, P, s, W);
+    if (P.pairs8) GINT_PERSISTENT_LAUNCH(k_work<GINT_CL8>, P, s, W);
+    GINT_PERSISTENT_LAUNCH(k_work<GINT_CL>, P, s, W);
 }
 
 hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double *D, double *out, hipStream_t s) {
@@ -949,5 +956,6 @@ void gint_prime_grids_fp64() {
     gint_resident_blocks((const void *)k_force<false, GINT_SHAPE_2S2P1D>, 256);
     gint_resident_blocks((const void *)k_force<true, GINT_SHAPE_ANY>, 256);
     gint_resident_blocks((const void *)k_force<true, GINT_SHAPE_2S2P1D>, 256);
-    gint_resident_blocks((const void *)k_work, 256);
+    gint_resident_blocks((const void *)k_work<GINT_CL>, 256);
+    gint_resident_blocks((const void *)k_work<GINT_CL8>, 256);
 }

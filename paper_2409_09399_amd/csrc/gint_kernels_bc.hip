@@ -24,14 +24,19 @@
 
 namespace {
 
-constexpr int BC_CI = 8;                    // I images per staged chunk (four 32-wide k-steps)
+constexpr int BC_WAVES = 8;                 // waves of a rho/force workgroup
+constexpr int BC_THREADS = 64 * BC_WAVES;
+constexpr int BC_CI = 8;                    // I images per staged chunk (four 32-wide k-steps), one per wave
 constexpr int BC_ROW = 16 * BC_CI + 8;      // 16-bit elements per point row of the chunk tile
 // J images per wave in one J group (their psi accumulators stay in
-// registers through the group): eight for rho, six for the force pass, whose
-// per-point gradient code needs the registers of the other two
+// registers through the group): three for rho, two for the force pass,
+// whose per-point gradient code needs more registers.  With these the
+// kernels fit about 128 VGPRs, so that two workgroups (four waves per SIMD)
+// share a CU and hide each other's table and D latency; measured on the
+// bilayer, more J per wave spills and fewer re-evaluates phi more often.
 template <bool FORCE>
 constexpr int bc_jw() {
-    return FORCE ? 6 : 8;
+    return FORCE ? 2 : 3;
 }
 constexpr int BC_PSTR = 17;                 // floats per point row of a wave's psi buffer
 
@@ -136,20 +141,20 @@ __device__ inline int claim_brick(int *counters, int nbricks, int *slot, unsigne
 // one brick per claimed work item.
 // ---------------------------------------------------------------------------
 template <class T, int KS, bool FORCE, bool RHO>
-__global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ F,
+__global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_bc_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ F,
                                                   double *__restrict__ ZE0, double *__restrict__ rho0) {
     typedef Split16<T> S;
     typedef typename S::vec vec;
     constexpr bool WRHO = !FORCE || RHO;
     constexpr int BC_JW = bc_jw<FORCE>();   // J images per wave in one J group
-    constexpr int BC_JG = 4 * BC_JW;         // J images per J group (four waves, round-robin)
+    constexpr int BC_JG = BC_WAVES * BC_JW;  // J images per J group (round-robin over the waves)
     __shared__ __attribute__((aligned(16))) T tA[2][GINT_BCPTS][BC_ROW];
-    __shared__ float psb[4][GINT_BCPTS * BC_PSTR];
+    // a wave's psi rows; after the last J group, its 64 rho partials (FP64)
+    __shared__ __attribute__((aligned(16))) float psb[BC_WAVES][GINT_BCPTS * BC_PSTR];
     __shared__ unsigned long long act[GINT_UMAX];
     __shared__ short lst[GINT_UMAX];
-    __shared__ double red[4][GINT_BCPTS];
     __shared__ double fbuf[FORCE ? GINT_UMAX : 1][3];
-    __shared__ double zred[4][10];
+    __shared__ double zred[BC_WAVES][10];
     __shared__ int s_nact;
     __shared__ int s_item;
     __shared__ unsigned s_done;
@@ -170,7 +175,7 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
         const cptr<int> pt = cst(P0.ptab + bk.pt_off);
         double z9[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, en = 0.0;
         if constexpr (FORCE) {
-            for (int i = threadIdx.x; i < n; i += 256) fbuf[i][0] = fbuf[i][1] = fbuf[i][2] = 0.0;
+            for (int i = threadIdx.x; i < n; i += BC_THREADS) fbuf[i][0] = fbuf[i][1] = fbuf[i][2] = 0.0;
         }
         for (int s0 = 0; s0 < bk.nb[0]; ++s0)
         for (int s1 = 0; s1 < bk.nb[1]; ++s1)
@@ -187,7 +192,7 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
             double vpt = 0.0;
             if (FORCE && inside) vpt = V0[SY.g_off + r.g];
             // phase 1: activity of every union image on the 64 points
-            for (int i = w; i < n; i += 4) {
+            for (int i = w; i < n; i += BC_WAVES) {
                 const Disp d = disp_at(P, r, uslot(U, i));
                 const unsigned long long m = __ballot(inside && d.in);
                 if (lane == 0) act[i] = m;
@@ -218,18 +223,17 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
                 for (int ic = 0; ic < nact; ic += BC_CI) {
                     // pair-table entries of the chunk's I images and the wave's J
                     // images, one per lane (lane 8 q + jj: I image ic + q, J image
-                    // jg + w + 4 jj), loaded before the stage so that their latency
-                    // is hidden behind it
+                    // jg + w + BC_WAVES jj), loaded before the stage so that their
+                    // latency is hidden behind it
                     int ptv = -1;
                     {
-                        const int ix = ic + (lane >> 3), jx = jg + w + 4 * (lane & 7);
+                        const int ix = ic + (lane >> 3), jx = jg + w + BC_WAVES * (lane & 7);
                         if ((lane & 7) < BC_JW && ix < nact && jx < nact)
                             ptv = P0.ptab[bk.pt_off + (long long)lst[ix] * n + lst[jx]];
                     }
-                    // stage the chunk: wave w writes slots 2w and 2w+1
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        const int slot = 2 * w + q, idx = ic + slot;
+                    // stage the chunk: wave w writes slot w
+                    {
+                        const int slot = w, idx = ic + slot;
                         T *h0 = &tA[0][lane][slot * 16];
                         T *h1 = &tA[1][lane][slot * 16];
                         if (idx < nact) {
@@ -244,53 +248,61 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
                         }
                     }
                     __syncthreads();
-                    // psi_J += phi_chunk D_sym(chunk, J) for the wave's J images: the
-                    // B operands of all four k-steps of a J are requested first
+                    // psi_J += phi_chunk D_sym(chunk, J) for the wave's J images, one
+                    // 32-wide k-step (two I images) at a time: the step's B operands
+                    // of every J are requested first, then each A fragment is read
+                    // from LDS once and serves all the wave's J
+                    int jv[BC_JW];
+                    unsigned long long mjv[BC_JW];
 #pragma unroll
                     for (int jj = 0; jj < BC_JW; ++jj) {
-                        const int jidx = jg + w + 4 * jj;
-                        if (jidx >= nact) break;
-                        const int j = __builtin_amdgcn_readfirstlane((int)lst[jidx]);
-                        const unsigned long long mj = uniform64(act[j]);
-                        vec bh[BC_CI / 2], blo[BC_CI / 2];
-                        unsigned long long mm[BC_CI / 2];
+                        const int jidx = jg + w + BC_WAVES * jj;
+                        jv[jj] = jidx < nact ? __builtin_amdgcn_readfirstlane((int)lst[jidx]) : -1;
+                        mjv[jj] = jv[jj] >= 0 ? uniform64(act[jv[jj]]) : 0ull;
+                    }
 #pragma unroll
-                        for (int s = 0; s < BC_CI / 2; ++s) {
-                            mm[s] = 0ull;
-                            const int i0x = ic + 2 * s, i1x = i0x + 1;
-                            if (i0x >= nact) continue;
-                            const int i0 = __builtin_amdgcn_readfirstlane((int)lst[i0x]);
-                            const int i1 = i1x < nact ? __builtin_amdgcn_readfirstlane((int)lst[i1x]) : -1;
+                    for (int s = 0; s < BC_CI / 2; ++s) {
+                        const int i0x = ic + 2 * s, i1x = i0x + 1;
+                        if (i0x >= nact) break;
+                        const int i0 = __builtin_amdgcn_readfirstlane((int)lst[i0x]);
+                        const int i1 = i1x < nact ? __builtin_amdgcn_readfirstlane((int)lst[i1x]) : -1;
+                        const unsigned long long mi = uniform64(act[i0] | (i1 >= 0 ? act[i1] : 0ull));
+                        vec bh[BC_JW], blo[BC_JW];
+                        unsigned long long mm[BC_JW];
+                        unsigned long long any = 0ull;
+#pragma unroll
+                        for (int jj = 0; jj < BC_JW; ++jj) {
                             const int b0 = __builtin_amdgcn_readlane(ptv, 16 * s + jj);
                             const int b1 = i1 >= 0 ? __builtin_amdgcn_readlane(ptv, 16 * s + 8 + jj) : -1;
-                            if (b0 < 0 && b1 < 0) continue;
-                            mm[s] = uniform64((act[i0] | (i1 >= 0 ? act[i1] : 0ull)) & mj);
+                            mm[jj] = (b0 >= 0 || b1 >= 0) ? (mi & mjv[jj]) : 0ull;
+                            any |= mm[jj];
                             const int bl = lane < 32 ? b0 : b1;
-                            if (bl >= 0) {
+                            if (mm[jj] != 0ull && bl >= 0) {
                                 const unsigned short *src =
                                     d16 + (size_t)bl * 512 + (lane & 15) * 16 + 8 * ((lane >> 4) & 1);
-                                bh[s] = *(const vec *)src;
-                                blo[s] = *(const vec *)(src + 256);
+                                bh[jj] = *(const vec *)src;
+                                blo[jj] = *(const vec *)(src + 256);
                             } else {
 #pragma unroll
                                 for (int e = 0; e < 8; ++e) {
-                                    bh[s][e] = (T)0.f;
-                                    blo[s][e] = (T)0.f;
+                                    bh[jj][e] = (T)0.f;
+                                    blo[jj][e] = (T)0.f;
                                 }
                             }
                         }
+                        if (any == 0ull) continue;
+                        const int col = (2 * s + (lane >> 5)) * 16 + 8 * ((lane >> 4) & 1);
 #pragma unroll
-                        for (int s = 0; s < BC_CI / 2; ++s) {
-                            if (mm[s] == 0ull) continue;
-                            const int col = (2 * s + (lane >> 5)) * 16 + 8 * ((lane >> 4) & 1);
+                        for (int t = 0; t < 4; ++t) {
+                            if (!((any >> (16 * t)) & 0xFFFFull)) continue;
+                            const vec ah = *(const vec *)&tA[0][16 * t + (lane & 15)][col];
+                            const vec al = *(const vec *)&tA[1][16 * t + (lane & 15)][col];
 #pragma unroll
-                            for (int t = 0; t < 4; ++t) {
-                                if (!((mm[s] >> (16 * t)) & 0xFFFFull)) continue;
-                                const vec ah = *(const vec *)&tA[0][16 * t + (lane & 15)][col];
-                                const vec al = *(const vec *)&tA[1][16 * t + (lane & 15)][col];
-                                c[jj][t] = S::mfma(ah, bh[s], c[jj][t]);
-                                c[jj][t] = S::mfma(ah, blo[s], c[jj][t]);
-                                c[jj][t] = S::mfma(al, bh[s], c[jj][t]);
+                            for (int jj = 0; jj < BC_JW; ++jj) {
+                                if (!((mm[jj] >> (16 * t)) & 0xFFFFull)) continue;
+                                c[jj][t] = S::mfma(ah, bh[jj], c[jj][t]);
+                                c[jj][t] = S::mfma(ah, blo[jj], c[jj][t]);
+                                c[jj][t] = S::mfma(al, bh[jj], c[jj][t]);
                             }
                         }
                     }
@@ -300,7 +312,7 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
                 float *ps = psb[w];
 #pragma unroll
                 for (int jj = 0; jj < BC_JW; ++jj) {
-                    const int jidx = jg + w + 4 * jj;
+                    const int jidx = jg + w + BC_WAVES * jj;
                     if (jidx >= nact) break;
                     const int j = __builtin_amdgcn_readfirstlane((int)lst[jidx]);
                     const unsigned long long mj = uniform64(act[j]);
@@ -364,16 +376,26 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
                 }
             }
             if constexpr (WRHO) {
-                red[w][lane] = racc;
+                // the partials go into the wave's own psi buffer, which only
+                // this wave has used since the last barrier
+                ((double *)psb[w])[lane] = racc;
                 __syncthreads();
-                if (w == 0 && inside)
-                    rho0[SY.g_off + r.g] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
+                if (w == 0 && inside) {
+                    double q[BC_WAVES];
+#pragma unroll
+                    for (int k = 0; k < BC_WAVES; ++k) q[k] = ((const double *)psb[k])[lane];
+#pragma unroll
+                    for (int h = 1; h < BC_WAVES; h *= 2)
+#pragma unroll
+                        for (int k = 0; k < BC_WAVES; k += 2 * h) q[k] += q[k + h];
+                    rho0[SY.g_off + r.g] = q[0];
+                }
             }
             __syncthreads();
         }
         if constexpr (FORCE) {
             // forces of the brick's images, then Z and E of the workgroup's points
-            for (int i = threadIdx.x; i < n; i += 256) {
+            for (int i = threadIdx.x; i < n; i += BC_THREADS) {
                 const int a = U[i].atom;
                 if (fbuf[i][0] != 0.0 || fbuf[i][1] != 0.0 || fbuf[i][2] != 0.0) {
                     atomicAdd(F + 3 * a + 0, fbuf[i][0]);
@@ -394,7 +416,14 @@ __global__ __launch_bounds__(256, 2) void k_bc_mx(GDev P0, const double *__restr
             __syncthreads();
             if (threadIdx.x < 10) {
                 const int k = threadIdx.x;
-                const double v = (zred[0][k] + zred[1][k]) + (zred[2][k] + zred[3][k]);
+                double q[BC_WAVES];
+#pragma unroll
+                for (int u = 0; u < BC_WAVES; ++u) q[u] = zred[u][k];
+#pragma unroll
+                for (int h = 1; h < BC_WAVES; h *= 2)
+#pragma unroll
+                    for (int u = 0; u < BC_WAVES; u += 2 * h) q[u] += q[u + h];
+                const double v = q[0];
                 if (v != 0.0) atomicAdd(ZE0 + 10 * bk.sys + k, v);
             }
             __syncthreads();
@@ -617,9 +646,9 @@ hipError_t launch_bc(const void *k, const GDev &P, hipStream_t s, const double *
     if (P.nbricks <= 0) return hipSuccess;
     hipError_t e = gint_launch_fill((double *)P.counter, 4, 0.0, s);   // the eight queue counters
     if (e != hipSuccess) return e;
-    const int grid = gint_persistent_grid(k, P.nbricks, 256);
+    const int grid = gint_persistent_grid(k, P.nbricks, BC_THREADS);
     void *argv[] = {const_cast<GDev *>(&P), &V, &F, &ZE, &rho};
-    e = hipLaunchKernel(k, dim3(grid), dim3(256), argv, 0, s);
+    e = hipLaunchKernel(k, dim3(grid), dim3(BC_THREADS), argv, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -666,9 +695,9 @@ hipError_t gint_launch_vlocal_bc(const GDev &P, int prec, const GBlk *blocks, co
 
 void gint_prime_grids_bc(int prec) {
     for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
-        gint_resident_blocks(bc_kernel_for<false, false>(prec, shape), 256);
-        gint_resident_blocks(bc_kernel_for<true, false>(prec, shape), 256);
-        gint_resident_blocks(bc_kernel_for<true, true>(prec, shape), 256);
+        gint_resident_blocks(bc_kernel_for<false, false>(prec, shape), BC_THREADS);
+        gint_resident_blocks(bc_kernel_for<true, false>(prec, shape), BC_THREADS);
+        gint_resident_blocks(bc_kernel_for<true, true>(prec, shape), BC_THREADS);
     }
     if (prec == 2) {
         gint_resident_blocks((const void *)k_bcv_mx<__bf16, GINT_SHAPE_2S2P1D>, 256);

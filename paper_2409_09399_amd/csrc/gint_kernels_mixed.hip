@@ -188,6 +188,175 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// H_IJR (Eq. 2), mixed precision, clusters of up to eight atoms.  Eight
+// waves: wave w evaluates A atom w and B atom w on the bigcell's 64 points
+// (one point per lane) and owns the eight tiles (a_i, b_{(w-i)&7}); two
+// k-steps of 32 points.  Against the four-atom kernel every evaluation feeds
+// twice the tiles, which is what bounds this stage: per bigcell it is VALU
+// (orbital evaluation), not MFMA, work.  The FP32 tiles of a bigcell are
+// formed four at a time and folded into FP64 accumulators.
+// ---------------------------------------------------------------------------
+template <class T, int KS>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_vlocal_mx8(
+    GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
+    typedef Split16<T> S;
+    typedef typename S::vec vec;
+    __shared__ __attribute__((aligned(16))) T tA[2][GINT_CL8][16][TSTR];
+    __shared__ __attribute__((aligned(16))) T tB[2][GINT_CL8][16][TSTR];
+    __shared__ unsigned maskpt2[2][GINT_BCPTS];
+    __shared__ int s_item;
+    const float sphi = (float)P0.phi_scale;
+    const float sB = pow2_scale(*cst(P0.vmax) * (8192.0 / P0.phi_scale));
+    const double unscale = 1.0 / ((double)sphi * (double)sB);
+    // double-buffered activity mask (bits 0-7: A slots, 8-15: B slots)
+    if (threadIdx.x < 2 * GINT_BCPTS) maskpt2[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
+    int cur = 0;
+    for (;;) {
+    const int item_ = claim_item(P0.counter, &s_item);
+    if (item_ >= P0.nitems) break;
+    const GItem it = ldc(P0.items + item_);
+    CPair8 &pr = cst(P0.pairs8)[it.pair];
+    GDev P = P0;
+    bind_system(P, pr.sys);
+    CSys &SY = cst(P0.sys)[pr.sys];
+    const double *V = V0 + SY.g_off;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const Slot sa = slot_of(P, pr.a[w], pr.shiftA), sb = slot_of(P, pr.b[w], pr.shiftB);
+    d4v acc[GINT_CL8];
+#pragma unroll
+    for (int i = 0; i < GINT_CL8; ++i) acc[i] = (d4v){0.0, 0.0, 0.0, 0.0};
+
+    for (int bc = 0; bc < it.bc_count; ++bc) {
+        const GBig o = ldc(P.bigcells + it.bc_begin + bc);
+        unsigned *maskpt = maskpt2[cur];
+        {
+            const int pt = lane;
+            const P3 r = point_of(P, o, pt);
+            const double vpt = V[r.g];
+            unsigned bits = 0;
+            const Disp da = disp_at(P, r, sa);
+            const bool zA = half_active(da.in);
+            if (da.in) {
+                CSpecies &sp = cst(P.species)[sa.species];
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
+                        T hi, lo;
+                        constexpr int SH = decltype(shp)::value;
+                        if constexpr (SH != GINT_SHAPE_ANY) {
+                            if (mu >= ChanShape<SH>::norb) return;
+                            S::split_mix(v, hi, lo);
+                        } else {
+                            S::split(v, hi, lo);
+                        }
+                        tA[0][w][mu][pt] = hi;
+                        tA[1][w][mu][pt] = lo;
+                    });
+                });
+                bits |= 1u << w;
+            } else if (zA) {
+#pragma unroll
+                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
+                    tA[0][w][mu][pt] = (T)0.f;
+                    tA[1][w][mu][pt] = (T)0.f;
+                }
+            }
+            const Disp db = disp_at(P, r, sb);
+            const bool zB = half_active(db.in);
+            if (db.in) {
+                CSpecies &sp = cst(P.species)[sb.species];
+                const float vg = (float)vpt * sB;
+                with_shape<KS>(sp, [&](auto shp) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
+                        T hi, lo;
+                        constexpr int SH = decltype(shp)::value;
+                        if constexpr (SH != GINT_SHAPE_ANY) {
+                            if (mu >= ChanShape<SH>::norb) return;
+                            S::split_mix(v, hi, lo);
+                        } else {
+                            S::split(v, hi, lo);
+                        }
+                        tB[0][w][mu][pt] = hi;
+                        tB[1][w][mu][pt] = lo;
+                    });
+                });
+                bits |= 1u << (GINT_CL8 + w);
+            } else if (zB) {
+#pragma unroll
+                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
+                    tB[0][w][mu][pt] = (T)0.f;
+                    tB[1][w][mu][pt] = (T)0.f;
+                }
+            }
+            if (bits) atomicOr(&maskpt[pt], bits);
+        }
+        __syncthreads();
+        if (threadIdx.x < GINT_BCPTS) maskpt2[cur ^ 1][threadIdx.x] = 0u;
+        cur ^= 1;
+        // activity of the two 32-point k-steps per slot
+        const unsigned mp = maskpt[lane];
+        unsigned km[2] = {0u, 0u};
+#pragma unroll
+        for (int b = 0; b < 2 * GINT_CL8; ++b) {
+            const unsigned long long bl = __ballot((mp >> b) & 1u);
+            if (bl & 0xffffffffull) km[0] |= 1u << b;
+            if (bl >> 32) km[1] |= 1u << b;
+        }
+        const int row = lane & 15, col = 8 * (lane >> 4);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f4v c32[4];
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) c32[ii] = (f4v){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) {
+                const int i = 4 * h + ii, j = (w - i) & (GINT_CL8 - 1);
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    if (!((km[kk] >> i) & 1u) || !((km[kk] >> (GINT_CL8 + j)) & 1u)) continue;
+                    const vec ahi = *(const vec *)&tA[0][i][row][32 * kk + col];
+                    const vec alo = *(const vec *)&tA[1][i][row][32 * kk + col];
+                    const vec bhi = *(const vec *)&tB[0][j][row][32 * kk + col];
+                    const vec blo = *(const vec *)&tB[1][j][row][32 * kk + col];
+                    c32[ii] = S::mfma(ahi, bhi, c32[ii]);
+                    c32[ii] = S::mfma(ahi, blo, c32[ii]);
+                    c32[ii] = S::mfma(alo, bhi, c32[ii]);
+                }
+            }
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[4 * h + ii][q] += (double)c32[ii][q];
+        }
+        __syncthreads();
+    }
+    // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
+    const bool exclusive = it.pad != 0;
+    const int nu = lane & 15;
+#pragma unroll
+    for (int i = 0; i < GINT_CL8; ++i) {
+        const int j = (w - i) & (GINT_CL8 - 1);
+        const int ai = pr.a[i], bj = pr.b[j];
+        if (ai < 0 || bj < 0) continue;
+        const int na = cst(P.atoms)[ai].norb, nb = cst(P.atoms)[bj].norb;
+        const long long off = pr.hoff[i * GINT_CL8 + j], offt = pr.hoff_t[i * GINT_CL8 + j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int mu = 4 * (lane >> 4) + q;
+            if (mu >= na || nu >= nb) continue;
+            const double v = P.w * unscale * acc[i][q];
+            if (exclusive) {
+                if (off >= 0) H[off + (long long)mu * nb + nu] = v;
+                if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
+            } else {
+                if (off >= 0) atomicAdd(H + off + (long long)mu * nb + nu, v);
+                if (!pr.self && offt >= 0) atomicAdd(H + offt + (long long)nu * na + mu, v);
+            }
+        }
+    }
+    }
+}
+
 namespace {
 
 // Row atom i of D_sym as 16-bit hi/lo MFMA B operands for psi = phi_B D^T:
@@ -558,6 +727,10 @@ struct KVlocal {
     template <class T, int KS>
     static const void *get() { return (const void *)k_vlocal_mx<T, KS>; }
 };
+struct KVlocal8 {
+    template <class T, int KS>
+    static const void *get() { return (const void *)k_vlocal_mx8<T, KS>; }
+};
 struct KRho {
     template <class T, int KS>
     static const void *get() { return (const void *)k_rho_mx<T, KS>; }
@@ -576,15 +749,15 @@ const void *kernel_for(int prec, int shape_all) {
     return fixed ? K::template get<_Float16, GINT_SHAPE_2S2P1D>() : K::template get<_Float16, GINT_SHAPE_ANY>();
 }
 
-template <class K, class... Args>
+template <class K, int THREADS = 256, class... Args>
 hipError_t launch_form(const GDev &P, int prec, hipStream_t s, Args... args) {
     const void *k = kernel_for<K>(prec, P.shape_all);
     if (P.nitems <= 0) return hipSuccess;
     hipError_t e = gint_launch_fill((double *)P.counter, 1, 0.0, s);
     if (e != hipSuccess) return e;
-    const int grid = gint_persistent_grid(k, P.nitems, 256);
+    const int grid = gint_persistent_grid(k, P.nitems, THREADS);
     void *argv[] = {const_cast<GDev *>(&P), &args...};
-    e = hipLaunchKernel(k, dim3(grid), dim3(256), argv, 0, s);
+    e = hipLaunchKernel(k, dim3(grid), dim3(THREADS), argv, 0, s);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
@@ -601,6 +774,7 @@ hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long 
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
+    if (P.pairs8) return launch_form<KVlocal8, 512>(P, prec, s, V, H);
     return launch_form<KVlocal>(P, prec, s, V, H);
 }
 
@@ -619,6 +793,7 @@ int gint_resident_blocks(const void *kernel, int threads);
 void gint_prime_grids_mx(int prec) {
     for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
         gint_resident_blocks(kernel_for<KVlocal>(prec, shape), 256);
+        gint_resident_blocks(kernel_for<KVlocal8>(prec, shape), 512);
         gint_resident_blocks(kernel_for<KRho>(prec, shape), 256);
         gint_resident_blocks(kernel_for<KForce<false>>(prec, shape), 256);
         gint_resident_blocks(kernel_for<KForce<true>>(prec, shape), 256);

@@ -127,8 +127,9 @@ struct Cluster {
     double reach;    // max_a |tau_a - c| + rc_a
 };
 
-struct PairOut {
-    GPair pair;
+template <int CL>
+struct PairOutT {
+    GPairT<CL> pair;
     std::vector<GBig> bcs;
 };
 
@@ -337,7 +338,252 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
     return GINT_OK;
 }
 
+// Bigcell circumradius: centre at offset 1.5 grid steps, corners at +-1.5
+// (slightly enlarged so that rounding never drops a point on the sphere).
+double bigcell_radius(const Geometry &G) {
+    double Rb = 0;
+    for (int q = 0; q < 8; ++q) {
+        const Vec3 d = G.point((q & 1) ? 1.5 : -1.5, (q & 2) ? 1.5 : -1.5, (q & 4) ? 1.5 : -1.5);
+        Rb = std::max(Rb, std::sqrt(dot(d, d)));
+    }
+    Rb *= 1.0 + 1e-12;
+    Rb += 1e-12;
+    return Rb;
+}
+
 }  // namespace
+
+// Clusters of at most cl atoms (spatial bisection), the cluster pairs that
+// overlap on the grid with their bigcell lists, and the work items over them
+// (canonical pairs; with_swapped also adds the swapped copy of every
+// non-self pair and the items that cover both orders).
+template <int CL>
+int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const std::vector<double> &rc,
+                        const BlockMap &bm, int cl, int maxbc_opt, double Rb, bool with_swapped,
+                        std::vector<GPairT<CL>> &pairs, HostPlan &hp) {
+    auto fail = [&](int code, const char *msg) {
+        hp.error = msg;
+        return code;
+    };
+    const int natom = (int)pos.size();
+    // ---- clusters
+    std::vector<std::vector<int>> groups;
+    {
+        std::vector<int> all(natom);
+        for (int i = 0; i < natom; ++i) all[i] = i;
+        bisect(pos, all, cl, groups);
+    }
+    std::vector<Cluster> cls(groups.size());
+    for (size_t c = 0; c < groups.size(); ++c) {
+        Cluster &C = cls[c];
+        C.atoms = groups[c];
+        Vec3 m{0, 0, 0};
+        for (int a : C.atoms) m = add(m, pos[a]);
+        m = {m.x / C.atoms.size(), m.y / C.atoms.size(), m.z / C.atoms.size()};
+        C.c = m;
+        C.reach = 0;
+        for (int a : C.atoms) C.reach = std::max(C.reach, std::sqrt(dot(sub(pos[a], m), sub(pos[a], m))) + rc[a]);
+    }
+    hp.ncluster = (int)cls.size();
+
+    // ---- cluster pairs: (A, B, T) with A < B, or A == B and T >= 0 lexicographically
+    const int ncl = (int)cls.size();
+    std::vector<std::vector<PairOutT<CL>>> per_a(ncl);
+    std::atomic<int> next{0};
+    std::atomic<int> err{GINT_OK};
+    auto worker = [&]() {
+        for (;;) {
+            const int A = next.fetch_add(1);
+            if (A >= ncl || err.load() != GINT_OK) break;
+            const Cluster &CA = cls[A];
+            for (int B = A; B < ncl; ++B) {
+                const Cluster &CB = cls[B];
+                const Vec3 dc = sub(CA.c, CB.c);
+                const double reach = CA.reach + CB.reach;
+                int tlo[3], thi[3];
+                for (int k = 0; k < 3; ++k) {
+                    const double u = G.frac(dc, k);
+                    tlo[k] = (int)std::floor(u - reach / G.spacing[k]) - 1;
+                    thi[k] = (int)std::ceil(u + reach / G.spacing[k]) + 1;
+                }
+                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
+                    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
+                        for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
+                            if (A == B && (t0 < 0 || (t0 == 0 && (t1 < 0 || (t1 == 0 && t2 < 0))))) continue;
+                            const Vec3 sh = G.lat(t0, t1, t2);
+                            const Vec3 cb = add(CB.c, sh);
+                            const Vec3 d = sub(CA.c, cb);
+                            if (dot(d, d) >= reach * reach) continue;
+                            // atom pairs and their blocks
+                            PairOutT<CL> po;
+                            GPairT<CL> &P = po.pair;
+                            std::memset(&P, 0, sizeof(P));
+                            for (int k = 0; k < CL; ++k) { P.a[k] = -1; P.b[k] = -1; }
+                            for (size_t k = 0; k < CA.atoms.size(); ++k) P.a[k] = CA.atoms[k];
+                            for (size_t k = 0; k < CB.atoms.size(); ++k) P.b[k] = CB.atoms[k];
+                            P.shiftA[0] = P.shiftA[1] = P.shiftA[2] = 0.0;
+                            P.shiftB[0] = sh.x; P.shiftB[1] = sh.y; P.shiftB[2] = sh.z;
+                            P.self = (A == B && t0 == 0 && t1 == 0 && t2 == 0) ? 1 : 0;
+                            bool any_overlap = false;
+                            for (int ia = 0; ia < CL; ++ia)
+                                for (int jb = 0; jb < CL; ++jb) {
+                                    P.hoff[ia * CL + jb] = -1;
+                                    P.hoff_t[ia * CL + jb] = -1;
+                                    const int a = P.a[ia], b = P.b[jb];
+                                    if (a < 0 || b < 0) continue;
+                                    const Vec3 dab = sub(pos[a], add(pos[b], sh));
+                                    const bool near = dot(dab, dab) < (rc[a] + rc[b]) * (rc[a] + rc[b]);
+                                    const long long o = bm.find(a, b, t0, t1, t2);
+                                    const long long ot = bm.find(b, a, -t0, -t1, -t2);
+                                    P.hoff[ia * CL + jb] = o;
+                                    P.hoff_t[ia * CL + jb] = ot;
+                                    if (near) {
+                                        any_overlap = true;
+                                        if (o < 0 || ot < 0) {
+                                            // missing block: an error only if some grid point lies in both spheres
+                                            const double ra = rc[a], rbb = rc[b];
+                                            const Vec3 pb = add(pos[b], sh);
+                                            long long lo[3], hi[3];
+                                            for (int k = 0; k < 3; ++k) {
+                                                const double u = G.frac(pos[a], k), ext = ra / G.spacing[k];
+                                                lo[k] = (long long)std::floor((u - ext) * G.N[k]) - 1;
+                                                hi[k] = (long long)std::ceil((u + ext) * G.N[k]) + 1;
+                                            }
+                                            bool hit = false;
+                                            for (long long n0 = lo[0]; n0 <= hi[0] && !hit; ++n0)
+                                                for (long long n1 = lo[1]; n1 <= hi[1] && !hit; ++n1)
+                                                    for (long long n2 = lo[2]; n2 <= hi[2] && !hit; ++n2) {
+                                                        const Vec3 r = G.point((double)n0, (double)n1, (double)n2);
+                                                        const Vec3 xa = sub(r, pos[a]), xb = sub(r, pb);
+                                                        if (std::sqrt(dot(xa, xa)) < ra && std::sqrt(dot(xb, xb)) < rbb) hit = true;
+                                                    }
+                                            if (hit) {
+                                                int expected = GINT_OK;
+                                                err.compare_exchange_strong(expected, GINT_EPATTERN);
+                                            }
+                                        }
+                                    }
+                                }
+                            if (!any_overlap) continue;
+                            // bigcells in the intersection of the two clusters' reach
+                            long long blo[3], bhi[3];
+                            for (int k = 0; k < 3; ++k) {
+                                const double ua = G.frac(CA.c, k), ub = G.frac(cb, k);
+                                const double ea = (CA.reach + Rb) / G.spacing[k], eb = (CB.reach + Rb) / G.spacing[k];
+                                const double lo = std::max(ua - ea, ub - eb), hi = std::min(ua + ea, ub + eb);
+                                blo[k] = (long long)std::floor(lo * G.N[k] / GINT_BC) - 1;
+                                bhi[k] = (long long)std::ceil(hi * G.N[k] / GINT_BC) + 1;
+                            }
+                            for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
+                                for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
+                                    for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
+                                        const Vec3 ctr = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, GINT_BC * b2 + 1.5);
+                                        bool ina = false, inb = false;
+                                        for (int a : CA.atoms) {
+                                            const Vec3 x = sub(ctr, pos[a]);
+                                            const double R = rc[a] + Rb;
+                                            if (dot(x, x) < R * R) { ina = true; break; }
+                                        }
+                                        if (!ina) continue;
+                                        for (int b : CB.atoms) {
+                                            const Vec3 x = sub(ctr, add(pos[b], sh));
+                                            const double R = rc[b] + Rb;
+                                            if (dot(x, x) < R * R) { inb = true; break; }
+                                        }
+                                        if (!inb) continue;
+                                        if (std::llabs(b0) > (1LL << 28) || std::llabs(b1) > (1LL << 28) || std::llabs(b2) > (1LL << 28)) {
+                                            int expected = GINT_OK;
+                                            err.compare_exchange_strong(expected, GINT_EINVAL);
+                                            continue;
+                                        }
+                                        po.bcs.push_back(make_bigcell(G.N, GINT_BC * b0, GINT_BC * b1, GINT_BC * b2));
+                                    }
+                            if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
+                        }
+            }
+        }
+    };
+    unsigned nth = std::thread::hardware_concurrency();
+    if (nth == 0) nth = 4;
+    nth = std::min(nth, 16u);
+    std::vector<std::thread> th;
+    for (unsigned t = 0; t < nth; ++t) th.emplace_back(worker);
+    for (auto &t : th) t.join();
+    if (err.load() != GINT_OK)
+        return fail(err.load(), err.load() == GINT_EPATTERN ? "an overlapping (I,J,R) block is missing from the pattern"
+                                                            : "grid index out of range");
+
+    // ---- flatten: canonical pairs, then their swapped copies
+    pairs.clear();
+    hp.bigcells.clear();
+    std::vector<std::pair<int, int>> ranges;   // per canonical pair: bigcell begin, count
+    for (int A = 0; A < ncl; ++A)
+        for (auto &po : per_a[A]) {
+            ranges.push_back({(int)hp.bigcells.size(), (int)po.bcs.size()});
+            hp.bigcells.insert(hp.bigcells.end(), po.bcs.begin(), po.bcs.end());
+            pairs.push_back(po.pair);
+            if (hp.bigcells.size() > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
+        }
+    hp.ncanon = (int)pairs.size();
+    std::vector<int> swapped_of(hp.ncanon, -1);
+    for (int p = 0; p < hp.ncanon && with_swapped; ++p) {
+        const GPairT<CL> P = pairs[p];
+        if (P.self) continue;
+        GPairT<CL> S;
+        std::memset(&S, 0, sizeof(S));
+        for (int k = 0; k < CL; ++k) { S.a[k] = P.b[k]; S.b[k] = P.a[k]; }
+        for (int k = 0; k < 3; ++k) { S.shiftA[k] = P.shiftB[k]; S.shiftB[k] = P.shiftA[k]; }
+        S.self = 0;
+        for (int i = 0; i < CL; ++i)
+            for (int j = 0; j < CL; ++j) {
+                S.hoff[i * CL + j] = P.hoff_t[j * CL + i];
+                S.hoff_t[i * CL + j] = P.hoff[j * CL + i];
+            }
+        swapped_of[p] = (int)pairs.size();
+        pairs.push_back(S);
+    }
+
+    // ---- work items: runs of at most maxbc bigcells, longest first.  With
+    // enough pairs to fill the GPU several times over, a pair is one item
+    // (exclusive: its H blocks are written with plain stores); otherwise long
+    // pairs are split for load balance.
+    long long total_bc = 0;
+    int longest = 0;
+    for (int p = 0; p < hp.ncanon; ++p) {
+        total_bc += ranges[p].second;
+        longest = std::max(longest, ranges[p].second);
+    }
+    int maxbc = maxbc_opt;
+    if (maxbc <= 0) {
+        const long long slots = 2048;    // resident workgroups of a large GPU, with margin
+        const long long per_slot = (total_bc + slots - 1) / slots;
+        maxbc = (int)std::max<long long>(64, std::min<long long>(std::max<long long>(per_slot, 64), 1LL << 30));
+        if (longest <= per_slot * 2) maxbc = std::max(maxbc, longest);
+    }
+    hp.items_canon.clear();
+    hp.items_ordered.clear();
+    for (int p = 0; p < hp.ncanon; ++p) {
+        const int beg = ranges[p].first, cnt = ranges[p].second;
+        const int nchunk = (cnt + maxbc - 1) / maxbc;
+        const int excl = nchunk == 1 ? 1 : 0;
+        for (int c = 0; c < nchunk; ++c) {
+            const int b0 = beg + (int)((long long)cnt * c / nchunk);
+            const int b1 = beg + (int)((long long)cnt * (c + 1) / nchunk);
+            hp.items_canon.push_back({p, b0, b1 - b0, excl});
+            hp.items_ordered.push_back({p, b0, b1 - b0, excl});
+            if (swapped_of[p] >= 0) hp.items_ordered.push_back({swapped_of[p], b0, b1 - b0, excl});
+        }
+    }
+    auto longer = [](const GItem &x, const GItem &y) {
+        if (x.bc_count != y.bc_count) return x.bc_count > y.bc_count;
+        if (x.pair != y.pair) return x.pair < y.pair;
+        return x.bc_begin < y.bc_begin;
+    };
+    std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
+    std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
+
+    return GINT_OK;
+}
 
 static int build_one(const gint_system *sys, const gint_options *opt, bool bricks, HostPlan &hp) {
     auto fail = [&](int code, const char *msg) {
@@ -345,8 +591,17 @@ static int build_one(const gint_system *sys, const gint_options *opt, bool brick
         return code;
     };
     if (!sys) return fail(GINT_EINVAL, "null system");
+    // clusters of up to eight atoms serve only the eight-wave mixed Vlocal,
+    // i.e. plans whose rho and force run on bricks.  The default is four: on
+    // the bilayers a pair of eight-atom clusters covers half as many bigcells
+    // as four pairs of four-atom ones, so the orbital evaluations, which
+    // bound Vlocal, do not drop, and the per-bigcell overhead doubles.
+    const bool wide_ok = opt && opt->precision != GINT_FP64 &&
+                         (opt->decomposition == GINT_DECOMP_DEFAULT || opt->decomposition == GINT_DECOMP_BIGCELL_RHO_FORCE);
     const int cl = (opt && opt->cluster_atoms > 0) ? opt->cluster_atoms : GINT_CL;
-    if (cl < 1 || cl > GINT_CL) return fail(GINT_EINVAL, "cluster_atoms out of range");
+    if (cl < 1 || cl > GINT_CL8) return fail(GINT_EINVAL, "cluster_atoms out of range");
+    if (cl > GINT_CL && !wide_ok)
+        return fail(GINT_EINVAL, "clusters of more than 4 atoms need a mixed-precision plan with bigcell rho/force");
     const int maxbc_opt = (opt && opt->max_bigcells_per_item > 0) ? opt->max_bigcells_per_item : 0;
     hp.cluster_atoms = cl;
     if (sys->natom < 1 || !sys->pos || !sys->species) return fail(GINT_EINVAL, "bad atoms");
@@ -534,233 +789,13 @@ static int build_one(const gint_system *sys, const gint_options *opt, bool brick
     }
     hp.nnz = nnz;
 
-    // ---- clusters
-    std::vector<std::vector<int>> groups;
+    // ---- clusters, cluster pairs and their work items
+    const double Rb = bigcell_radius(G);
     {
-        std::vector<int> all(natom);
-        for (int i = 0; i < natom; ++i) all[i] = i;
-        bisect(pos, all, cl, groups);
+        const int r = cl > GINT_CL ? build_cluster_pairs<GINT_CL8>(G, pos, rc, bm, cl, maxbc_opt, Rb, false, hp.pairs8, hp)
+                                   : build_cluster_pairs<GINT_CL>(G, pos, rc, bm, cl, maxbc_opt, Rb, true, hp.pairs, hp);
+        if (r != GINT_OK) return r;
     }
-    std::vector<Cluster> cls(groups.size());
-    for (size_t c = 0; c < groups.size(); ++c) {
-        Cluster &C = cls[c];
-        C.atoms = groups[c];
-        Vec3 m{0, 0, 0};
-        for (int a : C.atoms) m = add(m, pos[a]);
-        m = {m.x / C.atoms.size(), m.y / C.atoms.size(), m.z / C.atoms.size()};
-        C.c = m;
-        C.reach = 0;
-        for (int a : C.atoms) C.reach = std::max(C.reach, std::sqrt(dot(sub(pos[a], m), sub(pos[a], m))) + rc[a]);
-    }
-    hp.ncluster = (int)cls.size();
-
-    // bigcell circumradius: centre at offset 1.5 grid steps, corners at +-1.5
-    double Rb = 0;
-    for (int q = 0; q < 8; ++q) {
-        const Vec3 d = G.point((q & 1) ? 1.5 : -1.5, (q & 2) ? 1.5 : -1.5, (q & 4) ? 1.5 : -1.5);
-        Rb = std::max(Rb, std::sqrt(dot(d, d)));
-    }
-    Rb *= 1.0 + 1e-12;
-    Rb += 1e-12;
-
-    double maxreach = 0;
-    for (auto &C : cls) maxreach = std::max(maxreach, C.reach);
-
-    // ---- cluster pairs: (A, B, T) with A < B, or A == B and T >= 0 lexicographically
-    const int ncl = (int)cls.size();
-    std::vector<std::vector<PairOut>> per_a(ncl);
-    std::atomic<int> next{0};
-    std::atomic<int> err{GINT_OK};
-    auto worker = [&]() {
-        for (;;) {
-            const int A = next.fetch_add(1);
-            if (A >= ncl || err.load() != GINT_OK) break;
-            const Cluster &CA = cls[A];
-            for (int B = A; B < ncl; ++B) {
-                const Cluster &CB = cls[B];
-                const Vec3 dc = sub(CA.c, CB.c);
-                const double reach = CA.reach + CB.reach;
-                int tlo[3], thi[3];
-                for (int k = 0; k < 3; ++k) {
-                    const double u = G.frac(dc, k);
-                    tlo[k] = (int)std::floor(u - reach / G.spacing[k]) - 1;
-                    thi[k] = (int)std::ceil(u + reach / G.spacing[k]) + 1;
-                }
-                for (int t0 = tlo[0]; t0 <= thi[0]; ++t0)
-                    for (int t1 = tlo[1]; t1 <= thi[1]; ++t1)
-                        for (int t2 = tlo[2]; t2 <= thi[2]; ++t2) {
-                            if (A == B && (t0 < 0 || (t0 == 0 && (t1 < 0 || (t1 == 0 && t2 < 0))))) continue;
-                            const Vec3 sh = G.lat(t0, t1, t2);
-                            const Vec3 cb = add(CB.c, sh);
-                            const Vec3 d = sub(CA.c, cb);
-                            if (dot(d, d) >= reach * reach) continue;
-                            // atom pairs and their blocks
-                            PairOut po;
-                            GPair &P = po.pair;
-                            std::memset(&P, 0, sizeof(P));
-                            for (int k = 0; k < GINT_CL; ++k) { P.a[k] = -1; P.b[k] = -1; }
-                            for (size_t k = 0; k < CA.atoms.size(); ++k) P.a[k] = CA.atoms[k];
-                            for (size_t k = 0; k < CB.atoms.size(); ++k) P.b[k] = CB.atoms[k];
-                            P.shiftA[0] = P.shiftA[1] = P.shiftA[2] = 0.0;
-                            P.shiftB[0] = sh.x; P.shiftB[1] = sh.y; P.shiftB[2] = sh.z;
-                            P.self = (A == B && t0 == 0 && t1 == 0 && t2 == 0) ? 1 : 0;
-                            bool any_overlap = false;
-                            for (int ia = 0; ia < GINT_CL; ++ia)
-                                for (int jb = 0; jb < GINT_CL; ++jb) {
-                                    P.hoff[ia * 4 + jb] = -1;
-                                    P.hoff_t[ia * 4 + jb] = -1;
-                                    const int a = P.a[ia], b = P.b[jb];
-                                    if (a < 0 || b < 0) continue;
-                                    const Vec3 dab = sub(pos[a], add(pos[b], sh));
-                                    const bool near = dot(dab, dab) < (rc[a] + rc[b]) * (rc[a] + rc[b]);
-                                    const long long o = bm.find(a, b, t0, t1, t2);
-                                    const long long ot = bm.find(b, a, -t0, -t1, -t2);
-                                    P.hoff[ia * 4 + jb] = o;
-                                    P.hoff_t[ia * 4 + jb] = ot;
-                                    if (near) {
-                                        any_overlap = true;
-                                        if (o < 0 || ot < 0) {
-                                            // missing block: an error only if some grid point lies in both spheres
-                                            const double ra = rc[a], rbb = rc[b];
-                                            const Vec3 pb = add(pos[b], sh);
-                                            long long lo[3], hi[3];
-                                            for (int k = 0; k < 3; ++k) {
-                                                const double u = G.frac(pos[a], k), ext = ra / G.spacing[k];
-                                                lo[k] = (long long)std::floor((u - ext) * G.N[k]) - 1;
-                                                hi[k] = (long long)std::ceil((u + ext) * G.N[k]) + 1;
-                                            }
-                                            bool hit = false;
-                                            for (long long n0 = lo[0]; n0 <= hi[0] && !hit; ++n0)
-                                                for (long long n1 = lo[1]; n1 <= hi[1] && !hit; ++n1)
-                                                    for (long long n2 = lo[2]; n2 <= hi[2] && !hit; ++n2) {
-                                                        const Vec3 r = G.point((double)n0, (double)n1, (double)n2);
-                                                        const Vec3 xa = sub(r, pos[a]), xb = sub(r, pb);
-                                                        if (std::sqrt(dot(xa, xa)) < ra && std::sqrt(dot(xb, xb)) < rbb) hit = true;
-                                                    }
-                                            if (hit) {
-                                                int expected = GINT_OK;
-                                                err.compare_exchange_strong(expected, GINT_EPATTERN);
-                                            }
-                                        }
-                                    }
-                                }
-                            if (!any_overlap) continue;
-                            // bigcells in the intersection of the two clusters' reach
-                            long long blo[3], bhi[3];
-                            for (int k = 0; k < 3; ++k) {
-                                const double ua = G.frac(CA.c, k), ub = G.frac(cb, k);
-                                const double ea = (CA.reach + Rb) / G.spacing[k], eb = (CB.reach + Rb) / G.spacing[k];
-                                const double lo = std::max(ua - ea, ub - eb), hi = std::min(ua + ea, ub + eb);
-                                blo[k] = (long long)std::floor(lo * G.N[k] / GINT_BC) - 1;
-                                bhi[k] = (long long)std::ceil(hi * G.N[k] / GINT_BC) + 1;
-                            }
-                            for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
-                                for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
-                                    for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
-                                        const Vec3 ctr = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, GINT_BC * b2 + 1.5);
-                                        bool ina = false, inb = false;
-                                        for (int a : CA.atoms) {
-                                            const Vec3 x = sub(ctr, pos[a]);
-                                            const double R = rc[a] + Rb;
-                                            if (dot(x, x) < R * R) { ina = true; break; }
-                                        }
-                                        if (!ina) continue;
-                                        for (int b : CB.atoms) {
-                                            const Vec3 x = sub(ctr, add(pos[b], sh));
-                                            const double R = rc[b] + Rb;
-                                            if (dot(x, x) < R * R) { inb = true; break; }
-                                        }
-                                        if (!inb) continue;
-                                        if (std::llabs(b0) > (1LL << 28) || std::llabs(b1) > (1LL << 28) || std::llabs(b2) > (1LL << 28)) {
-                                            int expected = GINT_OK;
-                                            err.compare_exchange_strong(expected, GINT_EINVAL);
-                                            continue;
-                                        }
-                                        po.bcs.push_back(make_bigcell(G.N, GINT_BC * b0, GINT_BC * b1, GINT_BC * b2));
-                                    }
-                            if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
-                        }
-            }
-        }
-    };
-    unsigned nth = std::thread::hardware_concurrency();
-    if (nth == 0) nth = 4;
-    nth = std::min(nth, 16u);
-    std::vector<std::thread> th;
-    for (unsigned t = 0; t < nth; ++t) th.emplace_back(worker);
-    for (auto &t : th) t.join();
-    if (err.load() != GINT_OK)
-        return fail(err.load(), err.load() == GINT_EPATTERN ? "an overlapping (I,J,R) block is missing from the pattern"
-                                                            : "grid index out of range");
-
-    // ---- flatten: canonical pairs, then their swapped copies
-    hp.pairs.clear();
-    hp.bigcells.clear();
-    std::vector<std::pair<int, int>> ranges;   // per canonical pair: bigcell begin, count
-    for (int A = 0; A < ncl; ++A)
-        for (auto &po : per_a[A]) {
-            ranges.push_back({(int)hp.bigcells.size(), (int)po.bcs.size()});
-            hp.bigcells.insert(hp.bigcells.end(), po.bcs.begin(), po.bcs.end());
-            hp.pairs.push_back(po.pair);
-            if (hp.bigcells.size() > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
-        }
-    hp.ncanon = (int)hp.pairs.size();
-    std::vector<int> swapped_of(hp.ncanon, -1);
-    for (int p = 0; p < hp.ncanon; ++p) {
-        const GPair &P = hp.pairs[p];
-        if (P.self) continue;
-        GPair S;
-        std::memset(&S, 0, sizeof(S));
-        for (int k = 0; k < GINT_CL; ++k) { S.a[k] = P.b[k]; S.b[k] = P.a[k]; }
-        for (int k = 0; k < 3; ++k) { S.shiftA[k] = P.shiftB[k]; S.shiftB[k] = P.shiftA[k]; }
-        S.self = 0;
-        for (int i = 0; i < GINT_CL; ++i)
-            for (int j = 0; j < GINT_CL; ++j) {
-                S.hoff[i * 4 + j] = P.hoff_t[j * 4 + i];
-                S.hoff_t[i * 4 + j] = P.hoff[j * 4 + i];
-            }
-        swapped_of[p] = (int)hp.pairs.size();
-        hp.pairs.push_back(S);
-    }
-
-    // ---- work items: runs of at most maxbc bigcells, longest first.  With
-    // enough pairs to fill the GPU several times over, a pair is one item
-    // (exclusive: its H blocks are written with plain stores); otherwise long
-    // pairs are split for load balance.
-    long long total_bc = 0;
-    int longest = 0;
-    for (int p = 0; p < hp.ncanon; ++p) {
-        total_bc += ranges[p].second;
-        longest = std::max(longest, ranges[p].second);
-    }
-    int maxbc = maxbc_opt;
-    if (maxbc <= 0) {
-        const long long slots = 2048;    // resident workgroups of a large GPU, with margin
-        const long long per_slot = (total_bc + slots - 1) / slots;
-        maxbc = (int)std::max<long long>(64, std::min<long long>(std::max<long long>(per_slot, 64), 1LL << 30));
-        if (longest <= per_slot * 2) maxbc = std::max(maxbc, longest);
-    }
-    hp.items_canon.clear();
-    hp.items_ordered.clear();
-    for (int p = 0; p < hp.ncanon; ++p) {
-        const int beg = ranges[p].first, cnt = ranges[p].second;
-        const int nchunk = (cnt + maxbc - 1) / maxbc;
-        const int excl = nchunk == 1 ? 1 : 0;
-        for (int c = 0; c < nchunk; ++c) {
-            const int b0 = beg + (int)((long long)cnt * c / nchunk);
-            const int b1 = beg + (int)((long long)cnt * (c + 1) / nchunk);
-            hp.items_canon.push_back({p, b0, b1 - b0, excl});
-            hp.items_ordered.push_back({p, b0, b1 - b0, excl});
-            if (swapped_of[p] >= 0) hp.items_ordered.push_back({swapped_of[p], b0, b1 - b0, excl});
-        }
-    }
-    auto longer = [](const GItem &x, const GItem &y) {
-        if (x.bc_count != y.bc_count) return x.bc_count > y.bc_count;
-        if (x.pair != y.pair) return x.pair < y.pair;
-        return x.bc_begin < y.bc_begin;
-    };
-    std::sort(hp.items_canon.begin(), hp.items_canon.end(), longer);
-    std::sort(hp.items_ordered.begin(), hp.items_ordered.end(), longer);
 
     // ---- bigcell-stationary bricks.  Default shape: about 2 Bohr along each
     // axis (anisotropic grids get anisotropic bricks), at most 8 bigcells;
@@ -796,6 +831,25 @@ static int build_one(const gint_system *sys, const gint_options *opt, bool brick
         for (int k = 0; k < 3; ++k) hp.brick[k] = B[k];
     }
     return GINT_OK;
+}
+
+// Appends the cluster pairs of system i of a batch, with its atom and
+// matrix offsets applied.
+template <int CL>
+void merge_pairs(const std::vector<GPairT<CL>> &src, int i, int atom_off, long long nnz_off,
+                 std::vector<GPairT<CL>> &dst) {
+    for (GPairT<CL> P : src) {
+        for (int k = 0; k < CL; ++k) {
+            if (P.a[k] >= 0) P.a[k] += atom_off;
+            if (P.b[k] >= 0) P.b[k] += atom_off;
+        }
+        for (int k = 0; k < CL * CL; ++k) {
+            if (P.hoff[k] >= 0) P.hoff[k] += nnz_off;
+            if (P.hoff_t[k] >= 0) P.hoff_t[k] += nnz_off;
+        }
+        P.sys = i;
+        dst.push_back(P);
+    }
 }
 
 int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp) {
@@ -853,24 +907,18 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             at.species += species_off;
             hp.atoms.push_back(at);
         }
-        const int pair_off = (int)hp.pairs.size();
+        if (i > 0 && one.pairs8.empty() != hp.pairs8.empty()) {
+            hp.error = "systems of one plan must share the cluster size";
+            return GINT_EINVAL;
+        }
+        const int pair_off = (int)(hp.pairs.size() + hp.pairs8.size());
         const int bc_off = (int)hp.bigcells.size();
         if (hp.bigcells.size() + one.bigcells.size() > (size_t)0x7fffffff) {
             hp.error = "too many bigcells";
             return GINT_ENOMEM;
         }
-        for (GPair P : one.pairs) {
-            for (int k = 0; k < GINT_CL; ++k) {
-                if (P.a[k] >= 0) P.a[k] += atom_off;
-                if (P.b[k] >= 0) P.b[k] += atom_off;
-            }
-            for (int k = 0; k < GINT_CL * GINT_CL; ++k) {
-                if (P.hoff[k] >= 0) P.hoff[k] += nnz_off;
-                if (P.hoff_t[k] >= 0) P.hoff_t[k] += nnz_off;
-            }
-            P.sys = i;
-            hp.pairs.push_back(P);
-        }
+        merge_pairs(one.pairs, i, atom_off, nnz_off, hp.pairs);
+        merge_pairs(one.pairs8, i, atom_off, nnz_off, hp.pairs8);
         hp.bigcells.insert(hp.bigcells.end(), one.bigcells.begin(), one.bigcells.end());
         {
             const int ub = (int)hp.uatoms.size();

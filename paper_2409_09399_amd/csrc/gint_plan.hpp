@@ -14,10 +14,11 @@ struct HostPlan {
     std::vector<GAtom> atoms;
     std::vector<double> tab;
     std::vector<float> tab32;
-    std::vector<GPair> pairs;        // [0, ncanon): canonical; [ncanon, ..): swapped copies
+    std::vector<GPair> pairs;        // clusters of <= 4 atoms: [0, ncanon) canonical, then swapped copies
+    std::vector<GPair8> pairs8;      // clusters of 5..8 atoms (canonical only; instead of pairs)
     std::vector<GBig> bigcells;
     std::vector<GItem> items_canon;  // canonical pairs, longest first
-    std::vector<GItem> items_ordered;// canonical + swapped, longest first
+    std::vector<GItem> items_ordered;// canonical + swapped, longest first (only the canonical ones with pairs8)
     std::vector<GSys> sys;           // one per system
     std::vector<GBlk> blocks;        // pattern blocks with their transposes (symmetry check, D16 conversion)
     std::vector<GBrick> bricks;      // bigcell-stationary bricks (rho and force), empty unless built

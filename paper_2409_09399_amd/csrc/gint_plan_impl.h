@@ -19,7 +19,7 @@ struct gint_plan {
     int device = 0;
     GDev canon{};      // canonical items (vlocal, rho, work)
     GDev ordered{};    // canonical + swapped items (force)
-    DevBuf species, atoms, tab, tab32, pairs, bigcells, items_canon, items_ordered, sys, ws;
+    DevBuf species, atoms, tab, tab32, pairs, pairs8, bigcells, items_canon, items_ordered, sys, ws;
     DevBuf bricks, uatoms, ptab, d16;   // bigcell-stationary path (rho and force)
     bool bc = false;                    // rho and force run over bricks
     bool bc_vlocal = false;             // and Vlocal too

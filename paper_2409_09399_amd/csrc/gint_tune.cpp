@@ -15,8 +15,12 @@ hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
 namespace {
 
 // candidates in trial order (0 = the plan's default): (cluster_atoms,
-// max_bigcells_per_item) of Vlocal, and bricks in bigcells along a1, a2, a3
+// max_bigcells_per_item) of Vlocal, and bricks in bigcells along a1, a2, a3.
+// Mixed-precision plans with rho and force on bricks take clusters of up to
+// eight atoms (the eight-wave Vlocal kernel), the others up to four.
 constexpr int kCand[][2] = {{4, 0}, {3, 0}, {4, 32}, {2, 0}, {4, 128}, {3, 32}, {4, 8}, {2, 32}};
+constexpr int kCandWide[][2] = {{4, 0}, {8, 0}, {3, 0}, {6, 0}, {4, 128}, {8, 32}, {4, 32}, {2, 0}};
+static_assert(sizeof(kCand) == sizeof(kCandWide), "one cluster candidate per trial in both lists");
 constexpr int kBrick[][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 1}, {1, 1, 2}, {2, 1, 1}, {1, 2, 1}, {2, 2, 2}, {4, 4, 2}};
 constexpr int kNCand = (int)(sizeof(kCand) / sizeof(kCand[0]));
 static_assert(kNCand <= GINT_TUNE_MAX, "candidate list longer than the report");
@@ -71,13 +75,16 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
             return GINT_EHIP;
         }
     rep.best_brick = -1;
+    const bool wide = opt->precision != GINT_FP64 &&
+                      (opt->decomposition == GINT_DECOMP_DEFAULT || opt->decomposition == GINT_DECOMP_BIGCELL_RHO_FORCE);
+    const int(*cand)[2] = wide ? kCandWide : kCand;
     int rc = GINT_OK;
     for (int c = 0; c < kNCand; ++c) {
         const double elapsed = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         if (c > 0 && elapsed >= budget_seconds) break;
         gint_options o = *opt;
-        o.cluster_atoms = kCand[c][0];
-        o.max_bigcells_per_item = kCand[c][1];
+        o.cluster_atoms = cand[c][0];
+        o.max_bigcells_per_item = cand[c][1];
         for (int k = 0; k < 3; ++k) o.brick[k] = kBrick[c][k];
         gint_plan *p = nullptr;
         rc = gint_plan_create(&p, sys, n_sys, &o, stream);
@@ -108,7 +115,7 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
         const int t = rep.ntrials;
         rep.cluster_atoms[t] = o.cluster_atoms;
         rep.max_bigcells_per_item[t] = o.max_bigcells_per_item;
-        for (int k = 0; k < 3; ++k) rep.brick[t][k] = q.decomposition == GINT_DECOMP_BIGCELL ? q.brick[k] : 0;
+        for (int k = 0; k < 3; ++k) rep.brick[t][k] = q.decomposition != GINT_DECOMP_CLUSTER_PAIRS ? q.brick[k] : 0;
         rep.vlocal_ms[t] = vl;
         rep.rho_force_ms[t] = rf;
         rep.step_ms[t] = (double)vl + (double)rf;

@@ -1,10 +1,16 @@
 // Builds the host plan (paper_2409_09399_amd/csrc/gint_plan.cpp, compiled
 // here without HIP) for a system dumped by tests/test_sanitizers.py, so that
 // the plan builder runs under AddressSanitizer and UndefinedBehaviorSanitizer,
-// and checks the bigcell-stationary bricks against brute force: for sampled
-// grid points, every atom image within rcut of the point must be in the
-// union of the point's brick, and for every two such images the pair table
-// must name the pattern block (I, J, T_J - T_I).  Test infrastructure only.
+// and checks it against brute force:
+//   - the bigcell-stationary bricks: for sampled grid points, every atom
+//     image within rcut of the point must be in the union of the point's
+//     brick, and for every two such images the pair table must name the
+//     pattern block (I, J, T_J - T_I);
+//   - the cluster pairs (clusters of up to 4 or up to 8 atoms): over the
+//     canonical pairs, the tiles a Vlocal pass stores (block and, for a
+//     non-self pair, its transpose) reach no pattern block twice, and reach
+//     every block whose two spheres overlap by more than a grid cell.
+// Test infrastructure only.
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -40,10 +46,10 @@ int fail(const char *what, long a = 0, long b = 0) {
 
 int main(int argc, char **argv) {
     if (argc < 2) {
-        std::fprintf(stderr, "usage: %s <dir> [b0 b1 b2 [nocheck]]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s <dir> [b0 b1 b2 [cluster_atoms [nocheck]]]\n", argv[0]);
         return 2;
     }
-    const bool check = argc < 6;
+    const bool check = argc < 7;
     const std::string dir = argv[1];
     long natom, nspecies, nblk, ngrid, nnz, nchan, knots, mode;
     {
@@ -99,6 +105,7 @@ int main(int argc, char **argv) {
     opt.precision = GINT_MIXED_FP16X3;
     if (argc >= 5)
         for (int k = 0; k < 3; ++k) opt.brick[k] = std::atoi(argv[2 + k]);
+    if (argc >= 6) opt.cluster_atoms = std::atoi(argv[5]);
     HostPlan hp;
     const auto t0 = std::chrono::steady_clock::now();
     const int rc = gint_build_host_plan(&sys, 1, &opt, true, hp);
@@ -108,10 +115,61 @@ int main(int argc, char **argv) {
         return 1;
     }
     const int B[3] = {hp.brick[0], hp.brick[1], hp.brick[2]};
+    const size_t npairs = hp.pairs.size() + hp.pairs8.size();
     if (!check) {
-        std::printf("plan built in %.3f s: %zu pairs, %zu bricks (%d x %d x %d), %zu images, %zu pair-table entries\n",
-                    secs, hp.pairs.size(), hp.bricks.size(), B[0], B[1], B[2], hp.uatoms.size(), hp.ptab.size());
+        std::printf("plan built in %.3f s: %zu pairs (clusters of %d), %zu pair bigcells, %zu items, %zu bricks "
+                    "(%d x %d x %d), %zu images, %zu pair-table entries\n",
+                    secs, npairs, hp.cluster_atoms, hp.bigcells.size(), hp.items_canon.size(), hp.bricks.size(), B[0],
+                    B[1], B[2], hp.uatoms.size(), hp.ptab.size());
         return 0;
+    }
+
+    // cluster pairs: stores per pattern block over the canonical pairs
+    {
+        std::map<long long, int> writes;
+        auto visit = [&](const auto &pairs, int CL) {
+            for (int p = 0; p < hp.ncanon; ++p) {
+                const auto &P = pairs[p];
+                for (int ia = 0; ia < CL; ++ia)
+                    for (int jb = 0; jb < CL; ++jb) {
+                        if (P.a[ia] < 0 || P.b[jb] < 0) continue;
+                        if (P.hoff[ia * CL + jb] >= 0) ++writes[P.hoff[ia * CL + jb]];
+                        if (!P.self && P.hoff_t[ia * CL + jb] >= 0) ++writes[P.hoff_t[ia * CL + jb]];
+                    }
+            }
+        };
+        if (!hp.pairs8.empty()) {
+            if ((int)hp.pairs8.size() != hp.ncanon || hp.cluster_atoms <= GINT_CL) return fail("8-atom pair list");
+            visit(hp.pairs8, GINT_CL8);
+        } else {
+            if (hp.cluster_atoms > GINT_CL) return fail("4-atom pair list");
+            visit(hp.pairs, GINT_CL);
+        }
+        double hmax = 0;
+        for (int k = 0; k < 3; ++k) {
+            const double *c = &cell[3 * k];
+            hmax = std::max(hmax, std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]) / grid[k]);
+        }
+        long required = 0;
+        for (long b = 0; b < nblk; ++b) {
+            const auto it = writes.find(boff[b]);
+            const int nw = it == writes.end() ? 0 : it->second;
+            if (nw > 1) return fail("a pattern block is stored by two tiles", b, nw);
+            double d2 = 0;
+            for (int c = 0; c < 3; ++c) {
+                const double x = pos[3 * bi[b] + c] -
+                                 (pos[3 * bj[b] + c] + br[3 * b] * cell[c] + br[3 * b + 1] * cell[3 + c] +
+                                  br[3 * b + 2] * cell[6 + c]);
+                d2 += x * x;
+            }
+            // a lens wider than 3 grid steps contains a grid point
+            if (std::sqrt(d2) < rcut[species[bi[b]]] + rcut[species[bj[b]]] - 3.0 * hmax) {
+                ++required;
+                if (nw != 1) return fail("an overlapping pattern block is not stored", b, nw);
+            }
+        }
+        std::printf("cluster pairs ok: %d canonical pairs (clusters of %d), %zu blocks stored, %ld required; ",
+                    hp.ncanon, hp.cluster_atoms, writes.size(), required);
     }
 
     // brute-force checks of the bricks on sampled grid points
@@ -190,7 +248,7 @@ int main(int argc, char **argv) {
     }
     std::printf("plan driver ok: %zu pairs, %zu items, %zu bricks (%d x %d x %d), %zu images, %ld points checked "
                 "(%ld images)\n",
-                hp.pairs.size(), hp.items_ordered.size(), hp.bricks.size(), B[0], B[1], B[2], hp.uatoms.size(),
-                checked, images);
+                npairs, hp.items_ordered.size(), hp.bricks.size(), B[0], B[1], B[2], hp.uatoms.size(), checked,
+                images);
     return 0;
 }

@@ -65,6 +65,9 @@ def test_rejects_bad_inputs(G):
     t = _tiny(); t.cell = np.zeros((3, 3))
     assert _create(G, t) == G.GINT_EINVAL
     assert _create(G, s, cluster_atoms=9) == G.GINT_EINVAL
+    # clusters of more than four atoms: only mixed-precision plans with rho and force on bricks
+    assert _create(G, s, cluster_atoms=5) == G.GINT_EINVAL
+    assert _create(G, s, cluster_atoms=8, precision=G.GINT_MIXED_FP16X3, decomposition=1) == G.GINT_EINVAL
     assert _create(G, s, precision=7) == G.GINT_EUNSUPPORTED
 
 

@@ -34,13 +34,13 @@ def torch_dev():
     return torch, torch.device("cuda:0")
 
 
-def run(G, torch, dev, s, precision, decomposition=0, brick=(0, 0, 0), fused=True):
+def run(G, torch, dev, s, precision, decomposition=0, brick=(0, 0, 0), fused=True, cluster_atoms=0):
     """Vlocal, rho and force/stress of one system; with fused, also the
     one-pass rho + force/stress (out["fused"]), checked by the callers at the
     same bounds (in the mixed forms the two passes round differently)."""
-    plan = G.Plan(s, precision=precision, decomposition=decomposition, brick=brick)
+    plan = G.Plan(s, precision=precision, decomposition=decomposition, brick=brick, cluster_atoms=cluster_atoms)
     print(f"[mixed] plan {s.name} prec={precision} decomposition={plan.sizes.decomposition} "
-          f"brick={tuple(plan.sizes.brick)} nbricks={plan.sizes.nbricks}", flush=True)
+          f"brick={tuple(plan.sizes.brick)} nbricks={plan.sizes.nbricks} clusters={plan.sizes.ncluster}", flush=True)
     v = torch.tensor(s.v, device=dev)
     d = torch.tensor(s.d, device=dev)
     h = torch.full((s.nnz,), float("nan"), dtype=torch.float64, device=dev)
@@ -98,8 +98,9 @@ def record(name, prec, errs):
             f.write(json.dumps({"case": name, "precision": prec, **errs}) + "\n")
 
 
-DECOMP = [1, 2, 3]
-DECOMP_IDS = ["cluster_pairs", "bigcell", "bigcell_rho_force"]
+# 0: the default (Vlocal on cluster pairs, rho and force on bricks)
+DECOMP = [0, 1, 2, 3]
+DECOMP_IDS = ["default", "cluster_pairs", "bigcell", "bigcell_rho_force"]
 
 
 @pytest.mark.parametrize("decomp", DECOMP, ids=DECOMP_IDS)
@@ -115,7 +116,7 @@ def test_mixed_diamond(torch_dev, oracle_mod, prec, decomp):
     got = run(G, torch, dev, s, prec, decomposition=decomp)
     errs, errf = errors(got, ref), errors(got["fused"], ref)
     print("[mixed] diamond", prec, decomp, errs, "fused", errf, flush=True)
-    record(f"diamond8/{DECOMP_IDS[decomp - 1]}", prec, errs)
+    record(f"diamond8/{DECOMP_IDS[decomp]}", prec, errs)
     for k, b in BOUNDS[prec].items():
         assert errs[k] <= b, (k, errs[k], b)
         assert errf[k] <= b, ("fused", k, errf[k], b)
@@ -178,23 +179,27 @@ def test_tbg148_coarse_full_oracle(torch_dev, oracle_mod):
     print("[mixed] tbg148 fp64", e64, flush=True)
     for k in ("H_rel", "rho_rel", "F_rel", "sigma_rel", "E_rel"):
         assert e64[k] <= 1e-11, (k, e64[k])
-    for prec in (1, 2):
-        errs = errors(run(G, torch, dev, s, prec), ref)
-        print("[mixed] tbg148", prec, errs, flush=True)
-        record("tbg148_coarse", prec, errs)
+    # FP16x3 and BF16x3 on the default plan, and FP16x3 with Vlocal on
+    # clusters of eight atoms (the eight-wave kernel: many pairs, split items)
+    for prec, cl in ((1, 0), (2, 0), (1, 8)):
+        errs = errors(run(G, torch, dev, s, prec, cluster_atoms=cl, fused=False), ref)
+        print("[mixed] tbg148", prec, f"cl={cl}", errs, flush=True)
+        record(f"tbg148_coarse/cl{cl}", prec, errs)
         for k, b in BOUNDS[prec].items():
-            assert errs[k] <= b, (prec, k, errs[k], b)
+            assert errs[k] <= b, (prec, cl, k, errs[k], b)
 
 
-@pytest.mark.parametrize("case", [(1, (0, 0, 0)), (2, (0, 0, 0)), (2, (1, 1, 1)), (2, (3, 1, 2)), (3, (0, 0, 0))],
-                         ids=["cluster_pairs", "bigcell", "bigcell_1x1x1", "bigcell_3x1x2", "bigcell_rho_force"])
+@pytest.mark.parametrize("case", [(1, (0, 0, 0), 0), (2, (0, 0, 0), 0), (2, (1, 1, 1), 0), (2, (3, 1, 2), 0),
+                                  (3, (0, 0, 0), 0), (0, (0, 0, 0), 0), (0, (0, 0, 0), 8), (3, (0, 0, 0), 6)],
+                         ids=["cluster_pairs", "bigcell", "bigcell_1x1x1", "bigcell_3x1x2", "bigcell_rho_force",
+                              "default", "default_cl8", "bigcell_rho_force_cl6"])
 @pytest.mark.parametrize("prec", [1, 2], ids=["fp16x3", "bf16x3"])
 def test_mixed_three_species(torch_dev, oracle_mod, prec, case):
     """Species with different channel sets (spd, sp, 2s2p1d) in a skewed cell
     on a grid that is not a multiple of 4 along any axis, against the full
     oracle, at the same bounds; both decompositions, and bricks of several
     shapes."""
-    decomp, brick = case
+    decomp, brick, cl = case
     from paper_2409_09399_amd import gint as G
     from paper_2409_09399_amd import inputs as I
     torch, dev = torch_dev
@@ -210,10 +215,10 @@ def test_mixed_three_species(torch_dev, oracle_mod, prec, case):
     o = oracle_mod.Oracle(s)
     F, Z, E, sig = o.force_stress()
     ref = dict(h=o.vlocal(), rho=o.rho(), rho_abs=o.rho_abs(), F=F, sig=sig, E=E)
-    got = run(G, torch, dev, s, prec, decomposition=decomp, brick=brick)
+    got = run(G, torch, dev, s, prec, decomposition=decomp, brick=brick, cluster_atoms=cl)
     errs, errf = errors(got, ref), errors(got["fused"], ref)
     print("[mixed] three species", prec, case, errs, "fused", errf, flush=True)
-    record(f"mixed5/{DECOMP_IDS[decomp - 1]}/{brick}", prec, errs)
+    record(f"mixed5/{DECOMP_IDS[decomp]}/{brick}/cl{cl}", prec, errs)
     for k, b in BOUNDS[prec].items():
         assert errs[k] <= b, (k, errs[k], b)
         assert errf[k] <= b, ("fused", k, errf[k], b)
