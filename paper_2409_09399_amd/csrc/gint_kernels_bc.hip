@@ -193,8 +193,7 @@ __global__ __launch_bounds__(BC_THREADS) __attribute__((amdgpu_waves_per_eu(4, 4
             if (FORCE && inside) vpt = V0[SY.g_off + r.g];
             // phase 1: activity of every union image on the 64 points
             for (int i = w; i < n; i += BC_WAVES) {
-                const Disp d = disp_at(P, r, uslot(U, i));
-                const unsigned long long m = __ballot(inside && d.in);
+                const unsigned long long m = __ballot(inside && reaches(P, r, uslot(U, i)));
                 if (lane == 0) act[i] = m;
             }
             __syncthreads();

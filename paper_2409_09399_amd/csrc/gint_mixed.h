@@ -326,19 +326,44 @@ __device__ inline Disp disp_of(const GDev &P, const P3 &r, int atom, cdouble *sh
     return d;
 }
 
+// sqrt(r2) for r2 >= 0 to near FP64 accuracy: the FP32 reciprocal square
+// root (relative error about 2e-7 after the conversions) refined by one
+// Newton step in FP64, r1 = r0 + (r2 - r0^2) / (2 r0), which squares the
+// relative error (about 1e-13).  Five FP64-class operations against about a
+// dozen for the correctly rounded square root.  r2 below the FP32 range
+// (r < 1e-19) gives 0.
+__device__ inline double sqrt_r2(double r2) {
+    const float f = (float)r2;
+    if (!(f > 0.f)) return 0.0;
+    const float y = __builtin_amdgcn_rsqf(f);
+    const double r0 = (double)(f * y);
+    return fma(fma(-r0, r0, r2), (double)(0.5f * y), r0);
+}
+
 __device__ inline Disp disp_at(const GDev &P, const P3 &r, const Slot &s) {
     Disp d{0.f, 0.f, 0.f, Knot{0, 0.f}, false};
     if (s.species < 0) return d;
     const double dx = r.x - s.x, dy = r.y - s.y, dz = r.z - s.z;
     const double r2 = dx * dx + dy * dy + dz * dz;
     CSpecies &sp = cst(P.species)[s.species];
-    const double rr = sqrt(r2);
-    d.in = r2 < sp.rcut2 && rr < sp.rcut;
     d.x = (float)dx;
     d.y = (float)dy;
     d.z = (float)dz;
-    if (d.in) d.kn = knot_of(sp, rr);
+    if (r2 < sp.rcut2) {
+        const double rr = sqrt_r2(r2);
+        d.in = rr < sp.rcut;
+        if (d.in) d.kn = knot_of(sp, rr);
+    }
     return d;
+}
+
+// Whether slot s reaches point r: the r2 part of disp_at's test alone (a
+// superset of disp_at's d.in, which also requires sqrt(r2) < rcut; the two
+// differ only within an ulp of the cutoff sphere, where the orbitals vanish).
+__device__ inline bool reaches(const GDev &P, const P3 &r, const Slot &s) {
+    if (s.species < 0) return false;
+    const double dx = r.x - s.x, dy = r.y - s.y, dz = r.z - s.z;
+    return dx * dx + dy * dy + dz * dz < cst(P.species)[s.species].rcut2;
 }
 
 // Orbital rows of a Vlocal tile that reach stored outputs: the orbital
