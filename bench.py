@@ -211,7 +211,7 @@ def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, aut
         f"step {elapsed / steps * 1e3:.2f} ms{' (graph)' if graph else ''}")
     plan.close()
     return {"value": W * steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "kernel_ms": kern_ms,
-            "decomposition": decomposition,
+            "decomposition": decomposition, "cluster_atoms": int(opts.get("cluster_atoms") or 4),
             "fused_rho_force_stress_ms": fused_ms, "W": W, "plan_seconds": plan_s, "options": opts,
             "autotune": tune, "steps": steps, "warmup": warmup, "graph": graph}
 
@@ -220,11 +220,12 @@ PROFILE = os.path.join(ROOT, "profiles", "gint_tbg868_counters.md")
 # the kernel that serves each stage, by precision form and decomposition
 # (gint_sizes.decomposition: 1 cluster pairs, 2 bricks, 3 bricks for rho and
 # force only)
-def kernel_names(prec, decomposition):
+def kernel_names(prec, decomposition, cluster_atoms=4):
     if prec == 0:
         return {"vlocal": "k_vlocal", "rho": "k_rho", "force_stress": "k_force<false>"}
     t = "fp16" if prec == 1 else "bf16"
-    pairs = {"vlocal": f"k_vlocal_mx<{t}>", "rho": f"k_rho_mx<{t}>", "force_stress": f"k_force_mx<{t},false>"}
+    vl = f"k_vlocal_mx8<{t}>" if cluster_atoms > 4 else f"k_vlocal_mx<{t}>"
+    pairs = {"vlocal": vl, "rho": f"k_rho_mx<{t}>", "force_stress": f"k_force_mx<{t},false>"}
     bricks = {"vlocal": f"k_bcv_mx<{t}>", "rho": f"k_bc_mx<{t},rho>", "force_stress": f"k_bc_mx<{t},force>"}
     if decomposition == 2:
         return bricks
@@ -251,7 +252,7 @@ def sources_sha256(prec):
     return h.hexdigest()
 
 
-def profiled_counters(cfg, prec, key, decomposition):
+def profiled_counters(cfg, prec, key, decomposition, cluster_atoms=4):
     """Per-launch counters of a kernel from the committed rocprofv3 summary
     of the bilayer workload (HBM bytes from FETCH_SIZE and WRITE_SIZE
     calibrated with a plain copy; instruction counts), or None when the
@@ -264,7 +265,7 @@ def profiled_counters(cfg, prec, key, decomposition):
         m = re.search(r"<!-- traffic (\[.*\]) -->", fh.read())
     if not m:
         return None
-    name, sha = kernel_names(prec, decomposition).get(key), sources_sha256(prec)
+    name, sha = kernel_names(prec, decomposition, cluster_atoms).get(key), sources_sha256(prec)
     for r in json.loads(m.group(1)):
         if r["kernel"] == name and r.get("sources_sha256") == sha:
             return r
@@ -287,11 +288,12 @@ def roofline(form, prec, cfg, peaks):
     t = km[dom] * 1e-3
     achieved = 2.0 * form["W"] / t / 1e12
     dec = form.get("decomposition", 1)
-    r = {"bound": "mfma", "kernel": kernel_names(prec, dec)[dom], "stage": dom, "achieved": achieved, "peak": peak,
+    cl = form.get("cluster_atoms", 4)
+    r = {"bound": "mfma", "kernel": kernel_names(prec, dec, cl)[dom], "stage": dom, "achieved": achieved, "peak": peak,
          "unit": "TFLOP/s", "frac": achieved / peak, "peak_measured": measured,
          "frac_measured": (achieved / measured) if measured else None,
          "algorithmic_flops": 2.0 * form["W"], "duration_ms": km[dom], "traffic": None}
-    c = profiled_counters(cfg, prec, dom, dec)
+    c = profiled_counters(cfg, prec, dom, dec, cl)
     if c:
         traffic = c["read_bytes"] + c["write_bytes"]
         r["traffic"] = traffic
@@ -365,6 +367,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph of the step")
     ap.add_argument("--autotune", action="store_true", help="choose the tile shape by timed trials first")
     ap.add_argument("--tune-seconds", type=float, default=2.0)
+    ap.add_argument("--sweep-seconds", type=float, default=60.0,
+                    help="wall-time budget of the tuner sweep reported for the bilayer (extra records)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="also run one plain device-to-device copy of this many bytes (untimed), the "
                          "calibration kernel for HBM byte counters")
@@ -443,6 +447,15 @@ def main():
         extra.append(extra_record(G, torch, dev, workload_name(3, batch), batch, [prec, 0], args.extra_steps, 1,
                                   graph=True, autotune=True, peaks=peaks))
         del batch
+        log(f"[bench] extra: {extra[-1]}")
+        # the tile-shape sweep of the tuner on this workload (every candidate
+        # timed; the analogue of the paper's batch-size table), reported only:
+        # the main form above runs the plan's default shapes
+        log("[bench] extra: tuner sweep on the bilayer ...")
+        G.autotune_forget()
+        _, sweep = G.autotune(systems[0], precision=prec, budget_seconds=args.sweep_seconds)
+        extra.append({"workload": workload_name(args.config, systems) + " tile sweep", "precision": args.precision,
+                      "autotune": sweep})
         log(f"[bench] extra: {extra[-1]}")
 
     cpu = None

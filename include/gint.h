@@ -277,7 +277,12 @@ void gint_graph_destroy(gint_graph *g);
  * have passed (the first always runs).  On input opt->precision and
  * opt->decomposition select the form (FP64 plans have no brick choice); on
  * success opt->cluster_atoms, opt->max_bigcells_per_item and opt->brick hold
- * the fastest candidates and *report every trial.  Synchronous. */
+ * the fastest candidates and *report every trial.  Synchronous.
+ * The choice is cached per process, keyed by the device, the form and the
+ * workload's shape class (number of systems, total atoms, grid points and
+ * pattern blocks, the first system's cell and grid): a later call for the
+ * same key returns the stored choice and report (report->cached = 1)
+ * without timing anything.  gint_autotune_forget() empties the cache. */
 #define GINT_TUNE_MAX 16
 typedef struct {
     int ntrials;                         /* trials timed */
@@ -290,9 +295,11 @@ typedef struct {
     double rho_force_ms[GINT_TUNE_MAX];  /* one rho + force/stress pass */
     double step_ms[GINT_TUNE_MAX];       /* their sum */
     double seconds;                      /* wall time of the search */
+    int cached;                          /* 1: returned from the cache, no trial run by this call */
 } gint_tune_report;
 int gint_autotune(const gint_system *sys, int n_sys, gint_options *opt, double budget_seconds,
                   void *stream, gint_tune_report *report);
+void gint_autotune_forget(void);
 
 /* Totals of a plan.  GINT_EINVAL on NULL arguments. */
 int gint_plan_query(const gint_plan *p, gint_sizes *out);

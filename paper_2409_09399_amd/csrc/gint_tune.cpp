@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "gint.h"
 #include "gint_internal.h"
@@ -21,7 +24,7 @@ namespace {
 constexpr int kCand[][2] = {{4, 0}, {3, 0}, {4, 32}, {2, 0}, {4, 128}, {3, 32}, {4, 8}, {2, 32}};
 constexpr int kCandWide[][2] = {{4, 0}, {8, 0}, {3, 0}, {6, 0}, {4, 128}, {8, 32}, {4, 32}, {2, 0}};
 static_assert(sizeof(kCand) == sizeof(kCandWide), "one cluster candidate per trial in both lists");
-constexpr int kBrick[][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 1}, {1, 1, 2}, {2, 1, 1}, {1, 2, 1}, {2, 2, 2}, {4, 4, 2}};
+constexpr int kBrick[][3] = {{0, 0, 0}, {1, 1, 1}, {2, 2, 1}, {2, 2, 4}, {1, 1, 2}, {2, 2, 2}, {4, 4, 2}, {4, 4, 4}};
 constexpr int kNCand = (int)(sizeof(kCand) / sizeof(kCand[0]));
 static_assert(kNCand <= GINT_TUNE_MAX, "candidate list longer than the report");
 static_assert(sizeof(kBrick) / sizeof(kBrick[0]) == (size_t)kNCand, "one brick candidate per trial");
@@ -34,6 +37,45 @@ struct Buffers {
             if (p) (void)hipFree(p);
     }
 };
+
+// Shape class of a tuning request: the device, the form, and the sizes of
+// the workload (two requests with equal keys get the same choice).
+struct TuneKey {
+    int device, precision, decomposition, n_sys;
+    long long natom, nblk;
+    int grid0[3];
+    double cell0[9];
+    bool operator==(const TuneKey &o) const {
+        return device == o.device && precision == o.precision && decomposition == o.decomposition &&
+               n_sys == o.n_sys && natom == o.natom && nblk == o.nblk &&
+               std::memcmp(grid0, o.grid0, sizeof(grid0)) == 0 && std::memcmp(cell0, o.cell0, sizeof(cell0)) == 0;
+    }
+};
+
+struct TuneEntry {
+    TuneKey key;
+    gint_options opt;
+    gint_tune_report rep;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune_cache;
+
+TuneKey tune_key(const gint_system *sys, int n_sys, const gint_options *opt) {
+    TuneKey k;
+    std::memset(&k, 0, sizeof(k));
+    if (hipGetDevice(&k.device) != hipSuccess) k.device = -1;
+    k.precision = opt->precision;
+    k.decomposition = opt->decomposition;
+    k.n_sys = n_sys;
+    for (int i = 0; i < n_sys; ++i) {
+        k.natom += sys[i].natom;
+        k.nblk += sys[i].nblk;
+    }
+    for (int d = 0; d < 3; ++d) k.grid0[d] = sys[0].grid[d];
+    for (int d = 0; d < 9; ++d) k.cell0[d] = sys[0].cell[d];
+    return k;
+}
 
 int step(gint_plan *p, Buffers &b, hipStream_t s) {
     int rc = gint_vlocal(p, b.v, b.h, s);
@@ -62,6 +104,19 @@ int timed_step(gint_plan *p, Buffers &b, hipStream_t s, hipEvent_t ev[3], float 
 extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *opt, double budget_seconds,
                              void *stream, gint_tune_report *report) {
     if (!sys || n_sys < 1 || !opt || !report || !(budget_seconds >= 0.0)) return GINT_EINVAL;
+    const TuneKey key = tune_key(sys, n_sys, opt);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const TuneEntry &e : g_tune_cache)
+            if (e.key == key) {
+                opt->cluster_atoms = e.opt.cluster_atoms;
+                opt->max_bigcells_per_item = e.opt.max_bigcells_per_item;
+                for (int k = 0; k < 3; ++k) opt->brick[k] = e.opt.brick[k];
+                *report = e.rep;
+                report->cached = 1;
+                return GINT_OK;
+            }
+    }
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)stream;
     gint_tune_report rep{};
@@ -129,6 +184,16 @@ extern "C" int gint_autotune(const gint_system *sys, int n_sys, gint_options *op
     opt->max_bigcells_per_item = rep.max_bigcells_per_item[rep.best];
     for (int k = 0; k < 3; ++k) opt->brick[k] = rep.brick[rep.best_brick][k];
     rep.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    rep.cached = 0;
     *report = rep;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache.push_back(TuneEntry{key, *opt, rep});
+    }
     return GINT_OK;
+}
+
+extern "C" void gint_autotune_forget(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
 }

@@ -68,12 +68,12 @@ class gint_tune_report(C.Structure):
                 ("cluster_atoms", C.c_int * GINT_TUNE_MAX), ("max_bigcells_per_item", C.c_int * GINT_TUNE_MAX),
                 ("brick", (C.c_int * 3) * GINT_TUNE_MAX), ("vlocal_ms", C.c_double * GINT_TUNE_MAX),
                 ("rho_force_ms", C.c_double * GINT_TUNE_MAX), ("step_ms", C.c_double * GINT_TUNE_MAX),
-                ("seconds", C.c_double)]
+                ("seconds", C.c_double), ("cached", C.c_int)]
 
 
 EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", "gint_work_units",
             "gint_check_symmetry", "gint_energy", "gint_energy_noalloc",
-            "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune",
+            "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune", "gint_autotune_forget",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
             "gint_last_hip_error", "gint_peaks_measure",
             "gint_scf_create", "gint_scf_solve", "gint_scf_fold_gamma", "gint_scf_destroy"]
@@ -134,6 +134,8 @@ def _load():
     lib.gint_graph_destroy.restype = None
     lib.gint_autotune.argtypes = [C.POINTER(gint_system), C.c_int, C.POINTER(gint_options), C.c_double, P,
                                   C.POINTER(gint_tune_report)]
+    lib.gint_autotune_forget.argtypes = []
+    lib.gint_autotune_forget.restype = None
     lib.gint_strerror.argtypes = [C.c_int]
     lib.gint_strerror.restype = C.c_char_p
     lib.gint_last_hip_error.argtypes = []
@@ -421,7 +423,12 @@ def autotune(system, precision: int = GINT_FP64, budget_seconds: float = 2.0, st
     return ({"cluster_atoms": int(opt.cluster_atoms), "max_bigcells_per_item": int(opt.max_bigcells_per_item),
              "brick": tuple(int(x) for x in opt.brick), "decomposition": decomposition, "precision": precision},
             {"trials": trials, "best": int(rep.best), "best_brick": int(rep.best_brick),
-             "seconds": float(rep.seconds)})
+             "seconds": float(rep.seconds), "cached": bool(rep.cached)})
+
+
+def autotune_forget():
+    """Empty the tuner's per-process cache (gint_autotune_forget)."""
+    _lib.gint_autotune_forget()
 
 
 def gint_rho_force_stress(plan: Plan, v_loc, d_vals, rho, force, stress, n_elec=None, energy=None, stream=None):
