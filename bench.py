@@ -345,6 +345,39 @@ def extra_record(G, torch, dev, name, systems, forms, steps, warmup, graph=False
     return rec
 
 
+def pipeline_record(G, torch, dev, name, system, prec, n_slabs, steps, whole):
+    """The streaming pipeline on one system: the first step (host builds of
+    the slab plans overlapped with the copies and kernels of earlier slabs)
+    and the steady-state step (cached slab plans streamed each step), against
+    the single plan's build time and step (`whole`, the same system's record
+    for this form)."""
+    v = torch.tensor(system.v, device=dev)
+    d = torch.tensor(system.d, device=dev)
+    e = lambda n: torch.empty(n, dtype=torch.float64, device=dev)
+    h, rho, F, sig, ne, E = e(system.nnz), e(system.ngrid), e(3 * system.natom), e(9), e(1), e(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pipe = G.Pipeline(system, n_slabs, precision=prec)
+    pipe.step(v, d, h, rho, F, sig, n_elec=ne, energy=E)
+    torch.cuda.synchronize()
+    first = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.step(v, d, h, rho, F, sig, n_elec=ne, energy=E)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    st = pipe.stats()
+    pipe.close()
+    W = whole["W"]
+    rec = {"workload": name + f" streamed in {n_slabs} slabs", "precision": DTYPES[prec], "n_slabs": n_slabs,
+           "first_step_s": first, "ms_per_step": dt * 1e3, "value": W / dt, "unit": UNIT, "steps": steps,
+           "single_plan_build_plus_step_s": whole["plan_seconds"] + whole["ms_per_step"] * 1e-3,
+           "single_plan_ms_per_step": whole["ms_per_step"], "stats": st}
+    del v, d, h, rho, F, sig, ne, E
+    torch.cuda.empty_cache()
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -367,6 +400,8 @@ def main():
     ap.add_argument("--graph", action="store_true", help="time replays of a captured HIP graph of the step")
     ap.add_argument("--autotune", action="store_true", help="choose the tile shape by timed trials first")
     ap.add_argument("--tune-seconds", type=float, default=2.0)
+    ap.add_argument("--pipeline-slabs", type=int, default=8,
+                    help="grid slabs of the streaming-pipeline record (extra records)")
     ap.add_argument("--sweep-seconds", type=float, default=60.0,
                     help="wall-time budget of the tuner sweep reported for the bilayer (extra records)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -440,6 +475,10 @@ def main():
         big = I.make_config(5)
         extra.append(extra_record(G, torch, dev, workload_name(5, [big]), [big], [prec, 0], args.extra_steps, 1,
                                   peaks=peaks))
+        log(f"[bench] extra: {extra[-1]}")
+        log("[bench] extra: the same system through the streaming pipeline ...")
+        extra.append(pipeline_record(G, torch, dev, workload_name(5, [big]), big, prec, args.pipeline_slabs,
+                                     args.extra_steps, extra[-1][DTYPES[prec]]))
         del big
         log(f"[bench] extra: {extra[-1]}")
         log("[bench] extra: batch of 64 crystals (graph, autotuned) ...")

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgint.so")
 SOURCES = ["gint_kernels.hip", "gint_kernels_mixed.hip", "gint_kernels_bc.hip", "gint_api.cpp", "gint_plan.cpp", "gint_tune.cpp",
-           "gint_peaks.hip", "gint_noalloc.hip", "gint_scf.hip"]
+           "gint_peaks.hip", "gint_noalloc.hip", "gint_scf.hip", "gint_pipeline.cpp"]
 ARCH = os.environ.get("GINT_OFFLOAD_ARCH", "gfx950")
 
 

@@ -12,33 +12,7 @@
 #include "gint_plan.hpp"
 #include "gint_plan_impl.h"
 
-hipError_t gint_launch_fill(double *p, long long n, double v, hipStream_t s);
-hipError_t gint_launch_vlocal(const GDev &P, const double *V, double *H, hipStream_t s);
-hipError_t gint_launch_rho(const GDev &P, const double *D, double *rho, hipStream_t s);
-hipError_t gint_launch_force(const GDev &P, const double *V, const double *D, double *F, double *ZE, double *rho,
-                             hipStream_t s);
-hipError_t gint_launch_work(const GDev &P, double *W, hipStream_t s);
-hipError_t gint_launch_dsym_check(const GBlk *blk, long long nblk, const double *D, double *out, hipStream_t s);
-hipError_t gint_launch_seg_sum(const GDev &P, const double *x, const double *y, double *part, int nparts,
-                               double *out, hipStream_t s);
-hipError_t gint_launch_finish_stress(const GDev &P, const double *ZE, double *stress, double *energy,
-                                     hipStream_t s);
-hipError_t gint_static_scratch(void **ptr, size_t *bytes);
-void gint_prime_grids_fp64();
-void gint_prime_grids_mx(int prec);
-hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
-                                 hipStream_t s);
-hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s);
-hipError_t gint_launch_force_mx(const GDev &P, int prec, const double *V, const double *D, double *F, double *ZE,
-                                double *rho, hipStream_t s);
-hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
-                              double *rho, hipStream_t s);
-hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
-                                const double *D, double *F, double *ZE, double *rho, hipStream_t s);
-void gint_prime_grids_bc(int prec);
-hipError_t gint_launch_vlocal_bc(const GDev &P, int prec, const GBlk *blocks, const double *V, double *H,
-                                 hipStream_t s);
-hipError_t gint_launch_absmax(const double *x, long long n, double *out, hipStream_t s);
+#include "gint_launch.h"
 
 namespace {
 thread_local int g_last_hip = 0;
@@ -98,6 +72,19 @@ size_t upload_bytes(const std::vector<T> &v) {
 }
 
 }  // namespace
+
+// The orbital scale of the 16-bit operands (a power of two with
+// phi_max * phi_scale in [2^12, 2^13)) and the plan-wide channel layout.
+void gint_plan_scales(const HostPlan &hp, GDev &d) {
+    int e = 0;
+    if (hp.phi_max > 0.0 && std::isfinite(hp.phi_max)) (void)std::frexp(hp.phi_max, &e);
+    int k = hp.phi_max > 0.0 ? 13 - e : 0;
+    k = k < -60 ? -60 : (k > 60 ? 60 : k);
+    d.phi_scale = std::ldexp(1.0, k);
+    d.shape_all = hp.species.empty() ? GINT_SHAPE_ANY : hp.species[0].shape;
+    for (const GSpecies &g : hp.species)
+        if (g.shape != d.shape_all) d.shape_all = GINT_SHAPE_ANY;
+}
 
 extern "C" {
 
@@ -212,17 +199,7 @@ int gint_plan_create(gint_plan **out, const gint_system *sys, int n_sys, const g
         for (int k = 0; k < 3; ++k) d.e[i][k] = hp.e[i][k];
     }
     d.w = hp.w;
-    {
-        // power of two with phi_max * phi_scale in [2^12, 2^13)
-        int e = 0;
-        if (hp.phi_max > 0.0 && std::isfinite(hp.phi_max)) (void)std::frexp(hp.phi_max, &e);
-        int k = hp.phi_max > 0.0 ? 13 - e : 0;
-        k = k < -60 ? -60 : (k > 60 ? 60 : k);
-        d.phi_scale = std::ldexp(1.0, k);
-    }
-    d.shape_all = hp.species.empty() ? GINT_SHAPE_ANY : hp.species[0].shape;
-    for (const GSpecies &g : hp.species)
-        if (g.shape != d.shape_all) d.shape_all = GINT_SHAPE_ANY;
+    gint_plan_scales(hp, d);
     d.vmax = (const double *)p->ws.p + 4;
     d.dmax = (const double *)p->ws.p + 5;
     if (bc) {

@@ -85,11 +85,41 @@ struct BlockKeyHash {
     }
 };
 
+// (I, J, R) -> element offset of the block, open addressing with linear
+// probing (offsets are >= 0; -1 marks an empty slot).
 struct BlockMap {
-    std::unordered_map<BlockKey, long long, BlockKeyHash> off;   // (I, J, R) -> element offset
+    struct Slot {
+        int i, j, r0, r1, r2;
+        long long off;
+    };
+    std::vector<Slot> t;
+    size_t mask = 0;
+    void reserve(size_t n) {
+        size_t cap = 16;
+        while (cap < 2 * n + 16) cap <<= 1;
+        t.assign(cap, Slot{0, 0, 0, 0, 0, -1});
+        mask = cap - 1;
+    }
+    // false if the key is already present
+    bool insert(const BlockKey &k, long long off) {
+        size_t h = BlockKeyHash()(k) & mask;
+        while (t[h].off >= 0) {
+            const Slot &s = t[h];
+            if (s.i == k.i && s.j == k.j && s.r0 == k.r0 && s.r1 == k.r1 && s.r2 == k.r2) return false;
+            h = (h + 1) & mask;
+        }
+        t[h] = Slot{k.i, k.j, k.r0, k.r1, k.r2, off};
+        return true;
+    }
     long long find(int i, int j, int r0, int r1, int r2) const {
-        auto it = off.find(BlockKey{i, j, r0, r1, r2});
-        return it == off.end() ? -1 : it->second;
+        if (t.empty()) return -1;
+        size_t h = BlockKeyHash()(BlockKey{i, j, r0, r1, r2}) & mask;
+        for (;;) {
+            const Slot &s = t[h];
+            if (s.off < 0) return -1;
+            if (s.i == i && s.j == j && s.r0 == r0 && s.r1 == r1 && s.r2 == r2) return s.off;
+            h = (h + 1) & mask;
+        }
     }
 };
 
@@ -209,7 +239,8 @@ void parallel_for(int n, F f) {
 // GINT_OK, or 1 if some brick's union exceeds GINT_UMAX (the caller retries
 // with smaller bricks).
 int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vector<double> &rc,
-                 const std::vector<int> &spec, const BlockIndex &bidx, const int B[3], double Rb, HostPlan &hp) {
+                 const std::vector<int> &spec, const BlockIndex &bidx, const int B[3], double Rb, const GintSlab &slab,
+                 HostPlan &hp) {
     const int natom = (int)pos.size();
     int nbk[3];
     for (int k = 0; k < 3; ++k) nbk[k] = (G.N[k] + 4 * B[k] - 1) / (4 * B[k]);
@@ -248,7 +279,8 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
                         bhi[k] = nhi / (4 * B[k]);
                     }
                     if (empty) continue;
-                    for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
+                    for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0) {
+                        if (!slab.has((int)(4 * B[0] * b0), G.N[0])) continue;
                         for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
                             for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
                                 bool hit = false;
@@ -269,6 +301,7 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
                                 if (hit)
                                     out.push_back(Incidence{(int)((b0 * nbk[1] + b1) * nbk[2] + b2), a, t0, t1, t2});
                             }
+                    }
                 }
     });
     std::vector<Incidence> all;
@@ -353,13 +386,24 @@ double bigcell_radius(const Geometry &G) {
 
 }  // namespace
 
+struct GintSlabShared {
+    bool pattern = false;
+    BlockMap bm;
+    long long nnz = 0;
+    bool index = false;
+    BlockIndex bidx;
+};
+
+GintSlabShared *gint_slab_shared_new() { return new GintSlabShared(); }
+void gint_slab_shared_free(GintSlabShared *s) { delete s; }
+
 // Clusters of at most cl atoms (spatial bisection), the cluster pairs that
 // overlap on the grid with their bigcell lists, and the work items over them
 // (canonical pairs; with_swapped also adds the swapped copy of every
 // non-self pair and the items that cover both orders).
 template <int CL>
 int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const std::vector<double> &rc,
-                        const BlockMap &bm, int cl, int maxbc_opt, double Rb, bool with_swapped,
+                        const BlockMap &bm, int cl, int maxbc_opt, double Rb, bool with_swapped, const GintSlab &slab,
                         std::vector<GPairT<CL>> &pairs, HostPlan &hp) {
     auto fail = [&](int code, const char *msg) {
         hp.error = msg;
@@ -474,7 +518,8 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
                                 blo[k] = (long long)std::floor(lo * G.N[k] / GINT_BC) - 1;
                                 bhi[k] = (long long)std::ceil(hi * G.N[k] / GINT_BC) + 1;
                             }
-                            for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0)
+                            for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0) {
+                                if (!slab.has((int)(((GINT_BC * b0) % G.N[0] + G.N[0]) % G.N[0]), G.N[0])) continue;
                                 for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
                                     for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
                                         const Vec3 ctr = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, GINT_BC * b2 + 1.5);
@@ -498,6 +543,7 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
                                         }
                                         po.bcs.push_back(make_bigcell(G.N, GINT_BC * b0, GINT_BC * b1, GINT_BC * b2));
                                     }
+                            }
                             if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
                         }
             }
@@ -516,14 +562,25 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
     // ---- flatten: canonical pairs, then their swapped copies
     pairs.clear();
     hp.bigcells.clear();
+    {
+        size_t nbc = 0, npair = 0;
+        for (int A = 0; A < ncl; ++A) {
+            npair += per_a[A].size();
+            for (auto &po : per_a[A]) nbc += po.bcs.size();
+        }
+        if (nbc > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
+        hp.bigcells.reserve(nbc);
+        pairs.reserve(with_swapped ? 2 * npair : npair);
+    }
     std::vector<std::pair<int, int>> ranges;   // per canonical pair: bigcell begin, count
-    for (int A = 0; A < ncl; ++A)
+    for (int A = 0; A < ncl; ++A) {
         for (auto &po : per_a[A]) {
             ranges.push_back({(int)hp.bigcells.size(), (int)po.bcs.size()});
             hp.bigcells.insert(hp.bigcells.end(), po.bcs.begin(), po.bcs.end());
             pairs.push_back(po.pair);
-            if (hp.bigcells.size() > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
         }
+        std::vector<PairOutT<CL>>().swap(per_a[A]);
+    }
     hp.ncanon = (int)pairs.size();
     std::vector<int> swapped_of(hp.ncanon, -1);
     for (int p = 0; p < hp.ncanon && with_swapped; ++p) {
@@ -565,7 +622,7 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
     for (int p = 0; p < hp.ncanon; ++p) {
         const int beg = ranges[p].first, cnt = ranges[p].second;
         const int nchunk = (cnt + maxbc - 1) / maxbc;
-        const int excl = nchunk == 1 ? 1 : 0;
+        const int excl = (nchunk == 1 && slab.count <= 1) ? 1 : 0;
         for (int c = 0; c < nchunk; ++c) {
             const int b0 = beg + (int)((long long)cnt * c / nchunk);
             const int b1 = beg + (int)((long long)cnt * (c + 1) / nchunk);
@@ -585,7 +642,8 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
     return GINT_OK;
 }
 
-static int build_one(const gint_system *sys, const gint_options *opt, bool bricks, HostPlan &hp) {
+static int build_one(const gint_system *sys, const gint_options *opt, bool bricks, const GintSlab &slab,
+                     HostPlan &hp) {
     auto fail = [&](int code, const char *msg) {
         hp.error = msg;
         return code;
@@ -755,45 +813,60 @@ static int build_one(const gint_system *sys, const gint_options *opt, bool brick
     }
     if (natom >= (1 << 22)) return fail(GINT_EINVAL, "too many atoms");
 
-    // ---- pattern
+    // ---- pattern (validated and indexed once per system when slabs share it)
     if (sys->nblk < 0 || (sys->nblk > 0 && (!sys->blk_i || !sys->blk_j || !sys->blk_r || !sys->blk_off)))
         return fail(GINT_EINVAL, "bad pattern arrays");
-    BlockMap bm;
-    bm.off.reserve((size_t)sys->nblk * 2 + 16);
-    std::vector<std::pair<long long, long long>> spans;
-    spans.reserve(sys->nblk);
-    long long nnz = 0;
-    for (int b = 0; b < sys->nblk; ++b) {
-        const int i = sys->blk_i[b], j = sys->blk_j[b];
-        const int *r = sys->blk_r + 3 * b;
-        if (i < 0 || i >= natom || j < 0 || j >= natom) return fail(GINT_EINVAL, "block atom out of range");
-        if (std::abs(r[0]) >= 2048 || std::abs(r[1]) >= 2048 || std::abs(r[2]) >= 2048)
-            return fail(GINT_EINVAL, "block R out of range");
-        const long long off = sys->blk_off[b];
-        const long long sz = (long long)norb[i] * norb[j];
-        if (off < 0) return fail(GINT_EINVAL, "negative block offset");
-        if (!bm.off.emplace(BlockKey{i, j, r[0], r[1], r[2]}, off).second) return fail(GINT_EINVAL, "duplicate block");
-        spans.push_back({off, off + sz});
-        nnz = std::max(nnz, off + sz);
+    BlockMap bm_local;
+    const BlockMap *bmp = &bm_local;
+    if (slab.shared && slab.shared->pattern) {
+        bmp = &slab.shared->bm;
+        hp.nnz = slab.shared->nnz;
+    } else {
+        BlockMap &bm = bm_local;
+        bm.reserve((size_t)sys->nblk);
+        std::vector<std::pair<long long, long long>> spans;
+        spans.reserve(sys->nblk);
+        long long nnz = 0;
+        for (int b = 0; b < sys->nblk; ++b) {
+            const int i = sys->blk_i[b], j = sys->blk_j[b];
+            const int *r = sys->blk_r + 3 * b;
+            if (i < 0 || i >= natom || j < 0 || j >= natom) return fail(GINT_EINVAL, "block atom out of range");
+            if (std::abs(r[0]) >= 2048 || std::abs(r[1]) >= 2048 || std::abs(r[2]) >= 2048)
+                return fail(GINT_EINVAL, "block R out of range");
+            const long long off = sys->blk_off[b];
+            const long long sz = (long long)norb[i] * norb[j];
+            if (off < 0) return fail(GINT_EINVAL, "negative block offset");
+            if (!bm.insert(BlockKey{i, j, r[0], r[1], r[2]}, off)) return fail(GINT_EINVAL, "duplicate block");
+            spans.push_back({off, off + sz});
+            nnz = std::max(nnz, off + sz);
+        }
+        std::sort(spans.begin(), spans.end());
+        for (size_t k = 1; k < spans.size(); ++k)
+            if (spans[k].first < spans[k - 1].second) return fail(GINT_EINVAL, "overlapping blocks");
+        hp.blocks.resize(sys->nblk);
+        for (int b = 0; b < sys->nblk; ++b) {
+            const int *r = sys->blk_r + 3 * b;
+            const long long ot = bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]);
+            if (ot < 0) return fail(GINT_EPATTERN, "pattern is not transpose-closed");
+            hp.blocks[b] = GBlk{sys->blk_off[b], ot, norb[sys->blk_i[b]], norb[sys->blk_j[b]], 0, sys->blk_i[b],
+                                sys->blk_j[b], 0};
+        }
+        hp.nnz = nnz;
+        if (slab.shared) {
+            slab.shared->bm = std::move(bm_local);
+            slab.shared->nnz = nnz;
+            slab.shared->pattern = true;
+            bmp = &slab.shared->bm;
+        }
     }
-    std::sort(spans.begin(), spans.end());
-    for (size_t k = 1; k < spans.size(); ++k)
-        if (spans[k].first < spans[k - 1].second) return fail(GINT_EINVAL, "overlapping blocks");
-    hp.blocks.resize(sys->nblk);
-    for (int b = 0; b < sys->nblk; ++b) {
-        const int *r = sys->blk_r + 3 * b;
-        const long long ot = bm.find(sys->blk_j[b], sys->blk_i[b], -r[0], -r[1], -r[2]);
-        if (ot < 0) return fail(GINT_EPATTERN, "pattern is not transpose-closed");
-        hp.blocks[b] = GBlk{sys->blk_off[b], ot, norb[sys->blk_i[b]], norb[sys->blk_j[b]], 0, sys->blk_i[b],
-                            sys->blk_j[b], 0};
-    }
-    hp.nnz = nnz;
+    const BlockMap &bm = *bmp;
 
     // ---- clusters, cluster pairs and their work items
     const double Rb = bigcell_radius(G);
     {
-        const int r = cl > GINT_CL ? build_cluster_pairs<GINT_CL8>(G, pos, rc, bm, cl, maxbc_opt, Rb, false, hp.pairs8, hp)
-                                   : build_cluster_pairs<GINT_CL>(G, pos, rc, bm, cl, maxbc_opt, Rb, true, hp.pairs, hp);
+        const int r = cl > GINT_CL
+                          ? build_cluster_pairs<GINT_CL8>(G, pos, rc, bm, cl, maxbc_opt, Rb, false, slab, hp.pairs8, hp)
+                          : build_cluster_pairs<GINT_CL>(G, pos, rc, bm, cl, maxbc_opt, Rb, true, slab, hp.pairs, hp);
         if (r != GINT_OK) return r;
     }
 
@@ -813,12 +886,23 @@ static int build_one(const gint_system *sys, const gint_options *opt, bool brick
                 B[k] = std::max(1, std::min(8, B[k]));
             }
         }
-        BlockIndex bidx;
-        bidx.build(sys->nblk, sys->blk_i, sys->blk_j, sys->blk_r);
+        BlockIndex bidx_local;
+        const BlockIndex *bidxp = &bidx_local;
+        if (slab.shared && slab.shared->index) {
+            bidxp = &slab.shared->bidx;
+        } else {
+            bidx_local.build(sys->nblk, sys->blk_i, sys->blk_j, sys->blk_r);
+            if (slab.shared) {
+                slab.shared->bidx = std::move(bidx_local);
+                slab.shared->index = true;
+                bidxp = &slab.shared->bidx;
+            }
+        }
+        const BlockIndex &bidx = *bidxp;
         std::vector<int> spec(natom);
         for (int i = 0; i < natom; ++i) spec[i] = sys->species[i];
         for (;;) {
-            const int r = build_bricks(G, pos, rc, spec, bidx, B, Rb, hp);
+            const int r = build_bricks(G, pos, rc, spec, bidx, B, Rb, slab, hp);
             if (r == GINT_OK) break;
             if (r != 1) return fail(r, "grid too large for the brick index");
             int ax = 0;
@@ -852,9 +936,15 @@ void merge_pairs(const std::vector<GPairT<CL>> &src, int i, int atom_off, long l
     }
 }
 
-int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp) {
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp,
+                         const GintSlab *slab_in) {
     if (!sys || n_sys < 1) {
         hp.error = "no systems";
+        return GINT_EINVAL;
+    }
+    const GintSlab slab = slab_in ? *slab_in : GintSlab{};
+    if (slab.count < 1 || slab.index < 0 || slab.index >= slab.count || (slab.count > 1 && n_sys != 1)) {
+        hp.error = "bad slab";
         return GINT_EINVAL;
     }
     hp = HostPlan();
@@ -863,7 +953,7 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
     long long tab_off = 0;
     for (int i = 0; i < n_sys; ++i) {
         HostPlan one;
-        const int rc = build_one(sys + i, opt, bricks, one);
+        const int rc = build_one(sys + i, opt, bricks, slab, one);
         if (rc != GINT_OK) {
             hp.error = "system " + std::to_string(i) + ": " + one.error;
             return rc;

@@ -40,7 +40,31 @@ struct HostPlan {
     std::string error;
 };
 
+// One slab of a grid cut along a1: the bigcells and bricks whose origin has
+// wrapped a1 index n0 with floor(n0 * count / N1) == index.  The slabs of a
+// count partition every pair's bigcells and every brick, so the per-slab
+// plans together do the work of the whole plan.
+struct GintSlabShared;   // the pattern indexes of a system, built by its first slab's build and reused
+GintSlabShared *gint_slab_shared_new();
+void gint_slab_shared_free(GintSlabShared *s);
+
+struct GintSlab {
+    int count = 1;
+    int index = 0;
+    // optional: with it, the builds of one system's slabs (in any order, one
+    // at a time) validate and index the pattern once; the later builds leave
+    // hp.blocks empty (the first one's plan carries them)
+    GintSlabShared *shared = nullptr;
+    bool has(int n0_wrapped, int N0) const {
+        return count <= 1 || (int)((long long)n0_wrapped * count / N0) == index;
+    }
+};
+
 // Builds the plan of n_sys systems (their work items merged into one queue).
-// With bricks set, also the bigcell-stationary bricks of every system.
+// With bricks set, also the bigcell-stationary bricks of every system.  With
+// a slab of count > 1 (one system only), only that slab's bigcells and
+// bricks, and every work item is marked as sharing its blocks (the other
+// slabs add to the same H blocks).
 // Returns GINT_OK or a negative gint error code (hp.error holds a message).
-int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp);
+int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *opt, bool bricks, HostPlan &hp,
+                         const GintSlab *slab = nullptr);

@@ -38,3 +38,8 @@ struct gint_plan {
 
 // Records e as the value gint_last_hip_error() reports.
 void gint_record_hip_error(int e);
+
+struct HostPlan;
+// The orbital scale of the mixed forms' 16-bit operands and the plan-wide
+// channel layout, from a host plan, into d.
+void gint_plan_scales(const HostPlan &hp, GDev &d);

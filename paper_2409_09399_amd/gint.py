@@ -63,6 +63,13 @@ class gint_system_sizes(C.Structure):
 GINT_TUNE_MAX = 16
 
 
+class gint_pipeline_stats(C.Structure):
+    _fields_ = [("n_slabs", C.c_int), ("slabs_built", C.c_int), ("steps", C.c_int), ("build_seconds", C.c_double),
+                ("first_step_seconds", C.c_double), ("wait_seconds", C.c_double),
+                ("shared_device_bytes", C.c_int64), ("slot_device_bytes", C.c_int64),
+                ("largest_slab_bytes", C.c_int64), ("all_slabs_bytes", C.c_int64), ("copied_bytes", C.c_int64)]
+
+
 class gint_tune_report(C.Structure):
     _fields_ = [("ntrials", C.c_int), ("best", C.c_int), ("best_brick", C.c_int),
                 ("cluster_atoms", C.c_int * GINT_TUNE_MAX), ("max_bigcells_per_item", C.c_int * GINT_TUNE_MAX),
@@ -76,7 +83,8 @@ EXPORTED = ["gint_plan_create", "gint_vlocal", "gint_rho", "gint_force_stress", 
             "gint_rho_force_stress", "gint_graph_create", "gint_graph_launch", "gint_graph_destroy", "gint_autotune", "gint_autotune_forget",
             "gint_plan_query", "gint_plan_query_system", "gint_plan_destroy", "gint_strerror",
             "gint_last_hip_error", "gint_peaks_measure",
-            "gint_scf_create", "gint_scf_solve", "gint_scf_fold_gamma", "gint_scf_destroy"]
+            "gint_scf_create", "gint_scf_solve", "gint_scf_fold_gamma", "gint_scf_destroy",
+            "gint_pipeline_create", "gint_pipeline_step", "gint_pipeline_query", "gint_pipeline_destroy"]
 
 
 def _hip_runtimes():
@@ -120,6 +128,12 @@ def _load():
     lib.gint_peaks_measure.argtypes = [C.POINTER(C.c_double), P]
     lib.gint_check_symmetry.argtypes = [P, P, P, P]
     lib.gint_scf_create.argtypes = [C.POINTER(C.c_void_p), P, C.POINTER(C.c_int64)]
+    lib.gint_pipeline_create.argtypes = [C.POINTER(C.c_void_p), C.POINTER(gint_system), C.POINTER(gint_options),
+                                         C.c_int]
+    lib.gint_pipeline_step.argtypes = [P] * 10
+    lib.gint_pipeline_query.argtypes = [P, C.POINTER(gint_pipeline_stats)]
+    lib.gint_pipeline_destroy.argtypes = [P]
+    lib.gint_pipeline_destroy.restype = None
     lib.gint_scf_solve.argtypes = [P, P, P, C.c_double, C.c_double, P, P, P, P, P]
     lib.gint_scf_fold_gamma.argtypes = [P, P, P, P]
     lib.gint_scf_destroy.argtypes = [P]
@@ -339,6 +353,56 @@ class Scf:
     def close(self):
         if getattr(self, "_p", None):
             _lib.gint_scf_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Pipeline:
+    """Streaming pipeline of one system (include/gint_pipeline.h): its grid
+    cut into n_slabs slabs along a1, slab plans built on a host thread and
+    streamed to the device while earlier slabs compute."""
+
+    def __init__(self, system, n_slabs: int, precision: int = GINT_FP64, decomposition: int = GINT_DECOMP_DEFAULT,
+                 cluster_atoms: int = 0, max_bigcells_per_item: int = 0, brick=(0, 0, 0)):
+        sts, keep, n = _marshal_batch(system)
+        if n != 1:
+            raise ValueError("a pipeline holds one system")
+        opt = gint_options()
+        opt.precision = precision
+        opt.decomposition = decomposition
+        opt.cluster_atoms = cluster_atoms
+        opt.max_bigcells_per_item = max_bigcells_per_item
+        for k in range(3):
+            opt.brick[k] = int(brick[k])
+        ptr = C.c_void_p()
+        _check(_lib.gint_pipeline_create(C.byref(ptr), sts, C.byref(opt), int(n_slabs)), "gint_pipeline_create")
+        self._p = ptr
+        s = system[0] if isinstance(system, (list, tuple)) else system
+        self.natom = int(s.natom)
+        self.ngrid = int(np.prod(s.grid))
+        self.nnz = int(s.nnz)
+
+    def step(self, v_loc, d_vals, h_vals, rho, force, stress, n_elec=None, energy=None, stream=None):
+        ne = _dev_ptr(n_elec, 1, "n_elec") if n_elec is not None else None
+        en = _dev_ptr(energy, 1, "energy") if energy is not None else None
+        _check(_lib.gint_pipeline_step(self._p, _dev_ptr(v_loc, self.ngrid, "v_loc"),
+                                       _dev_ptr(d_vals, self.nnz, "d_vals"), _dev_ptr(h_vals, self.nnz, "h_vals"),
+                                       _dev_ptr(rho, self.ngrid, "rho"), ne, _dev_ptr(force, 3 * self.natom, "force"),
+                                       _dev_ptr(stress, 9, "stress"), en, _stream(stream)), "gint_pipeline_step")
+
+    def stats(self) -> dict:
+        q = gint_pipeline_stats()
+        _check(_lib.gint_pipeline_query(self._p, C.byref(q)), "gint_pipeline_query")
+        return {k: getattr(q, k) for k, _ in gint_pipeline_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_p", None):
+            _lib.gint_pipeline_destroy(self._p)
             self._p = None
 
     def __del__(self):

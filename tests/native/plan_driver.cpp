@@ -9,8 +9,13 @@
 //   - the cluster pairs (clusters of up to 4 or up to 8 atoms): over the
 //     canonical pairs, the tiles a Vlocal pass stores (block and, for a
 //     non-self pair, its transpose) reach no pattern block twice, and reach
-//     every block whose two spheres overlap by more than a grid cell.
+//     every block whose two spheres overlap by more than a grid cell;
+//   - with slabs=N, the plans of the N slabs along a1: together they hold
+//     every (cluster pair, bigcell) visit and every brick of the whole plan
+//     exactly once, each in the slab of its origin, with no work item that
+//     stores H exclusively.
 // Test infrastructure only.
+// Usage: plan_driver <dir> [brick=b0,b1,b2] [cl=N] [slabs=N] [nocheck]
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -46,10 +51,26 @@ int fail(const char *what, long a = 0, long b = 0) {
 
 int main(int argc, char **argv) {
     if (argc < 2) {
-        std::fprintf(stderr, "usage: %s <dir> [b0 b1 b2 [cluster_atoms [nocheck]]]\n", argv[0]);
+        std::fprintf(stderr, "usage: %s <dir> [brick=b0,b1,b2] [cl=N] [slabs=N] [nocheck]\n", argv[0]);
         return 2;
     }
-    const bool check = argc < 7;
+    bool check = true;
+    int brick_arg[3] = {0, 0, 0}, cl_arg = 0, slabs_arg = 1;
+    for (int a = 2; a < argc; ++a) {
+        const std::string arg = argv[a];
+        if (arg == "nocheck")
+            check = false;
+        else if (arg.rfind("brick=", 0) == 0)
+            std::sscanf(arg.c_str() + 6, "%d,%d,%d", &brick_arg[0], &brick_arg[1], &brick_arg[2]);
+        else if (arg.rfind("cl=", 0) == 0)
+            cl_arg = std::atoi(arg.c_str() + 3);
+        else if (arg.rfind("slabs=", 0) == 0)
+            slabs_arg = std::atoi(arg.c_str() + 6);
+        else {
+            std::fprintf(stderr, "unknown argument %s\n", arg.c_str());
+            return 2;
+        }
+    }
     const std::string dir = argv[1];
     long natom, nspecies, nblk, ngrid, nnz, nchan, knots, mode;
     {
@@ -103,9 +124,8 @@ int main(int argc, char **argv) {
     sys.blk_off = off64.data();
     gint_options opt{};
     opt.precision = GINT_MIXED_FP16X3;
-    if (argc >= 5)
-        for (int k = 0; k < 3; ++k) opt.brick[k] = std::atoi(argv[2 + k]);
-    if (argc >= 6) opt.cluster_atoms = std::atoi(argv[5]);
+    for (int k = 0; k < 3; ++k) opt.brick[k] = brick_arg[k];
+    opt.cluster_atoms = cl_arg;
     HostPlan hp;
     const auto t0 = std::chrono::steady_clock::now();
     const int rc = gint_build_host_plan(&sys, 1, &opt, true, hp);
@@ -170,6 +190,76 @@ int main(int argc, char **argv) {
         }
         std::printf("cluster pairs ok: %d canonical pairs (clusters of %d), %zu blocks stored, %ld required; ",
                     hp.ncanon, hp.cluster_atoms, writes.size(), required);
+    }
+
+    // slabs: the per-slab plans partition the whole plan's work
+    if (slabs_arg > 1) {
+        typedef std::tuple<std::string, int, int, int> Visit;
+        auto visits = [&](const HostPlan &p, std::map<Visit, int> &out) {
+            auto add = [&](const auto &pairs, int CL) {
+                for (const GItem &it : p.items_canon) {
+                    const auto &P = pairs[it.pair];
+                    std::string key;
+                    for (int k = 0; k < CL; ++k) key += std::to_string(P.a[k]) + "," + std::to_string(P.b[k]) + ";";
+                    char sh[96];
+                    std::snprintf(sh, sizeof sh, "%.9f,%.9f,%.9f", P.shiftB[0], P.shiftB[1], P.shiftB[2]);
+                    key += sh;
+                    for (int b = 0; b < it.bc_count; ++b) {
+                        const GBig &o = p.bigcells[it.bc_begin + b];
+                        ++out[Visit{key, o.x, o.y, o.z}];
+                    }
+                }
+            };
+            if (!p.pairs8.empty())
+                add(p.pairs8, GINT_CL8);
+            else
+                add(p.pairs, GINT_CL);
+        };
+        std::map<Visit, int> whole, parts;
+        visits(hp, whole);
+        std::map<std::tuple<int, int, int>, int> bricks_whole, bricks_parts;
+        for (const GBrick &b : hp.bricks) ++bricks_whole[{b.o[0], b.o[1], b.o[2]}];
+        // the slab builds share one pattern index, as the pipeline's do; built
+        // in reverse order so the shared index is made by the last slab
+        GintSlabShared *shared = gint_slab_shared_new();
+        for (int k = slabs_arg - 1; k >= 0; --k) {
+            HostPlan sp;
+            GintSlab slab;
+            slab.count = slabs_arg;
+            slab.index = k;
+            slab.shared = shared;
+            const int r = gint_build_host_plan(&sys, 1, &opt, true, sp, &slab);
+            if (r != GINT_OK) {
+                gint_slab_shared_free(shared);
+                return fail("slab plan", k, r);
+            }
+            if ((k == slabs_arg - 1) != !sp.blocks.empty()) {
+                gint_slab_shared_free(shared);
+                return fail("only the first slab build carries the pattern blocks", k);
+            }
+            if (sp.nnz != hp.nnz) {
+                gint_slab_shared_free(shared);
+                return fail("slab nnz", (long)sp.nnz, (long)hp.nnz);
+            }
+            for (const GItem &it : sp.items_canon)
+                if (it.pad) return fail("a slab's work item stores H exclusively", k, it.pair);
+            for (const GBig &o : sp.bigcells)
+                if (!slab.has(((o.x % grid[0]) + grid[0]) % grid[0], grid[0])) return fail("bigcell outside its slab", k, o.x);
+            for (const GBrick &b : sp.bricks) {
+                if (!slab.has(b.o[0], grid[0])) return fail("brick outside its slab", k, b.o[0]);
+                if (sp.brick[0] == hp.brick[0] && sp.brick[1] == hp.brick[1] && sp.brick[2] == hp.brick[2])
+                    ++bricks_parts[{b.o[0], b.o[1], b.o[2]}];
+            }
+            visits(sp, parts);
+        }
+        gint_slab_shared_free(shared);
+        if (parts != whole)
+            return fail("the slabs' cluster-pair visits differ from the whole plan's", (long)parts.size(), (long)whole.size());
+        for (const auto &kv : parts)
+            if (kv.second != 1) return fail("a visit appears twice");
+        if (bricks_parts != bricks_whole)
+            return fail("the slabs' bricks differ from the whole plan's", (long)bricks_parts.size(), (long)bricks_whole.size());
+        std::printf("slabs ok: %d slabs, %zu visits, %zu bricks; ", slabs_arg, whole.size(), bricks_whole.size());
     }
 
     // brute-force checks of the bricks on sampled grid points

@@ -103,22 +103,24 @@ def test_oracle_under_sanitizers(drivers, tmp_path, oracle_mod):
         assert np.abs(got - ref).max() <= 1e-13 * max(np.abs(ref).max(), 1e-300)
 
 
-@pytest.mark.parametrize("case", [((0, 0, 0), 0), ((1, 1, 1), 4), ((3, 1, 2), 3), ((0, 0, 0), 6)],
-                         ids=["default", "1x1x1_cl4", "3x1x2_cl3", "cl6"])
+@pytest.mark.parametrize("case", [((0, 0, 0), 0, 1), ((1, 1, 1), 4, 1), ((3, 1, 2), 3, 3), ((0, 0, 0), 6, 1),
+                                  ((0, 0, 0), 0, 5), ((0, 0, 0), 8, 7)],
+                         ids=["default", "1x1x1_cl4", "3x1x2_cl3_slabs3", "cl6", "slabs5", "cl8_slabs7"])
 def test_plan_builder_under_sanitizers(drivers, tmp_path, case):
     """The plan builder runs clean under ASan/UBSan on a skewed three-species
     cell with a ragged grid and on a 76-atom twisted bilayer, its bricks pass
-    the brute-force union and pair-table checks, and its cluster pairs (of up
-    to eight atoms by default, up to four or three, six) store every
-    overlapping pattern block exactly once."""
+    the brute-force union and pair-table checks, its cluster pairs (clusters
+    of up to 4 by default, 3, 6 and 8) store every overlapping pattern block
+    exactly once, and the plans of grid slabs along a1 (the streaming
+    pipeline's) partition the whole plan's visits and bricks."""
     from paper_2409_09399_amd import inputs as I
     _, pdrv = drivers
-    brick, cl = case
+    brick, cl, slabs = case
     for k, s in enumerate((_three_species(), I.tbg_system(2, h=0.44))):
         d = tmp_path / f"s{k}"
         d.mkdir()
         dump(s, str(d))
-        args = [pdrv, str(d)] + [str(b) for b in brick] + [str(cl)]
+        args = [pdrv, str(d), "brick=%d,%d,%d" % brick, f"cl={cl}", f"slabs={slabs}"]
         out = run(args, timeout=600)
         print(s.name, out.strip())
         assert "plan driver ok" in out
