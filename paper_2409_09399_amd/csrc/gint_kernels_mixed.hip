@@ -16,25 +16,30 @@
 #include "gint_mixed.h"
 
 // ---------------------------------------------------------------------------
-// H_IJR (Eq. 2), mixed precision.  Tiles [hi/lo][slot][orbital][point]; wave
-// w owns the diagonal tiles (a_i, b_{(w-i)&3}); two k-steps of 32 points.
+// H_IJR (Eq. 2), mixed precision.  Tiles [A/B][hi/lo][slot][orbital][point].
+// Eight waves, one orbital set each per bigcell: wave w < 4 evaluates A atom
+// w, wave w >= 4 the V-weighted B atom w - 4, so a wave waits for one table
+// (and V) round trip per bigcell.  In the contraction wave w owns the two
+// tiles (a_i, b_j) with i = w & 3 and j = i + 2 (w >> 2) + {0, 1} (mod 4):
+// every slot's tiles spread over two waves, and one A fragment read serves
+// both products.  Two k-steps of 32 points.  A pass over a bigcell is a
+// latency chain (table round trip, evaluation, barrier, MFMA, fold), so the
+// kernel is held to 80 registers: three workgroups per CU (six waves per SIMD).
 // ---------------------------------------------------------------------------
 template <class T, int KS>
-__global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
     typedef Split16<T> S;
     typedef typename S::vec vec;
-    __shared__ __attribute__((aligned(16))) T tA[2][4][16][TSTR];
-    __shared__ __attribute__((aligned(16))) T tB[2][4][16][TSTR];
-    __shared__ unsigned maskpt2[2][GINT_BCPTS];
+    __shared__ __attribute__((aligned(16))) T tS[2][2][4][16][TSTR];
+    // per wave and bigcell: bit kk set if its atom reaches a point of k-step kk
+    __shared__ __attribute__((aligned(16))) unsigned s_act[8];
     __shared__ int s_item;
     // A = phi * sphi, B = V phi * sB, both below 2^13 in magnitude
     const float sphi = (float)P0.phi_scale;
     const float sB = pow2_scale(*cst(P0.vmax) * (8192.0 / P0.phi_scale));
     const double unscale = 1.0 / ((double)sphi * (double)sB);
-    // the activity mask is double-buffered: each bigcell uses buffer cur,
-    // clear on entry, and clears the other one for the next bigcell
-    if (threadIdx.x < 2 * GINT_BCPTS) maskpt2[threadIdx.x >> 6][threadIdx.x & 63] = 0u;
-    int cur = 0;
+    const int lane = threadIdx.x & 63, w = wave_id();
+    const int set = w >> 2, slot = w & 3;
     for (;;) {
     const int item_ = claim_item(P0.counter, &s_item);
     if (item_ >= P0.nitems) break;
@@ -44,129 +49,115 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
     bind_system(P, pr.sys);
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
-    const int lane = threadIdx.x & 63, w = wave_id();
-    const Slot sa = slot_of(P, pr.a[w], pr.shiftA), sb = slot_of(P, pr.b[w], pr.shiftB);
-    d4v acc[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[i] = (d4v){0.0, 0.0, 0.0, 0.0};
+    const Slot sl = uniform_slot(set ? slot_of(P, pr.b[slot], pr.shiftB) : slot_of(P, pr.a[slot], pr.shiftA));
+    const int i = slot, j0 = (slot + 2 * set) & 3, j1 = (j0 + 1) & 3;
+    d4v acc[2];
+    acc[0] = acc[1] = (d4v){0.0, 0.0, 0.0, 0.0};
 
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
-        unsigned *maskpt = maskpt2[cur];
         {
-            // phase 1: A atom (slot w) and B atom (slot w) at point lane
+            // phase 1: this wave's atom at point lane (V requested first, so
+            // its latency overlaps the table loads)
             const int pt = lane;
             const P3 r = point_of(P, o, pt);
-            // V at this point, requested before A is evaluated so its latency
-            // overlaps that work (every point of a bigcell is a valid index)
-            const double vpt = V[r.g];
-            unsigned bits = 0;
-            const Disp da = disp_at(P, r, sa);
-            const bool zA = half_active(da.in);
-            if (da.in) {
-                CSpecies &sp = cst(P.species)[sa.species];
+            const float vpt = set ? (float)V[r.g] : 0.f;
+            const Disp d = disp_at(P, r, sl);
+            const unsigned long long bl = __ballot(d.in);
+            const bool zero = ((bl >> (lane & 32)) & 0xffffffffull) != 0ull;
+            if (d.in) {
+                CSpecies &sp = cst(P.species)[sl.species];
+                const float sc = set ? vpt * sB : sphi;
+                float pend = 0.f;
                 with_shape<KS>(sp, [&](auto shp) {
-                    eval32<decltype(shp)::value>(sp, P.tab32, da.x, da.y, da.z, da.kn, sphi, [&](int mu, float v) {
+                    eval32<decltype(shp)::value>(sp, P.tab32, d.x, d.y, d.z, d.kn, sc, [&](int mu, float v) {
                         T hi, lo;
                         constexpr int SH = decltype(shp)::value;
                         if constexpr (SH != GINT_SHAPE_ANY) {
                             // padding rows reach only output rows or columns
                             // beyond the orbital count, which are never stored
-                            if (mu >= ChanShape<SH>::norb) return;
+                            constexpr int NO = ChanShape<SH>::norb;
+                            if (mu >= NO) return;
+                            if constexpr (S::pairs) {
+                                // orbitals arrive in increasing order: convert
+                                // them two at a time, each half stored to its row
+                                if (!(mu & 1) && mu + 1 < NO) {
+                                    pend = v;
+                                    return;
+                                }
+                                if (mu & 1) {
+                                    unsigned h2, l2;
+                                    S::split2(pend, v, h2, l2);
+                                    *(unsigned short *)&tS[set][0][slot][mu - 1][pt] = (unsigned short)h2;
+                                    *(unsigned short *)&tS[set][0][slot][mu][pt] = (unsigned short)(h2 >> 16);
+                                    *(unsigned short *)&tS[set][1][slot][mu - 1][pt] = (unsigned short)l2;
+                                    *(unsigned short *)&tS[set][1][slot][mu][pt] = (unsigned short)(l2 >> 16);
+                                    return;
+                                }
+                            }
                             S::split_mix(v, hi, lo);
                         } else {
                             S::split(v, hi, lo);
                         }
-                        tA[0][w][mu][pt] = hi;
-                        tA[1][w][mu][pt] = lo;
+                        tS[set][0][slot][mu][pt] = hi;
+                        tS[set][1][slot][mu][pt] = lo;
                     });
                 });
-                bits |= 1u << w;
-            } else if (zA) {
+            } else if (zero) {
                 // zeros only where the half is read: a 32-point k-step of
-                // slot w's tile enters the products only if A_w is active
-                // somewhere in it
+                // this slot's tile enters the products only if the atom is
+                // active somewhere in it
 #pragma unroll
                 for (int mu = 0; mu < rows_used<KS>(); ++mu) {
-                    tA[0][w][mu][pt] = (T)0.f;
-                    tA[1][w][mu][pt] = (T)0.f;
+                    tS[set][0][slot][mu][pt] = (T)0.f;
+                    tS[set][1][slot][mu][pt] = (T)0.f;
                 }
             }
-            const Disp db = disp_at(P, r, sb);
-            const bool zB = half_active(db.in);
-            if (db.in) {
-                CSpecies &sp = cst(P.species)[sb.species];
-                const float vg = (float)vpt * sB;
-                with_shape<KS>(sp, [&](auto shp) {
-                    eval32<decltype(shp)::value>(sp, P.tab32, db.x, db.y, db.z, db.kn, vg, [&](int mu, float v) {
-                        T hi, lo;
-                        constexpr int SH = decltype(shp)::value;
-                        if constexpr (SH != GINT_SHAPE_ANY) {
-                            // padding rows reach only output rows or columns
-                            // beyond the orbital count, which are never stored
-                            if (mu >= ChanShape<SH>::norb) return;
-                            S::split_mix(v, hi, lo);
-                        } else {
-                            S::split(v, hi, lo);
-                        }
-                        tB[0][w][mu][pt] = hi;
-                        tB[1][w][mu][pt] = lo;
-                    });
-                });
-                bits |= 1u << (4 + w);
-            } else if (zB) {
-#pragma unroll
-                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
-                    tB[0][w][mu][pt] = (T)0.f;
-                    tB[1][w][mu][pt] = (T)0.f;
-                }
-            }
-            if (bits) atomicOr(&maskpt[pt], bits);
+            if (lane == 0) s_act[w] = ((unsigned)bl != 0u ? 1u : 0u) | ((unsigned)(bl >> 32) != 0u ? 2u : 0u);
         }
         __syncthreads();
-        // the other buffer was last read before the previous bigcell's final barrier
-        if (threadIdx.x < GINT_BCPTS) maskpt2[cur ^ 1][threadIdx.x] = 0u;
-        cur ^= 1;
-        // phase 2: activity of the two 32-point k-steps
-        const unsigned mp = maskpt[lane];
-        unsigned km[2] = {0u, 0u};
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const unsigned long long bl = __ballot((mp >> b) & 1u);
-            if (bl & 0xffffffffull) km[0] |= 1u << b;
-            if (bl >> 32) km[1] |= 1u << b;
-        }
-        f4v c32[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) c32[i] = (f4v){0.f, 0.f, 0.f, 0.f};
+        // phase 2: the two tiles of this wave
+        const unsigned actA = s_act[i], actB0 = s_act[4 + j0], actB1 = s_act[4 + j1];
+        f4v c0 = (f4v){0.f, 0.f, 0.f, 0.f}, c1 = (f4v){0.f, 0.f, 0.f, 0.f};
         const int row = lane & 15, col = 8 * (lane >> 4);
+        bool any0 = false, any1 = false;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int j = (w - i) & 3;
-#pragma unroll
-            for (int kk = 0; kk < 2; ++kk) {
-                if (!((km[kk] >> i) & 1u) || !((km[kk] >> (4 + j)) & 1u)) continue;
-                const vec ahi = *(const vec *)&tA[0][i][row][32 * kk + col];
-                const vec alo = *(const vec *)&tA[1][i][row][32 * kk + col];
-                const vec bhi = *(const vec *)&tB[0][j][row][32 * kk + col];
-                const vec blo = *(const vec *)&tB[1][j][row][32 * kk + col];
-                c32[i] = S::mfma(ahi, bhi, c32[i]);
-                c32[i] = S::mfma(ahi, blo, c32[i]);
-                c32[i] = S::mfma(alo, bhi, c32[i]);
+        for (int kk = 0; kk < 2; ++kk) {
+            const bool b0 = ((actA & actB0) >> kk) & 1u, b1 = ((actA & actB1) >> kk) & 1u;
+            if (!b0 && !b1) continue;
+            const vec ahi = *(const vec *)&tS[0][0][i][row][32 * kk + col];
+            const vec alo = *(const vec *)&tS[0][1][i][row][32 * kk + col];
+            if (b0) {
+                const vec bhi = *(const vec *)&tS[1][0][j0][row][32 * kk + col];
+                const vec blo = *(const vec *)&tS[1][1][j0][row][32 * kk + col];
+                c0 = S::mfma(ahi, bhi, c0);
+                c0 = S::mfma(ahi, blo, c0);
+                c0 = S::mfma(alo, bhi, c0);
+                any0 = true;
+            }
+            if (b1) {
+                const vec bhi = *(const vec *)&tS[1][0][j1][row][32 * kk + col];
+                const vec blo = *(const vec *)&tS[1][1][j1][row][32 * kk + col];
+                c1 = S::mfma(ahi, bhi, c1);
+                c1 = S::mfma(ahi, blo, c1);
+                c1 = S::mfma(alo, bhi, c1);
+                any1 = true;
             }
         }
+        if (any0)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int q = 0; q < 4; ++q) acc[0][q] += (double)c0[q];
+        if (any1)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) acc[i][q] += (double)c32[i][q];
+            for (int q = 0; q < 4; ++q) acc[1][q] += (double)c1[q];
         __syncthreads();
     }
     // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
     const bool exclusive = it.pad != 0;
     const int nu = lane & 15;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int j = (w - i) & 3;
+    for (int t = 0; t < 2; ++t) {
+        const int j = t ? j1 : j0;
         const int ai = pr.a[i], bj = pr.b[j];
         if (ai < 0 || bj < 0) continue;
         const int na = cst(P.atoms)[ai].norb, nb = cst(P.atoms)[bj].norb;
@@ -175,7 +166,7 @@ __global__ __launch_bounds__(256, 4) void k_vlocal_mx(GDev P0, const double *__r
         for (int q = 0; q < 4; ++q) {
             const int mu = 4 * (lane >> 4) + q;
             if (mu >= na || nu >= nb) continue;
-            const double v = P.w * unscale * acc[i][q];
+            const double v = P.w * unscale * acc[t][q];
             if (exclusive) {
                 if (off >= 0) H[off + (long long)mu * nb + nu] = v;
                 if (!pr.self && offt >= 0) H[offt + (long long)nu * na + mu] = v;
@@ -775,7 +766,7 @@ hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long 
         if (e != hipSuccess) return e;
     }
     if (P.pairs8) return launch_form<KVlocal8, 512>(P, prec, s, V, H);
-    return launch_form<KVlocal>(P, prec, s, V, H);
+    return launch_form<KVlocal, 512>(P, prec, s, V, H);
 }
 
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s) {
@@ -792,7 +783,7 @@ int gint_resident_blocks(const void *kernel, int threads);
 
 void gint_prime_grids_mx(int prec) {
     for (int shape : {GINT_SHAPE_ANY, GINT_SHAPE_2S2P1D}) {
-        gint_resident_blocks(kernel_for<KVlocal>(prec, shape), 256);
+        gint_resident_blocks(kernel_for<KVlocal>(prec, shape), 512);
         gint_resident_blocks(kernel_for<KVlocal8>(prec, shape), 512);
         gint_resident_blocks(kernel_for<KRho>(prec, shape), 256);
         gint_resident_blocks(kernel_for<KForce<false>>(prec, shape), 256);

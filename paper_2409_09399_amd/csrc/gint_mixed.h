@@ -307,6 +307,17 @@ __device__ inline Slot slot_of(const GDev &P, int atom, cdouble *shift) {
     return s;
 }
 
+// A slot that is the same in every lane, said so (readfirstlane) so that it
+// lives in scalar registers.
+__device__ inline double uniform_f64(double v) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)b), hi = __builtin_amdgcn_readfirstlane((unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ inline Slot uniform_slot(const Slot &s) {
+    return Slot{uniform_f64(s.x), uniform_f64(s.y), uniform_f64(s.z), __builtin_amdgcn_readfirstlane(s.species)};
+}
+
 // The same from the atom index (descriptors loaded at the call; the rho and
 // force kernels use this form: holding two slots there costs more registers
 // than the loads).
