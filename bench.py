@@ -307,7 +307,9 @@ def roofline(form, prec, cfg, peaks):
             # a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles
             issue = c["valu_insts"] * 4.0 / (N_CU * 4 * CLOCK_GHZ * 1e9 * t)
             r["valu_issue_frac"] = issue
-            r["limiter"] = "valu" if issue > 0.5 else "latency"
+            # below ~3/4 issue the SIMDs have idle VALU cycles: the waves are
+            # waiting (memory, barriers, dependent chains), not out of VALU
+            r["limiter"] = "valu" if issue > 0.75 else "latency"
     return r
 
 
