@@ -207,10 +207,14 @@ def run_form(G, torch, systems, prec, steps, warmup, v, d, out, graph=False, aut
         ms["rho"].append(e[1].elapsed_time(e[2]))
         ms["force_stress"].append(e[2].elapsed_time(e[3]))
     kern_ms = {k: float(np.mean(x)) for k, x in ms.items()}
+    ms["step"] = [e[0].elapsed_time(e[3]) for e in evs]
+    # median and 90th percentile over the timed steps (eager steps in graph mode)
+    spread = {k: {"median": float(np.median(x)), "p90": float(np.percentile(x, 90))} for k, x in ms.items()}
     log(f"[bench] {DTYPES[prec]} per-call ms {kern_ms} (fused rho+force {fused_ms:.2f} ms), "
         f"step {elapsed / steps * 1e3:.2f} ms{' (graph)' if graph else ''}")
     plan.close()
     return {"value": W * steps / elapsed, "ms_per_step": elapsed / steps * 1e3, "kernel_ms": kern_ms,
+            "ms_spread": spread,
             "decomposition": decomposition, "cluster_atoms": int(opts.get("cluster_atoms") or 4),
             "fused_rho_force_stress_ms": fused_ms, "W": W, "plan_seconds": plan_s, "options": opts,
             "autotune": tune, "steps": steps, "warmup": warmup, "graph": graph}
@@ -461,7 +465,7 @@ def main():
         c = run_form(G, torch, systems, cmp_prec, args.steps, args.warmup, v, d, out_cmp, graph=args.graph,
                      opts=cmp_opts)
         cmp_form = {"precision": args.compare, "dtype": DTYPES[cmp_prec], "value": c["value"],
-                    "ms_per_step": c["ms_per_step"], "kernel_ms": c["kernel_ms"],
+                    "ms_per_step": c["ms_per_step"], "kernel_ms": c["kernel_ms"], "ms_spread": c["ms_spread"],
                     "fused_rho_force_stress_ms": c["fused_rho_force_stress_ms"],
                     "roofline": roofline(c, cmp_prec, args.config, peaks), "plan_options": c["options"],
                     "error_of_main_form": compare_outputs(out_main, out_cmp, systems)}
@@ -522,6 +526,7 @@ def main():
                    "W": main_form["W"], "natom": natom, "ngrid": ngrid, "nnz": nnz, "n_sys": n,
                    "graph": bool(args.graph), "plan_options": main_form["options"]},
         "kernel_ms": main_form["kernel_ms"],
+        "ms_spread": main_form["ms_spread"],
         "fused_rho_force_stress_ms": main_form["fused_rho_force_stress_ms"],
         "plan_seconds": main_form["plan_seconds"],
         "roofline": roofline(main_form, prec, args.config, peaks),
