@@ -627,8 +627,10 @@ const void *bc_kernel_for(int prec, int shape_all) {
     return fixed ? bc_kernel<_Float16, GINT_SHAPE_2S2P1D, FORCE, RHO>() : bc_kernel<_Float16, GINT_SHAPE_ANY, FORCE, RHO>();
 }
 
+}  // namespace
+
 // max |D| into P.dmax, then D_sym as 16-bit hi/lo into P.d16
-hipError_t prepare_d16(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D, hipStream_t s) {
+hipError_t gint_launch_d16(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D, hipStream_t s) {
     hipError_t e = gint_launch_fill(const_cast<double *>(P.dmax), 1, 0.0, s);
     if (e == hipSuccess) e = gint_launch_absmax(D, nnz, const_cast<double *>(P.dmax), s);
     if (e != hipSuccess || P.nblocks <= 0) return e;
@@ -640,6 +642,8 @@ hipError_t prepare_d16(const GDev &P, int prec, const GBlk *blocks, long long nn
         hipLaunchKernelGGL(k_d16<_Float16>, dim3(grid), dim3(256), 0, s, blocks, P.nblocks, D, P.dmax, d16);
     return hipGetLastError();
 }
+
+namespace {
 
 hipError_t launch_bc(const void *k, const GDev &P, hipStream_t s, const double *V, double *F, double *ZE, double *rho) {
     if (P.nbricks <= 0) return hipSuccess;
@@ -656,21 +660,30 @@ hipError_t launch_bc(const void *k, const GDev &P, hipStream_t s, const double *
 
 // rho (mixed forms, bigcell-stationary).  rho must be cleared by the caller
 // (points of bricks no atom reaches are not written).
+hipError_t gint_launch_rho_bc_prepared(const GDev &P, int prec, double *rho, hipStream_t s) {
+    return launch_bc(bc_kernel_for<false, false>(prec, P.shape_all), P, s, nullptr, nullptr, nullptr, rho);
+}
+
 hipError_t gint_launch_rho_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *D,
                               double *rho, hipStream_t s) {
-    hipError_t e = prepare_d16(P, prec, blocks, nnz, D, s);
+    hipError_t e = gint_launch_d16(P, prec, blocks, nnz, D, s);
     if (e != hipSuccess) return e;
-    return launch_bc(bc_kernel_for<false, false>(prec, P.shape_all), P, s, nullptr, nullptr, nullptr, rho);
+    return gint_launch_rho_bc_prepared(P, prec, rho, s);
 }
 
 // force/stress/E (and rho when given; rho cleared by the caller).  F and ZE
 // cleared by the caller.
-hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
-                                const double *D, double *F, double *ZE, double *rho, hipStream_t s) {
-    hipError_t e = prepare_d16(P, prec, blocks, nnz, D, s);
-    if (e != hipSuccess) return e;
+hipError_t gint_launch_force_bc_prepared(const GDev &P, int prec, const double *V, double *F, double *ZE, double *rho,
+                                         hipStream_t s) {
     if (rho) return launch_bc(bc_kernel_for<true, true>(prec, P.shape_all), P, s, V, F, ZE, rho);
     return launch_bc(bc_kernel_for<true, false>(prec, P.shape_all), P, s, V, F, ZE, nullptr);
+}
+
+hipError_t gint_launch_force_bc(const GDev &P, int prec, const GBlk *blocks, long long nnz, const double *V,
+                                const double *D, double *F, double *ZE, double *rho, hipStream_t s) {
+    hipError_t e = gint_launch_d16(P, prec, blocks, nnz, D, s);
+    if (e != hipSuccess) return e;
+    return gint_launch_force_bc_prepared(P, prec, V, F, ZE, rho, s);
 }
 
 // H (mixed forms, bigcell-stationary): P.vmax must hold max |V| of this call

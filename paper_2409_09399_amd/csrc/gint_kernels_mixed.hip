@@ -753,20 +753,25 @@ hipError_t launch_form(const GDev &P, int prec, hipStream_t s, Args... args) {
     return hipGetLastError();
 }
 
-hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
-                                 hipStream_t s) {
+// max |V| over the ngrid points of V into P.vmax, from which the mixed
+// Vlocal kernels take the scale of their B operand
+hipError_t gint_launch_vmax(const GDev &P, const double *V, long long ngrid, hipStream_t s) {
     hipError_t e = gint_launch_fill(const_cast<double *>(P.vmax), 1, 0.0, s);
     if (e != hipSuccess) return e;
-    long long blocks = (ngrid + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
-    if (blocks > 0) {
-        hipLaunchKernelGGL(k_absmax, dim3((unsigned)blocks), dim3(256), 0, s, V, ngrid,
-                           (unsigned long long *)const_cast<double *>(P.vmax));
-        e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
+    return gint_launch_absmax(V, ngrid, const_cast<double *>(P.vmax), s);
+}
+
+// the mixed Vlocal kernel alone (P.vmax already holds max |V| of this V)
+hipError_t gint_launch_vlocal_mx_prepared(const GDev &P, int prec, const double *V, double *H, hipStream_t s) {
     if (P.pairs8) return launch_form<KVlocal8, 512>(P, prec, s, V, H);
     return launch_form<KVlocal, 512>(P, prec, s, V, H);
+}
+
+hipError_t gint_launch_vlocal_mx(const GDev &P, int prec, const double *V, long long ngrid, double *H,
+                                 hipStream_t s) {
+    hipError_t e = gint_launch_vmax(P, V, ngrid, s);
+    if (e != hipSuccess) return e;
+    return gint_launch_vlocal_mx_prepared(P, prec, V, H, s);
 }
 
 hipError_t gint_launch_rho_mx(const GDev &P, int prec, const double *D, double *rho, hipStream_t s) {

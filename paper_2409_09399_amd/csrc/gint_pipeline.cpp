@@ -308,8 +308,17 @@ void slab_views(const gint_pipeline *p, const HostPlan &hp, const Packed &L, cha
     ordered.nitems = (int)hp.items_ordered.size();
 }
 
+// What every slab of a step shares, once per step: max |V| (the mixed
+// Vlocal's operand scale) and, with bricks, max |D| and the 16-bit D copy.
+hipError_t prepare_step(gint_pipeline *p, const double *v, const double *d, hipStream_t s) {
+    if (p->prec == GINT_FP64) return hipSuccess;
+    hipError_t e = gint_launch_vmax(p->base, v, p->ngrid, s);
+    if (e == hipSuccess && p->bc) e = gint_launch_d16(p->base, p->prec, p->blocks, p->nnz, d, s);
+    return e;
+}
+
 // The slab's share of Vlocal, rho and force/stress (accumulated into the
-// outputs the step has cleared).
+// outputs the step has cleared; prepare_step has run on the stream).
 hipError_t run_slab(gint_pipeline *p, const GDev &canon, const GDev &ordered, const double *v, const double *d,
                     double *h, double *rho, double *force, hipStream_t s) {
     hipError_t e;
@@ -319,18 +328,12 @@ hipError_t run_slab(gint_pipeline *p, const GDev &canon, const GDev &ordered, co
         if (e == hipSuccess) e = gint_launch_force(ordered, v, d, force, p->ZE, nullptr, s);
         return e;
     }
-    if (p->bc_vlocal) {
-        e = gint_launch_fill(const_cast<double *>(canon.vmax), 1, 0.0, s);
-        if (e == hipSuccess) e = gint_launch_absmax(v, p->ngrid, const_cast<double *>(canon.vmax), s);
-        if (e == hipSuccess) e = gint_launch_vlocal_bc(canon, p->prec, p->blocks, v, h, s);
-    } else {
-        e = gint_launch_vlocal_mx(canon, p->prec, v, p->ngrid, h, s);
-    }
+    e = p->bc_vlocal ? gint_launch_vlocal_bc(canon, p->prec, p->blocks, v, h, s)
+                     : gint_launch_vlocal_mx_prepared(canon, p->prec, v, h, s);
     if (e != hipSuccess) return e;
-    e = p->bc ? gint_launch_rho_bc(canon, p->prec, p->blocks, p->nnz, d, rho, s)
-              : gint_launch_rho_mx(canon, p->prec, d, rho, s);
+    e = p->bc ? gint_launch_rho_bc_prepared(canon, p->prec, rho, s) : gint_launch_rho_mx(canon, p->prec, d, rho, s);
     if (e != hipSuccess) return e;
-    return p->bc ? gint_launch_force_bc(ordered, p->prec, p->blocks, p->nnz, v, d, force, p->ZE, nullptr, s)
+    return p->bc ? gint_launch_force_bc_prepared(ordered, p->prec, v, force, p->ZE, nullptr, s)
                  : gint_launch_force_mx(ordered, p->prec, v, d, force, p->ZE, nullptr, s);
 }
 
@@ -435,6 +438,7 @@ int step_impl(gint_pipeline *p, const double *v_loc, const double *d_vals, doubl
     if (e == hipSuccess) e = gint_launch_fill(rho, p->ngrid, 0.0, s);
     if (e == hipSuccess) e = gint_launch_fill(force, 3LL * p->natom, 0.0, s);
     if (e == hipSuccess) e = gint_launch_fill(p->ZE, 10, 0.0, s);
+    if (e == hipSuccess) e = prepare_step(p, v_loc, d_vals, s);
     if (e != hipSuccess) return hip_rc(e);
     long long copied = 0;
     for (int k = 0; k < p->n_slabs; ++k) {
