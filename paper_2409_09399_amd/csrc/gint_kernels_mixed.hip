@@ -25,6 +25,8 @@
 // both products.  Two k-steps of 32 points.  A pass over a bigcell is a
 // latency chain (table round trip, evaluation, barrier, MFMA, fold), so the
 // kernel is held to 80 registers: three workgroups per CU (six waves per SIMD).
+// Its barriers order LDS only, so the V of the next bigcell, requested after
+// this one's table loads, stays in flight across them.
 // ---------------------------------------------------------------------------
 template <class T, int KS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
@@ -54,14 +56,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
     d4v acc[2];
     acc[0] = acc[1] = (d4v){0.0, 0.0, 0.0, 0.0};
 
+    const int pt = lane;
+    // V of the first bigcell; the next one's is requested after each
+    // bigcell's table loads (so they are not waited for together) and stays
+    // in flight across the LDS-only barriers
+    double vn = set ? V[point_index(P, ldc(P.bigcells + it.bc_begin), pt)] : 0.0;
     for (int bc = 0; bc < it.bc_count; ++bc) {
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         {
-            // phase 1: this wave's atom at point lane (V requested first, so
-            // its latency overlaps the table loads)
-            const int pt = lane;
+            // phase 1: this wave's atom at point lane
             const P3 r = point_of(P, o, pt);
-            const float vpt = set ? (float)V[r.g] : 0.f;
+            const float vpt = (float)vn;
             const Disp d = disp_at(P, r, sl);
             const unsigned long long bl = __ballot(d.in);
             const bool zero = ((bl >> (lane & 32)) & 0xffffffffull) != 0ull;
@@ -114,8 +119,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 }
             }
             if (lane == 0) s_act[w] = ((unsigned)bl != 0u ? 1u : 0u) | ((unsigned)(bl >> 32) != 0u ? 2u : 0u);
+            if (set && bc + 1 < it.bc_count) vn = V[point_index(P, ldc(P.bigcells + it.bc_begin + bc + 1), pt)];
         }
-        __syncthreads();
+        lds_barrier();
         // phase 2: the two tiles of this wave
         const unsigned actA = s_act[i], actB0 = s_act[4 + j0], actB1 = s_act[4 + j1];
         f4v c0 = (f4v){0.f, 0.f, 0.f, 0.f}, c1 = (f4v){0.f, 0.f, 0.f, 0.f};
@@ -150,7 +156,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
         if (any1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[1][q] += (double)c1[q];
-        __syncthreads();
+        lds_barrier();
     }
     // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
     const bool exclusive = it.pad != 0;

@@ -115,6 +115,22 @@ __device__ inline P3 point_of(const GDev &P, const GBig &o, int pt) {
     return r;
 }
 
+// Workgroup barrier ordering LDS traffic only: this wave's LDS (and scalar)
+// operations complete before it, outstanding global loads may stay in
+// flight across it.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Flat grid index of point pt of bigcell o (the index part of point_of).
+__device__ inline long long point_index(const GDev &P, const GBig &o, int pt) {
+    if (o.w >= 0) return o.w + (((pt >> 4) * P.N[1] + ((pt >> 2) & 3)) * P.N[2] + (pt & 3));
+    const int n0 = o.x + (pt >> 4), n1 = o.y + ((pt >> 2) & 3), n2 = o.z + (pt & 3);
+    return ((long long)wrapi(n0, P.N[0]) * P.N[1] + wrapi(n1, P.N[1])) * P.N[2] + wrapi(n2, P.N[2]);
+}
+
 // Cubic Hermite interpolant on the FP32 table: the interval record of knot k
 // ([chan][c0, c1, c2, c3], 16 bytes a channel, the cubic's coefficients in
 // t = r/dr - k) and t.
