@@ -31,8 +31,8 @@ int hip_fail(hipError_t e) {
 // before anything is enqueued.
 int check_device(const gint_plan *p);
 
-template <class T>
-int upload(DevBuf &b, const std::vector<T> &v, size_t &total) {
+template <class T, class A>
+int upload(DevBuf &b, const std::vector<T, A> &v, size_t &total) {
     b.bytes = v.size() * sizeof(T);
     if (b.bytes == 0) b.bytes = sizeof(T);
     hipError_t e = hipMalloc(&b.p, b.bytes);
@@ -66,8 +66,8 @@ int check_device(const gint_plan *p) {
     return cur == p->device ? GINT_OK : GINT_EINVAL;
 }
 
-template <class T>
-size_t upload_bytes(const std::vector<T> &v) {
+template <class T, class A>
+size_t upload_bytes(const std::vector<T, A> &v) {
     return v.empty() ? sizeof(T) : v.size() * sizeof(T);
 }
 

@@ -87,8 +87,8 @@ struct Packed {
     size_t bytes = 0;
 };
 
-template <class T>
-size_t place(size_t &at, const std::vector<T> &v) {
+template <class T, class A>
+size_t place(size_t &at, const std::vector<T, A> &v) {
     const size_t o = at;
     at = align_up(at + v.size() * sizeof(T));
     return o;
@@ -109,8 +109,8 @@ Packed layout(const HostPlan &hp) {
     return L;
 }
 
-template <class T>
-void put(char *dst, size_t off, const std::vector<T> &v) {
+template <class T, class A>
+void put(char *dst, size_t off, const std::vector<T, A> &v) {
     if (!v.empty()) std::memcpy(dst + off, v.data(), v.size() * sizeof(T));
 }
 

@@ -304,21 +304,39 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
                     }
                 }
     });
+    // group by brick, in (brick, atom, image) order: the incidences arrive
+    // atom-major with each atom's images in increasing order, so a stable
+    // counting sort by brick gives exactly the sorted order
     std::vector<Incidence> all;
     {
         size_t n = 0;
         for (auto &v : found) n += v.size();
-        all.reserve(n);
-        for (auto &v : found) {
-            all.insert(all.end(), v.begin(), v.end());
-            std::vector<Incidence>().swap(v);
+        if (nbricks_all <= (1LL << 26)) {
+            std::vector<size_t> at((size_t)nbricks_all + 1, 0);
+            for (const auto &v : found)
+                for (const Incidence &in : v) ++at[(size_t)in.brick + 1];
+            for (long long k = 0; k < nbricks_all; ++k) at[(size_t)k + 1] += at[(size_t)k];
+            all.resize(n);
+            for (auto &v : found) {
+                for (const Incidence &in : v) all[at[(size_t)in.brick]++] = in;
+                std::vector<Incidence>().swap(v);
+            }
+        } else {
+            all.reserve(n);
+            for (auto &v : found) {
+                all.insert(all.end(), v.begin(), v.end());
+                std::vector<Incidence>().swap(v);
+            }
+            std::sort(all.begin(), all.end());
         }
     }
-    std::sort(all.begin(), all.end());
     hp.bricks.clear();
     hp.uatoms.clear();
     std::vector<int> utrip;       // image triple of each union entry (pair-table lookups)
     std::vector<int> uatom_idx;
+    hp.uatoms.reserve(all.size());
+    utrip.reserve(3 * all.size());
+    uatom_idx.reserve(all.size());
     for (size_t k = 0; k < all.size();) {
         size_t e = k;
         while (e < all.size() && all[e].brick == all[k].brick) ++e;
@@ -352,7 +370,7 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
         br.pt_off = total;
         total += (long long)br.u_count * br.u_count;
     }
-    hp.ptab.assign((size_t)total, -1);
+    hp.ptab.resize((size_t)total);   // every entry is written below
     parallel_for((int)hp.bricks.size(), [&](int k) {
         const GBrick &br = hp.bricks[k];
         const int n = br.u_count;
@@ -559,28 +577,35 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
         return fail(err.load(), err.load() == GINT_EPATTERN ? "an overlapping (I,J,R) block is missing from the pattern"
                                                             : "grid index out of range");
 
-    // ---- flatten: canonical pairs, then their swapped copies
+    // ---- flatten: canonical pairs, then their swapped copies.  Offsets per
+    // A cluster first, then each A's pairs and bigcell lists are copied by a
+    // worker into place.
     pairs.clear();
     hp.bigcells.clear();
-    {
-        size_t nbc = 0, npair = 0;
-        for (int A = 0; A < ncl; ++A) {
-            npair += per_a[A].size();
-            for (auto &po : per_a[A]) nbc += po.bcs.size();
-        }
-        if (nbc > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
-        hp.bigcells.reserve(nbc);
-        pairs.reserve(with_swapped ? 2 * npair : npair);
-    }
-    std::vector<std::pair<int, int>> ranges;   // per canonical pair: bigcell begin, count
+    std::vector<size_t> pair_at(ncl + 1, 0), bc_at(ncl + 1, 0);
     for (int A = 0; A < ncl; ++A) {
+        size_t nb = 0;
+        for (auto &po : per_a[A]) nb += po.bcs.size();
+        pair_at[A + 1] = pair_at[A] + per_a[A].size();
+        bc_at[A + 1] = bc_at[A] + nb;
+    }
+    const size_t npair = pair_at[ncl], nbc = bc_at[ncl];
+    if (nbc > (size_t)0x7fffffff) return fail(GINT_ENOMEM, "too many bigcells");
+    pairs.reserve(with_swapped ? 2 * npair : npair);
+    pairs.resize(npair);
+    hp.bigcells.resize(nbc);
+    std::vector<std::pair<int, int>> ranges(npair);   // per canonical pair: bigcell begin, count
+    parallel_for(ncl, [&](int A) {
+        size_t p = pair_at[A], b = bc_at[A];
         for (auto &po : per_a[A]) {
-            ranges.push_back({(int)hp.bigcells.size(), (int)po.bcs.size()});
-            hp.bigcells.insert(hp.bigcells.end(), po.bcs.begin(), po.bcs.end());
-            pairs.push_back(po.pair);
+            ranges[p] = {(int)b, (int)po.bcs.size()};
+            std::copy(po.bcs.begin(), po.bcs.end(), hp.bigcells.begin() + b);
+            pairs[p] = po.pair;
+            ++p;
+            b += po.bcs.size();
         }
         std::vector<PairOutT<CL>>().swap(per_a[A]);
-    }
+    });
     hp.ncanon = (int)pairs.size();
     std::vector<int> swapped_of(hp.ncanon, -1);
     for (int p = 0; p < hp.ncanon && with_swapped; ++p) {
@@ -949,7 +974,7 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
     }
     hp = HostPlan();
     long long g_off = 0, nnz_off = 0;
-    int atom_off = 0, species_off = 0, nitems_ordered = 0;
+    int atom_off = 0, species_off = 0;
     long long tab_off = 0;
     for (int i = 0; i < n_sys; ++i) {
         HostPlan one;
@@ -978,73 +1003,90 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             hp.cluster_atoms = one.cluster_atoms;
         }
         hp.sys.push_back(S);
-        for (GBlk b : one.blocks) {
-            b.off += nnz_off;
-            b.off_t += nnz_off;
-            b.sys = i;
-            b.i += atom_off;
-            b.j += atom_off;
-            hp.blocks.push_back(b);
-        }
-        for (GSpecies sp : one.species) {
-            sp.tab_off += (int)tab_off;
-            hp.species.push_back(sp);
-        }
-        hp.tab.insert(hp.tab.end(), one.tab.begin(), one.tab.end());
-        hp.tab32.insert(hp.tab32.end(), one.tab32.begin(), one.tab32.end());
         hp.phi_max = std::max(hp.phi_max, one.phi_max);
-        for (GAtom at : one.atoms) {
-            at.species += species_off;
-            hp.atoms.push_back(at);
-        }
+        const size_t n_species = one.species.size(), n_tab = one.tab.size();
         if (i > 0 && one.pairs8.empty() != hp.pairs8.empty()) {
             hp.error = "systems of one plan must share the cluster size";
             return GINT_EINVAL;
         }
-        const int pair_off = (int)(hp.pairs.size() + hp.pairs8.size());
-        const int bc_off = (int)hp.bigcells.size();
-        if (hp.bigcells.size() + one.bigcells.size() > (size_t)0x7fffffff) {
-            hp.error = "too many bigcells";
-            return GINT_ENOMEM;
-        }
-        merge_pairs(one.pairs, i, atom_off, nnz_off, hp.pairs);
-        merge_pairs(one.pairs8, i, atom_off, nnz_off, hp.pairs8);
-        hp.bigcells.insert(hp.bigcells.end(), one.bigcells.begin(), one.bigcells.end());
-        {
-            const int ub = (int)hp.uatoms.size();
-            const long long pb = (long long)hp.ptab.size();
-            const int blk_base = (int)(hp.blocks.size() - one.blocks.size());
-            if (hp.uatoms.size() + one.uatoms.size() > (size_t)0x7fffffff) {
-                hp.error = "too many atom images in the bricks";
+        if (i == 0) {
+            // the first system's offsets are all zero: its arrays are taken
+            // as they are (no copy of the bigcell lists and pair tables)
+            hp.blocks = std::move(one.blocks);
+            hp.species = std::move(one.species);
+            hp.tab = std::move(one.tab);
+            hp.tab32 = std::move(one.tab32);
+            hp.atoms = std::move(one.atoms);
+            hp.pairs = std::move(one.pairs);
+            hp.pairs8 = std::move(one.pairs8);
+            hp.bigcells = std::move(one.bigcells);
+            hp.bricks = std::move(one.bricks);
+            hp.uatoms = std::move(one.uatoms);
+            hp.ptab = std::move(one.ptab);
+            hp.items_canon = std::move(one.items_canon);
+            hp.items_ordered = std::move(one.items_ordered);
+            for (int k = 0; k < 3; ++k) hp.brick[k] = one.brick[k];
+        } else {
+            for (GBlk b : one.blocks) {
+                b.off += nnz_off;
+                b.off_t += nnz_off;
+                b.sys = i;
+                b.i += atom_off;
+                b.j += atom_off;
+                hp.blocks.push_back(b);
+            }
+            for (GSpecies sp : one.species) {
+                sp.tab_off += (int)tab_off;
+                hp.species.push_back(sp);
+            }
+            hp.tab.insert(hp.tab.end(), one.tab.begin(), one.tab.end());
+            hp.tab32.insert(hp.tab32.end(), one.tab32.begin(), one.tab32.end());
+            for (GAtom at : one.atoms) {
+                at.species += species_off;
+                hp.atoms.push_back(at);
+            }
+            const int pair_off = (int)(hp.pairs.size() + hp.pairs8.size());
+            const int bc_off = (int)hp.bigcells.size();
+            if (hp.bigcells.size() + one.bigcells.size() > (size_t)0x7fffffff) {
+                hp.error = "too many bigcells";
                 return GINT_ENOMEM;
             }
-            for (GBrick b : one.bricks) {
-                b.sys = i;
-                b.u_begin += ub;
-                b.pt_off += pb;
-                hp.bricks.push_back(b);
+            merge_pairs(one.pairs, i, atom_off, nnz_off, hp.pairs);
+            merge_pairs(one.pairs8, i, atom_off, nnz_off, hp.pairs8);
+            hp.bigcells.insert(hp.bigcells.end(), one.bigcells.begin(), one.bigcells.end());
+            {
+                const int ub = (int)hp.uatoms.size();
+                const long long pb = (long long)hp.ptab.size();
+                const int blk_base = (int)(hp.blocks.size() - one.blocks.size());
+                if (hp.uatoms.size() + one.uatoms.size() > (size_t)0x7fffffff) {
+                    hp.error = "too many atom images in the bricks";
+                    return GINT_ENOMEM;
+                }
+                for (GBrick b : one.bricks) {
+                    b.sys = i;
+                    b.u_begin += ub;
+                    b.pt_off += pb;
+                    hp.bricks.push_back(b);
+                }
+                for (GUAtom u : one.uatoms) {
+                    u.atom += atom_off;
+                    u.species += species_off;
+                    hp.uatoms.push_back(u);
+                }
+                hp.ptab.reserve(hp.ptab.size() + one.ptab.size());
+                for (int b : one.ptab) hp.ptab.push_back(b >= 0 ? b + blk_base : -1);
             }
-            for (GUAtom u : one.uatoms) {
-                u.atom += atom_off;
-                u.species += species_off;
-                hp.uatoms.push_back(u);
+            for (GItem it : one.items_canon) {
+                it.pair += pair_off;
+                it.bc_begin += bc_off;
+                hp.items_canon.push_back(it);
             }
-            hp.ptab.reserve(hp.ptab.size() + one.ptab.size());
-            for (int b : one.ptab) hp.ptab.push_back(b >= 0 ? b + blk_base : -1);
-            if (i == 0)
-                for (int k = 0; k < 3; ++k) hp.brick[k] = one.brick[k];
+            for (GItem it : one.items_ordered) {
+                it.pair += pair_off;
+                it.bc_begin += bc_off;
+                hp.items_ordered.push_back(it);
+            }
         }
-        for (GItem it : one.items_canon) {
-            it.pair += pair_off;
-            it.bc_begin += bc_off;
-            hp.items_canon.push_back(it);
-        }
-        for (GItem it : one.items_ordered) {
-            it.pair += pair_off;
-            it.bc_begin += bc_off;
-            hp.items_ordered.push_back(it);
-        }
-        nitems_ordered += (int)one.items_ordered.size();
         hp.ncanon += one.ncanon;
         hp.ncluster += one.ncluster;
         hp.natom += one.natom;
@@ -1053,14 +1095,13 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
         g_off += one.ngrid;
         nnz_off += one.nnz;
         atom_off += one.natom;
-        species_off += (int)one.species.size();
-        tab_off += (long long)one.tab.size();
+        species_off += (int)n_species;
+        tab_off += (long long)n_tab;
         if (tab_off > 0x7fffffffLL) {
             hp.error = "radial tables too large";
             return GINT_EINVAL;
         }
     }
-    (void)nitems_ordered;
     if (n_sys > 1) {
         auto longer = [](const GItem &x, const GItem &y) {
             if (x.bc_count != y.bc_count) return x.bc_count > y.bc_count;

@@ -3,11 +3,40 @@
 // batches plus their neighbouring atoms, with the GEMM descriptors stored
 // contiguously by integer index).
 #pragma once
+#include <memory>
+#include <new>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "gint.h"
 #include "gint_internal.h"
+
+// An allocator whose resize leaves trivially constructible elements
+// uninitialised: the plan's largest arrays are written in full by worker
+// threads right after they are sized, so their pages are first touched (and
+// zeroed by the OS) in parallel rather than by one thread.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U> &) noexcept {}
+    template <class U>
+    void construct(U *p) noexcept(std::is_nothrow_default_constructible<U>::value) {
+        ::new ((void *)p) U;
+    }
+    template <class U, class... A>
+    void construct(U *p, A &&...a) {
+        ::new ((void *)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using BigVec = std::vector<T, NoInitAlloc<T>>;
 
 struct HostPlan {
     std::vector<GSpecies> species;
@@ -16,14 +45,14 @@ struct HostPlan {
     std::vector<float> tab32;
     std::vector<GPair> pairs;        // clusters of <= 4 atoms: [0, ncanon) canonical, then swapped copies
     std::vector<GPair8> pairs8;      // clusters of 5..8 atoms (canonical only; instead of pairs)
-    std::vector<GBig> bigcells;
+    BigVec<GBig> bigcells;
     std::vector<GItem> items_canon;  // canonical pairs, longest first
     std::vector<GItem> items_ordered;// canonical + swapped, longest first (only the canonical ones with pairs8)
     std::vector<GSys> sys;           // one per system
     std::vector<GBlk> blocks;        // pattern blocks with their transposes (symmetry check, D16 conversion)
     std::vector<GBrick> bricks;      // bigcell-stationary bricks (rho and force), empty unless built
     std::vector<GUAtom> uatoms;      // their atom-image unions
-    std::vector<int> ptab;           // their pair tables (block indices, -1 = none)
+    BigVec<int> ptab;                // their pair tables (block indices, -1 = none)
     int brick[3] = {0, 0, 0};        // bigcells per brick along a1, a2, a3
     int ncanon = 0;
     int ncluster = 0;
