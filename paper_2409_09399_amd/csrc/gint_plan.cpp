@@ -536,10 +536,41 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
                                 blo[k] = (long long)std::floor(lo * G.N[k] / GINT_BC) - 1;
                                 bhi[k] = (long long)std::ceil(hi * G.N[k] / GINT_BC) + 1;
                             }
+                            // along a3 the bigcell centre is c0 + b2 v; an atom's sphere
+                            // of radius R holds it for b2 between the roots of
+                            // |c0 - p + b2 v|^2 = R^2.  The hull of those intervals over
+                            // a cluster, widened by one bigcell, bounds the b2 the exact
+                            // test below can accept, so only they are tested
+                            const Vec3 v{GINT_BC * G.e[2].x, GINT_BC * G.e[2].y, GINT_BC * G.e[2].z};
+                            const double vv = dot(v, v);
+                            auto hull = [&](const Cluster &C, const Vec3 &shift, const Vec3 &c0, double &lo, double &hi) {
+                                lo = 1e300;
+                                hi = -1e300;
+                                for (int a : C.atoms) {
+                                    const Vec3 d = sub(c0, add(pos[a], shift));
+                                    const double R = rc[a] + Rb;
+                                    const double bq = dot(d, v), disc = bq * bq - vv * (dot(d, d) - R * R);
+                                    if (disc < 0) continue;
+                                    const double sq = std::sqrt(disc);
+                                    lo = std::min(lo, (-bq - sq) / vv);
+                                    hi = std::max(hi, (-bq + sq) / vv);
+                                }
+                            };
+                            const Vec3 zero{0.0, 0.0, 0.0};
                             for (long long b0 = blo[0]; b0 <= bhi[0]; ++b0) {
                                 if (!slab.has((int)(((GINT_BC * b0) % G.N[0] + G.N[0]) % G.N[0]), G.N[0])) continue;
-                                for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1)
-                                    for (long long b2 = blo[2]; b2 <= bhi[2]; ++b2) {
+                                for (long long b1 = blo[1]; b1 <= bhi[1]; ++b1) {
+                                    const Vec3 c0 = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, 1.5);
+                                    double la, ha, lb, hb;
+                                    hull(CA, zero, c0, la, ha);
+                                    if (la > ha) continue;
+                                    hull(CB, sh, c0, lb, hb);
+                                    if (lb > hb) continue;
+                                    const double zl = std::max(la, lb), zh = std::min(ha, hb);
+                                    if (zl > zh + 2.0) continue;
+                                    const long long z0 = std::max(blo[2], (long long)std::floor(zl) - 1);
+                                    const long long z1 = std::min(bhi[2], (long long)std::ceil(zh) + 1);
+                                    for (long long b2 = z0; b2 <= z1; ++b2) {
                                         const Vec3 ctr = G.point(GINT_BC * b0 + 1.5, GINT_BC * b1 + 1.5, GINT_BC * b2 + 1.5);
                                         bool ina = false, inb = false;
                                         for (int a : CA.atoms) {
@@ -561,6 +592,7 @@ int build_cluster_pairs(const Geometry &G, const std::vector<Vec3> &pos, const s
                                         }
                                         po.bcs.push_back(make_bigcell(G.N, GINT_BC * b0, GINT_BC * b1, GINT_BC * b2));
                                     }
+                                }
                             }
                             if (!po.bcs.empty()) per_a[A].push_back(std::move(po));
                         }
