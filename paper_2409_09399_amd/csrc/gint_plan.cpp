@@ -163,35 +163,39 @@ struct PairOutT {
     std::vector<GBig> bcs;
 };
 
-// (I, J, R) -> block index, open addressing with linear probing.
+// (I, J, R) -> block index: per atom I, its blocks sorted by (J, R), found
+// by binary search.  The pair-table loops look up many J for one I in a row,
+// so the row (a few KB) stays in cache.
 struct BlockIndex {
-    struct Slot {
-        int i, j, r0, r1, r2, b;
-    };
-    std::vector<Slot> t;
-    size_t mask = 0;
-    static size_t hash(int i, int j, int r0, int r1, int r2) {
-        return BlockKeyHash()(BlockKey{i, j, r0, r1, r2});
-    }
-    void build(int nblk, const int *bi, const int *bj, const int *br) {
-        size_t cap = 16;
-        while (cap < 2 * (size_t)nblk + 16) cap <<= 1;
-        t.assign(cap, Slot{0, 0, 0, 0, 0, -1});
-        mask = cap - 1;
-        for (int b = 0; b < nblk; ++b) {
-            size_t h = hash(bi[b], bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2]) & mask;
-            while (t[h].b >= 0) h = (h + 1) & mask;
-            t[h] = Slot{bi[b], bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2], b};
+    struct Ent {
+        int j, r0, r1, r2, b;
+        bool operator<(const Ent &o) const {
+            if (j != o.j) return j < o.j;
+            if (r0 != o.r0) return r0 < o.r0;
+            if (r1 != o.r1) return r1 < o.r1;
+            return r2 < o.r2;
         }
+    };
+    std::vector<size_t> row;   // natom + 1 offsets into ent
+    std::vector<Ent> ent;
+    void build(int nblk, const int *bi, const int *bj, const int *br) {
+        int natom = 0;
+        for (int b = 0; b < nblk; ++b) natom = std::max(natom, std::max(bi[b], bj[b]) + 1);
+        row.assign((size_t)natom + 1, 0);
+        for (int b = 0; b < nblk; ++b) ++row[(size_t)bi[b] + 1];
+        for (int i = 0; i < natom; ++i) row[(size_t)i + 1] += row[(size_t)i];
+        ent.resize((size_t)nblk);
+        std::vector<size_t> at(row.begin(), row.end() - 1);
+        for (int b = 0; b < nblk; ++b) ent[at[(size_t)bi[b]]++] = Ent{bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2], b};
+        for (int i = 0; i < natom; ++i) std::sort(ent.begin() + row[(size_t)i], ent.begin() + row[(size_t)i + 1]);
     }
     int find(int i, int j, int r0, int r1, int r2) const {
-        size_t h = hash(i, j, r0, r1, r2) & mask;
-        for (;;) {
-            const Slot &s = t[h];
-            if (s.b < 0) return -1;
-            if (s.i == i && s.j == j && s.r0 == r0 && s.r1 == r1 && s.r2 == r2) return s.b;
-            h = (h + 1) & mask;
-        }
+        if (i < 0 || (size_t)i + 1 >= row.size()) return -1;
+        const auto lo = ent.begin() + row[(size_t)i], hi = ent.begin() + row[(size_t)i + 1];
+        const Ent key{j, r0, r1, r2, 0};
+        const auto it = std::lower_bound(lo, hi, key);
+        if (it != hi && it->j == j && it->r0 == r0 && it->r1 == r1 && it->r2 == r2) return it->b;
+        return -1;
     }
 };
 
