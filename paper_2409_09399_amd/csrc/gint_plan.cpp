@@ -178,6 +178,7 @@ struct BlockIndex {
     };
     std::vector<size_t> row;   // natom + 1 offsets into ent
     std::vector<Ent> ent;
+    std::vector<int> tr;       // per block: the index of its transpose (J, I, -R), -1 if absent
     void build(int nblk, const int *bi, const int *bj, const int *br) {
         int natom = 0;
         for (int b = 0; b < nblk; ++b) natom = std::max(natom, std::max(bi[b], bj[b]) + 1);
@@ -188,6 +189,8 @@ struct BlockIndex {
         std::vector<size_t> at(row.begin(), row.end() - 1);
         for (int b = 0; b < nblk; ++b) ent[at[(size_t)bi[b]]++] = Ent{bj[b], br[3 * b], br[3 * b + 1], br[3 * b + 2], b};
         for (int i = 0; i < natom; ++i) std::sort(ent.begin() + row[(size_t)i], ent.begin() + row[(size_t)i + 1]);
+        tr.assign((size_t)nblk, -1);
+        for (int b = 0; b < nblk; ++b) tr[(size_t)b] = find(bj[b], bi[b], -br[3 * b], -br[3 * b + 1], -br[3 * b + 2]);
     }
     int find(int i, int j, int r0, int r1, int r2) const {
         if (i < 0 || (size_t)i + 1 >= row.size()) return -1;
@@ -379,13 +382,16 @@ int build_bricks(const Geometry &G, const std::vector<Vec3> &pos, const std::vec
         const GBrick &br = hp.bricks[k];
         const int n = br.u_count;
         int *pt = hp.ptab.data() + br.pt_off;
+        // (j, i) is the transpose block of (i, j): one lookup per unordered pair
         for (int i = 0; i < n; ++i) {
             const int ui = br.u_begin + i;
             const int *ti = &utrip[3 * (size_t)ui];
-            for (int j = 0; j < n; ++j) {
+            for (int j = i; j < n; ++j) {
                 const int uj = br.u_begin + j;
                 const int *tj = &utrip[3 * (size_t)uj];
-                pt[(size_t)i * n + j] = bidx.find(uatom_idx[ui], uatom_idx[uj], tj[0] - ti[0], tj[1] - ti[1], tj[2] - ti[2]);
+                const int b = bidx.find(uatom_idx[ui], uatom_idx[uj], tj[0] - ti[0], tj[1] - ti[1], tj[2] - ti[2]);
+                pt[(size_t)i * n + j] = b;
+                if (j != i) pt[(size_t)j * n + i] = b >= 0 ? bidx.tr[(size_t)b] : -1;
             }
         }
     });
