@@ -240,19 +240,25 @@ int upload_shared(gint_pipeline *p, const HostPlan &hp) {
     const size_t nws = 6 + 10 + kParts;
     const size_t o_ws = at;
     at = align_up(at + nws * sizeof(double));
-    std::vector<char> img(at, 0);
+    // the host image covers the tables, atoms, systems and blocks; the D copy
+    // is written on the device each step before it is read, and only the
+    // workspace needs zeros
+    std::vector<char> img(o_d16, 0);
     put(img.data(), o_species, hp.species);
     put(img.data(), o_atoms, hp.atoms);
     put(img.data(), o_tab, hp.tab);
     put(img.data(), o_tab32, hp.tab32);
     put(img.data(), o_sys, hp.sys);
     put(img.data(), o_blocks, hp.blocks);
+    const std::vector<double> ws0(nws, 0.0);
     hipError_t e = hipMalloc(&p->shared, at);
     if (e != hipSuccess) {
         p->shared = nullptr;
         return hip_rc(e);
     }
-    e = hipMemcpy(p->shared, img.data(), at, hipMemcpyHostToDevice);
+    e = hipMemcpy(p->shared, img.data(), o_d16, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->shared + o_ws, ws0.data(), nws * sizeof(double), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_rc(e);
     p->st.shared_device_bytes = (int64_t)at;
     char *b = p->shared;
