@@ -1,7 +1,8 @@
 """Differentiation form: autograd through the adjoint kernels.
 
-* gradcheck-style check of dL/dD, dL/dtau, dL/deps on a tiny cell against
-  central differences of the forward GPU density;
+* a directional check of dL/dD, dL/dtau, dL/deps on a tiny cell against
+  central differences of the forward GPU density, and torch.autograd.gradcheck
+  of rho(D, tau, eps) there (D in a random subspace);
 * on the 868-atom bilayer (the benchmark geometry): dE/dtau on 10 random
   atoms and the full strain derivative against central finite differences
   (dR = 1e-4 Bohr, strain 1e-5) of the FP64 GPU energy, and against the
@@ -53,6 +54,32 @@ def test_rho_vjp_tiny(torch_dev):
         ep = torch.zeros(3, 3, dtype=torch.float64, device=dev); ep[a, b] = he
         fd = (Lval(ee=ep) - Lval(ee=-ep)) / (2 * he)
         assert abs(fd - float(eps.grad[a, b])) <= 2e-6 * float(eps.grad.abs().max()), (a, b)
+
+
+def test_rho_gradcheck_tiny(torch_dev):
+    """torch.autograd.gradcheck of rho(D, tau, eps) in FP64 on the tiny cell:
+    D moves in a random three-dimensional subspace (the full nnz would take a
+    forward pass per entry), tau and eps in full, rho projected onto four
+    random vectors; the Jacobian from the adjoint kernels must match central
+    differences entry by entry."""
+    from paper_2409_09399_amd import autograd as A
+    from paper_2409_09399_amd import inputs as I
+    torch, dev = torch_dev
+    s = I.diamond8(4, grid=(12, 12, 12))
+    rng = np.random.default_rng(3)
+    d0 = torch.tensor(s.d, device=dev)
+    U = torch.tensor(rng.normal(size=(3, s.nnz)) * np.abs(s.d).max(), device=dev)
+    Pm = torch.tensor(rng.normal(size=(s.ngrid, 4)), device=dev)
+
+    def f(c, tau, eps):
+        return A.rho(s, d0 + c @ U, tau, eps) @ Pm
+
+    c = torch.zeros(3, dtype=torch.float64, device=dev, requires_grad=True)
+    tau = torch.tensor(s.pos, device=dev, requires_grad=True)
+    eps = torch.zeros(3, 3, dtype=torch.float64, device=dev, requires_grad=True)
+    # nondet_tol: the FP64 atomics of the adjoint kernels may add in another
+    # order on a second backward pass
+    assert torch.autograd.gradcheck(f, (c, tau, eps), eps=1e-6, atol=1e-7, rtol=1e-5, nondet_tol=1e-10)
 
 
 def test_energy_fd_tbg868(torch_dev, oracle_mod):
