@@ -145,3 +145,33 @@ def test_autotune_choice_is_correct(env, oracle_mod, prec):
         plan.close()
     opts2, rep2 = G.autotune(s, precision=prec, budget_seconds=30.0)
     assert rep2["cached"] and opts2 == opts and rep2["best"] == rep["best"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["fp64", "fp16x3"])
+def test_rejected_calls_leave_outputs_untouched(env, prec):
+    """The header's error contract, through the raw C ABI: a call rejected
+    with GINT_EINVAL (a null argument) enqueues nothing, so outputs it was
+    given keep their contents, and the next valid call still works."""
+    torch, dev, G = env
+    from paper_2409_09399_amd import inputs as I
+    s = I.diamond8(2)
+    plan = G.Plan(s, precision=prec)
+    b = buffers(torch, dev, plan, [s])
+    for k in ("h", "rho", "F", "sig", "E", "ne"):
+        b[k].fill_(7.0)
+    torch.cuda.synchronize()
+    lib, p = G._lib, plan._p
+    ptr = lambda t: t.data_ptr()
+    st = torch.cuda.current_stream().cuda_stream
+    assert lib.gint_vlocal(p, None, ptr(b["h"]), st) == G.GINT_EINVAL
+    assert lib.gint_rho(p, None, ptr(b["rho"]), ptr(b["ne"]), st) == G.GINT_EINVAL
+    assert lib.gint_force_stress(p, ptr(b["v"]), ptr(b["d"]), ptr(b["F"]), None, ptr(b["E"]), st) == G.GINT_EINVAL
+    assert lib.gint_rho_force_stress(p, ptr(b["v"]), None, ptr(b["rho"]), ptr(b["ne"]), ptr(b["F"]), ptr(b["sig"]),
+                                     ptr(b["E"]), st) == G.GINT_EINVAL
+    torch.cuda.synchronize()
+    for k in ("h", "rho", "F", "sig", "E", "ne"):
+        assert bool((b[k] == 7.0).all()), k
+    eager(G, plan, b)
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(b["h"]).all()) and not bool((b["h"] == 7.0).all())
+    plan.close()
