@@ -1015,16 +1015,35 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
         return GINT_EINVAL;
     }
     hp = HostPlan();
+    // every system's plan first, then each merged array is reserved once at
+    // its final size (growing them system by system re-copied them)
+    std::vector<HostPlan> ones((size_t)n_sys);
+    for (int i = 0; i < n_sys; ++i) {
+        const int rc = build_one(sys + i, opt, bricks, slab, ones[(size_t)i]);
+        if (rc != GINT_OK) {
+            hp.error = "system " + std::to_string(i) + ": " + ones[(size_t)i].error;
+            return rc;
+        }
+    }
+    if (n_sys > 1) {
+        size_t nb = 0, nsp = 0, nt = 0, nt32 = 0, na = 0, np = 0, np8 = 0, nbc = 0, nbk = 0, nu = 0, npt = 0, nic = 0,
+               nio = 0;
+        for (const HostPlan &o : ones) {
+            nb += o.blocks.size(); nsp += o.species.size(); nt += o.tab.size(); nt32 += o.tab32.size();
+            na += o.atoms.size(); np += o.pairs.size(); np8 += o.pairs8.size(); nbc += o.bigcells.size();
+            nbk += o.bricks.size(); nu += o.uatoms.size(); npt += o.ptab.size(); nic += o.items_canon.size();
+            nio += o.items_ordered.size();
+        }
+        hp.blocks.reserve(nb); hp.species.reserve(nsp); hp.tab.reserve(nt); hp.tab32.reserve(nt32);
+        hp.atoms.reserve(na); hp.pairs.reserve(np); hp.pairs8.reserve(np8); hp.bigcells.reserve(nbc);
+        hp.bricks.reserve(nbk); hp.uatoms.reserve(nu); hp.ptab.reserve(npt); hp.items_canon.reserve(nic);
+        hp.items_ordered.reserve(nio); hp.sys.reserve((size_t)n_sys);
+    }
     long long g_off = 0, nnz_off = 0;
     int atom_off = 0, species_off = 0;
     long long tab_off = 0;
     for (int i = 0; i < n_sys; ++i) {
-        HostPlan one;
-        const int rc = build_one(sys + i, opt, bricks, slab, one);
-        if (rc != GINT_OK) {
-            hp.error = "system " + std::to_string(i) + ": " + one.error;
-            return rc;
-        }
+        HostPlan one = std::move(ones[(size_t)i]);
         GSys S{};
         for (int k = 0; k < 3; ++k) {
             S.N[k] = one.N[k];
@@ -1051,8 +1070,8 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
             hp.error = "systems of one plan must share the cluster size";
             return GINT_EINVAL;
         }
-        if (i == 0) {
-            // the first system's offsets are all zero: its arrays are taken
+        if (n_sys == 1) {
+            // a single system's offsets are all zero: its arrays are taken
             // as they are (no copy of the bigcell lists and pair tables)
             hp.blocks = std::move(one.blocks);
             hp.species = std::move(one.species);
@@ -1115,8 +1134,12 @@ int gint_build_host_plan(const gint_system *sys, int n_sys, const gint_options *
                     u.species += species_off;
                     hp.uatoms.push_back(u);
                 }
-                hp.ptab.reserve(hp.ptab.size() + one.ptab.size());
-                for (int b : one.ptab) hp.ptab.push_back(b >= 0 ? b + blk_base : -1);
+                const size_t pt0 = hp.ptab.size();
+                hp.ptab.resize(pt0 + one.ptab.size());
+                for (size_t q = 0; q < one.ptab.size(); ++q) {
+                    const int b = one.ptab[q];
+                    hp.ptab[pt0 + q] = b >= 0 ? b + blk_base : -1;
+                }
             }
             for (GItem it : one.items_canon) {
                 it.pair += pair_off;
