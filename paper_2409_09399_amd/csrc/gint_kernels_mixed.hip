@@ -57,6 +57,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
     acc[0] = acc[1] = (d4v){0.0, 0.0, 0.0, 0.0};
 
     const int pt = lane;
+    // FP16 tiles of a fixed orbital layout are stored 32 bits at a time:
+    // lanes 2k and 2k + 1 exchange their converted pairs of rows, and the
+    // even lane stores the lower row at points 2k, 2k + 1, the odd lane the
+    // upper (half the stores of 16-bit ones, and no two lanes in one bank
+    // word).  poff: this lane's byte offset within a pair of rows; psel: the
+    // byte selector that takes its half from each lane's pair.
+    constexpr bool PACK = S::pairs && KS != GINT_SHAPE_ANY;
+    const int poff = (lane & 1) * (TSTR * 2) + (lane & ~1) * 2;
+    const unsigned psel = (lane & 1) ? 0x03020706u : 0x05040100u;
     // V of the first bigcell; the next one's is requested after each
     // bigcell's table loads (so they are not waited for together) and stays
     // in flight across the LDS-only barriers
@@ -70,9 +79,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
             const Disp d = disp_at(P, r, sl);
             const unsigned long long bl = __ballot(d.in);
             const bool zero = ((bl >> (lane & 32)) & 0xffffffffull) != 0ull;
-            if (d.in) {
+            // with paired stores both lanes of a pair evaluate when either
+            // is active, the inactive one with weight 0
+            const bool ev = PACK ? ((bl >> (lane & ~1)) & 3ull) != 0ull : d.in;
+            if (ev) {
                 CSpecies &sp = cst(P.species)[sl.species];
-                const float sc = set ? vpt * sB : sphi;
+                const float sc = d.in ? (set ? vpt * sB : sphi) : 0.f;
                 float pend = 0.f;
                 with_shape<KS>(sp, [&](auto shp) {
                     eval32<decltype(shp)::value>(sp, P.tab32, d.x, d.y, d.z, d.kn, sc, [&](int mu, float v) {
@@ -93,10 +105,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                                 if (mu & 1) {
                                     unsigned h2, l2;
                                     S::split2(pend, v, h2, l2);
-                                    *(unsigned short *)&tS[set][0][slot][mu - 1][pt] = (unsigned short)h2;
-                                    *(unsigned short *)&tS[set][0][slot][mu][pt] = (unsigned short)(h2 >> 16);
-                                    *(unsigned short *)&tS[set][1][slot][mu - 1][pt] = (unsigned short)l2;
-                                    *(unsigned short *)&tS[set][1][slot][mu][pt] = (unsigned short)(l2 >> 16);
+                                    if constexpr (PACK) {
+                                        // the partner lane's pairs (quad_perm [1,0,3,2])
+                                        const unsigned oh = __builtin_amdgcn_update_dpp(0u, h2, 0xB1, 0xF, 0xF, false);
+                                        const unsigned ol = __builtin_amdgcn_update_dpp(0u, l2, 0xB1, 0xF, 0xF, false);
+                                        *(unsigned *)((char *)&tS[set][0][slot][mu - 1][0] + poff) = __builtin_amdgcn_perm(oh, h2, psel);
+                                        *(unsigned *)((char *)&tS[set][1][slot][mu - 1][0] + poff) = __builtin_amdgcn_perm(ol, l2, psel);
+                                    } else {
+                                        *(unsigned short *)&tS[set][0][slot][mu - 1][pt] = (unsigned short)h2;
+                                        *(unsigned short *)&tS[set][0][slot][mu][pt] = (unsigned short)(h2 >> 16);
+                                        *(unsigned short *)&tS[set][1][slot][mu - 1][pt] = (unsigned short)l2;
+                                        *(unsigned short *)&tS[set][1][slot][mu][pt] = (unsigned short)(l2 >> 16);
+                                    }
                                     return;
                                 }
                             }
@@ -112,10 +132,24 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 // zeros only where the half is read: a 32-point k-step of
                 // this slot's tile enters the products only if the atom is
                 // active somewhere in it
+                if constexpr (PACK) {
+                    // both lanes of a pair are here
+                    constexpr int NO = rows_used<KS>();
 #pragma unroll
-                for (int mu = 0; mu < rows_used<KS>(); ++mu) {
-                    tS[set][0][slot][mu][pt] = (T)0.f;
-                    tS[set][1][slot][mu][pt] = (T)0.f;
+                    for (int mu = 1; mu < NO; mu += 2) {
+                        *(unsigned *)((char *)&tS[set][0][slot][mu - 1][0] + poff) = 0u;
+                        *(unsigned *)((char *)&tS[set][1][slot][mu - 1][0] + poff) = 0u;
+                    }
+                    if constexpr (NO & 1) {
+                        tS[set][0][slot][NO - 1][pt] = (T)0.f;
+                        tS[set][1][slot][NO - 1][pt] = (T)0.f;
+                    }
+                } else {
+#pragma unroll
+                    for (int mu = 0; mu < rows_used<KS>(); ++mu) {
+                        tS[set][0][slot][mu][pt] = (T)0.f;
+                        tS[set][1][slot][mu][pt] = (T)0.f;
+                    }
                 }
             }
             if (lane == 0) s_act[w] = ((unsigned)bl != 0u ? 1u : 0u) | ((unsigned)(bl >> 32) != 0u ? 2u : 0u);
@@ -150,13 +184,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 any1 = true;
             }
         }
+        // the tiles are free once this wave's fragment reads have returned:
+        // the products are folded into FP64 after the barrier
+        lds_barrier();
         if (any0)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[0][q] += (double)c0[q];
         if (any1)
 #pragma unroll
             for (int q = 0; q < 4; ++q) acc[1][q] += (double)c1[q];
-        lds_barrier();
     }
     // 16x16x32 result layout: lane l, register q holds row 4 (l >> 4) + q, column l & 15
     const bool exclusive = it.pad != 0;
