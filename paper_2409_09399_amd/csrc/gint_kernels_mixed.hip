@@ -26,7 +26,9 @@
 // latency chain (table round trip, evaluation, barrier, MFMA, fold), so the
 // kernel is held to 80 registers: three workgroups per CU (six waves per SIMD).
 // Its barriers order LDS only, so the V of the next bigcell, requested after
-// this one's table loads, stays in flight across them.
+// this one's table loads, stays in flight across them.  The slot's species
+// constants (cutoffs, knot spacing, table base) are read once per item, so a
+// bigcell's chain holds no scalar descriptor round trips beyond its own.
 // ---------------------------------------------------------------------------
 template <class T, int KS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) void k_vlocal_mx(GDev P0, const double *__restrict__ V0, double *__restrict__ H) {
@@ -52,6 +54,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
     CSys &SY = cst(P0.sys)[pr.sys];
     const double *V = V0 + SY.g_off;
     const Slot sl = uniform_slot(set ? slot_of(P, pr.b[slot], pr.shiftB) : slot_of(P, pr.a[slot], pr.shiftA));
+    const SlotC slc = slot_consts(P, sl);
     const int i = slot, j0 = (slot + 2 * set) & 3, j1 = (j0 + 1) & 3;
     d4v acc[2];
     acc[0] = acc[1] = (d4v){0.0, 0.0, 0.0, 0.0};
@@ -76,7 +79,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
             // phase 1: this wave's atom at point lane
             const P3 r = point_of(P, o, pt);
             const float vpt = (float)vn;
-            const Disp d = disp_at(P, r, sl);
+            const Disp d = disp_c(r, slc);
             const unsigned long long bl = __ballot(d.in);
             const bool zero = ((bl >> (lane & 32)) & 0xffffffffull) != 0ull;
             // with paired stores both lanes of a pair evaluate when either
@@ -87,9 +90,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                 const float sc = d.in ? (set ? vpt * sB : sphi) : 0.f;
                 float pend = 0.f;
                 with_shape<KS>(sp, [&](auto shp) {
-                    eval32<decltype(shp)::value>(sp, P.tab32, d.x, d.y, d.z, d.kn, sc, [&](int mu, float v) {
+                    constexpr int SH = decltype(shp)::value;
+                    const Herm32 hm = hermite_c(slc, d.kn, ChanShape<SH>::nchan(sp));
+                    Rows32 R0;
+                    load_rows32(hm, ChanShape<SH>::nchan(sp), 0, R0);
+                    eval32_rows<SH>(sp, hm, R0, d.x, d.y, d.z, sc, [&](int mu, float v) {
                         T hi, lo;
-                        constexpr int SH = decltype(shp)::value;
                         if constexpr (SH != GINT_SHAPE_ANY) {
                             // padding rows reach only output rows or columns
                             // beyond the orbital count, which are never stored
@@ -106,9 +112,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6, 6))) voi
                                     unsigned h2, l2;
                                     S::split2(pend, v, h2, l2);
                                     if constexpr (PACK) {
-                                        // the partner lane's pairs (quad_perm [1,0,3,2])
-                                        const unsigned oh = __builtin_amdgcn_update_dpp(0u, h2, 0xB1, 0xF, 0xF, false);
-                                        const unsigned ol = __builtin_amdgcn_update_dpp(0u, l2, 0xB1, 0xF, 0xF, false);
+                                        // the partner lane's pairs (quad_perm [1,0,3,2]; every
+                                        // lane is active, so no old value is needed)
+                                        const unsigned oh = __builtin_amdgcn_mov_dpp(h2, 0xB1, 0xF, 0xF, true);
+                                        const unsigned ol = __builtin_amdgcn_mov_dpp(l2, 0xB1, 0xF, 0xF, true);
                                         *(unsigned *)((char *)&tS[set][0][slot][mu - 1][0] + poff) = __builtin_amdgcn_perm(oh, h2, psel);
                                         *(unsigned *)((char *)&tS[set][1][slot][mu - 1][0] + poff) = __builtin_amdgcn_perm(ol, l2, psel);
                                     } else {

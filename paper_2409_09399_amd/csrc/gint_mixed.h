@@ -384,6 +384,59 @@ __device__ inline Disp disp_at(const GDev &P, const P3 &r, const Slot &s) {
     return d;
 }
 
+// A slot with the cutoff and table constants of its species, read once per
+// work item, so that a loop over bigcells issues no species descriptor loads.
+struct SlotC {
+    Slot s;
+    double rcut2, rcut, inv_dr;
+    int kmax;            // last knot interval
+    const float *rec0;   // FP32 table records of the species
+};
+
+__device__ inline SlotC slot_consts(const GDev &P, const Slot &s) {
+    SlotC c{s, 0.0, 0.0, 0.0, 0, P.tab32};
+    if (s.species >= 0) {
+        CSpecies &sp = cst(P.species)[s.species];
+        c.rcut2 = sp.rcut2;
+        c.rcut = sp.rcut;
+        c.inv_dr = sp.inv_dr;
+        c.kmax = sp.nknots - 2;
+        c.rec0 = P.tab32 + 2 * (size_t)sp.tab_off;
+    }
+    return c;
+}
+
+// disp_at with the constants of c (the same arithmetic, knot_of included).
+__device__ inline Disp disp_c(const P3 &r, const SlotC &c) {
+    Disp d{0.f, 0.f, 0.f, Knot{0, 0.f}, false};
+    if (c.s.species < 0) return d;
+    const double dx = r.x - c.s.x, dy = r.y - c.s.y, dz = r.z - c.s.z;
+    const double r2 = dx * dx + dy * dy + dz * dz;
+    d.x = (float)dx;
+    d.y = (float)dy;
+    d.z = (float)dz;
+    if (r2 < c.rcut2) {
+        const double rr = sqrt_r2(r2);
+        d.in = rr < c.rcut;
+        if (d.in) {
+            const double t = rr * c.inv_dr;
+            int k = (int)t;
+            if (k > c.kmax) k = c.kmax;
+            d.kn = Knot{k, (float)(t - (double)k)};
+        }
+    }
+    return d;
+}
+
+// Hermite record of knot interval kn of the species of c (as hermite32).
+__device__ inline Herm32 hermite_c(const SlotC &c, Knot kn, int nchan) {
+    Herm32 h;
+    h.rec = c.rec0 + (size_t)kn.k * nchan * 4;
+    h.t = kn.t;
+    h.inv_dr = (float)c.inv_dr;
+    return h;
+}
+
 // Whether slot s reaches point r: the r2 part of disp_at's test alone (a
 // superset of disp_at's d.in, which also requires sqrt(r2) < rcut; the two
 // differ only within an ulp of the cutoff sphere, where the orbitals vanish).
