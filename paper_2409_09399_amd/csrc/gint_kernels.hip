@@ -86,6 +86,35 @@ __device__ __attribute__((always_inline)) inline Herm hermite(CSpecies &sp, cons
     return h;
 }
 
+// The cutoff and table constants of one species, read once per work item
+// (a loop over bigcells then issues no species descriptor loads).
+struct SpK {
+    double rcut2, rcut, inv_dr, dr;
+    int kmax;              // last knot interval
+    const double *tab0;    // the species' table records
+};
+
+// hermite<SHAPE> with the constants of k (the same arithmetic).
+__device__ __attribute__((always_inline)) inline Herm hermite_k(const SpK &k, int nchan, double r) {
+    double t = r * k.inv_dr;
+    int kn = (int)t;
+    if (kn > k.kmax) kn = k.kmax;
+    t -= (double)kn;
+    const double t2 = t * t, t3 = t2 * t;
+    Herm h;
+    h.row0 = k.tab0 + (size_t)kn * nchan * 2;
+    h.row1 = h.row0 + nchan * 2;
+    h.h00 = 2.0 * t3 - 3.0 * t2 + 1.0;
+    h.h10 = (t3 - 2.0 * t2 + t) * k.dr;
+    h.h01 = 3.0 * t2 - 2.0 * t3;
+    h.h11 = (t3 - t2) * k.dr;
+    h.d00 = (6.0 * t2 - 6.0 * t) * k.inv_dr;
+    h.d10 = 3.0 * t2 - 4.0 * t + 1.0;
+    h.d01 = -h.d00;
+    h.d11 = 3.0 * t2 - 2.0 * t;
+    return h;
+}
+
 __device__ inline void solid9(double x, double y, double z, double S[9]) {
     S[0] = kC0;
     S[1] = kC1 * y;
@@ -120,10 +149,8 @@ __device__ __attribute__((always_inline)) inline void load_rows(const Herm &h, i
 // phi_mu(x) * scale for the 16 orbital slots of one atom, written to dst
 // (LDS); slots past the atom's orbitals are zero.
 template <int SHAPE, bool PAD = true>
-__device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, const double *tab, double x, double y,
-                                                               double z, double r2, double scale, double *dst) {
-    const double r = sqrt(r2);
-    const Herm h = hermite<SHAPE>(sp, tab, r);
+__device__ __attribute__((always_inline)) inline void eval_phi_h(CSpecies &sp, const Herm &h, double x, double y,
+                                                                 double z, double scale, double *dst) {
     double S[9];
     solid9(x, y, z, S);
     const int nchan = ChanShape<SHAPE>::nchan(sp);
@@ -158,6 +185,12 @@ __device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, con
     // outputs beyond the orbital count)
     if constexpr (PAD)
         for (; slot < GINT_ORB; ++slot) dst[slot] = 0.0;
+}
+
+template <int SHAPE, bool PAD = true>
+__device__ __attribute__((always_inline)) inline void eval_phi(CSpecies &sp, const double *tab, double x, double y,
+                                                               double z, double r2, double scale, double *dst) {
+    eval_phi_h<SHAPE, PAD>(sp, hermite<SHAPE>(sp, tab, sqrt(r2)), x, y, z, scale, dst);
 }
 
 __device__ inline void zero16(double *dst) {
@@ -377,8 +410,27 @@ __device__ inline void store_psi(const d4 c[4], double *phiB, const unsigned *ma
 // ---------------------------------------------------------------------------
 constexpr int kVlocalThreads = 512;
 
+// The atom image of one slot of a work item and its species' constants,
+// read once per item.  species < 0: empty slot.
+struct SlotK {
+    double ax, ay, az, sx, sy, sz;    // atom position and lattice shift of the image
+    int species;
+    SpK k;
+};
+
+__device__ inline SlotK slot_k(const GDev &P, int a, cdouble *sh) {
+    SlotK s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, -1, SpK{0.0, 0.0, 0.0, 0.0, 0, P.tab}};
+    if (a >= 0) {
+        const GAtom at = ldc(P.atoms + a);
+        CSpecies &sp = cst(P.species)[at.species];
+        s = SlotK{at.x, at.y, at.z, sh[0], sh[1], sh[2], at.species,
+                  SpK{sp.rcut2, sp.rcut, sp.inv_dr, sp.dr, sp.nknots - 2, P.tab + sp.tab_off}};
+    }
+    return s;
+}
+
 template <int KS>
-__device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, const double *__restrict__ V,
+__device__ inline void stage_vlocal(const GDev &P, const SlotK &sk, const GBig &o, const double *__restrict__ V,
                                     double *phiA, double *phiB, unsigned *maskpt) {
     const int pt = threadIdx.x & 63, w = wave_id();
     const int slot = w & 3;
@@ -386,32 +438,28 @@ __device__ inline void stage_vlocal(const GDev &P, CPair &pr, const GBig &o, con
     const Pt r = bigcell_point(P, o, pt);
     // B waves request V first, so its latency overlaps the displacement work
     const double vpt = sideB ? V[r.g] : 0.0;
-    const int a = sideB ? pr.b[slot] : pr.a[slot];
-    cdouble *sh = sideB ? pr.shiftB : pr.shiftA;
     double *dst = (sideB ? phiB : phiA) + pt * PSTR + slot * GINT_ORB;
     bool in = false;
     double x = 0.0, y = 0.0, z = 0.0, r2 = 0.0;
-    int species = 0;
-    if (a >= 0) {
-        const GAtom at = ldc(P.atoms + a);
-        x = r.x - at.x - sh[0];
-        y = r.y - at.y - sh[1];
-        z = r.z - at.z - sh[2];
+    if (sk.species >= 0) {
+        x = r.x - sk.ax - sk.sx;
+        y = r.y - sk.ay - sk.sy;
+        z = r.z - sk.az - sk.sz;
         r2 = x * x + y * y + z * z;
-        species = at.species;
-        CSpecies &sp = cst(P.species)[species];
-        in = r2 < sp.rcut2 && sqrt(r2) < sp.rcut;
+        in = r2 < sk.k.rcut2 && sqrt(r2) < sk.k.rcut;
     }
     // zeros only where they are read: a 4-point k-step of this slot enters
     // the products only if the slot is active at one of its points (ballot
     // taken by the whole wave)
     const unsigned long long act = __ballot(in);
     if (in) {
-        CSpecies &sp = cst(P.species)[species];
+        CSpecies &sp = cst(P.species)[sk.species];
         // with a fixed layout the padding rows are not stored: they reach only
         // output rows or columns beyond the orbital count, which are never written
         with_shape<KS>(sp, [&](auto shp) {
-            eval_phi<decltype(shp)::value, KS == GINT_SHAPE_ANY>(sp, P.tab, x, y, z, r2, sideB ? P.w * vpt : 1.0, dst);
+            constexpr int SH = decltype(shp)::value;
+            eval_phi_h<SH, KS == GINT_SHAPE_ANY>(sp, hermite_k(sk.k, ChanShape<SH>::nchan(sp), sqrt(r2)), x, y, z,
+                                                 sideB ? P.w * vpt : 1.0, dst);
         });
         atomicOr(&maskpt[pt], 1u << (sideB ? 4 + slot : slot));
     } else if ((act >> (pt & ~3)) & 0xFull) {
@@ -442,6 +490,7 @@ __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const dou
     const double *V = V0 + SY.g_off;
     const int lane = threadIdx.x & 63, w = wave_id();
     const int i = w & 3, half = w >> 2;
+    const SlotK sk = slot_k(P, half ? pr.b[i] : pr.a[i], half ? pr.shiftB : pr.shiftA);
     d4 acc[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = (d4){0.0, 0.0, 0.0, 0.0};
@@ -450,7 +499,7 @@ __global__ __launch_bounds__(kVlocalThreads, 4) void k_vlocal(GDev P0, const dou
         const GBig o = ldc(P.bigcells + it.bc_begin + bc);
         if (threadIdx.x < GINT_BCPTS) maskpt[threadIdx.x] = 0u;
         __syncthreads();
-        stage_vlocal<KS>(P, pr, o, V, phiA, phiB, maskpt);
+        stage_vlocal<KS>(P, sk, o, V, phiA, phiB, maskpt);
         __syncthreads();
         // k-step t of this wave = points 32 half + 4t .. +3; its activity mask is
         // the OR over those 4 points, read into scalar registers once
